@@ -1,0 +1,230 @@
+/*
+ * cabcd.h - communication-avoiding primal and dual block coordinate descent
+ * (CA-BCD / CA-BDCD) for ridge regression on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2.2, eq. primal / eq. 6 / eq. 3): X is d x n with features
+ * as rows and data points as columns, y in R^n, lambda > 0,
+ *     min_w  f(w) = lambda/2 ||w||^2 + 1/(2n) ||X^T w - y||^2
+ *     min_a  D(a) = lambda/2 ||X a/(lambda n)||^2 + 1/(2n) ||a + y||^2,
+ *     w = -X a / (lambda n).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Matrix view.  Every routine sees the data through A, the matrix whose ROWS
+ * are the coordinates that get sampled: the primal passes A = X (d x n), the
+ * dual passes A = X^T (n x d).  Both methods then gather s*b rows of A, form
+ * their Gram matrix and dot them with one companion vector.
+ *
+ * Memory.  Every array pointer is a DEVICE pointer, owned by the caller, on the
+ * device that is current when the call is made; the library never frees
+ * caller memory.  Scalars are passed by value; the two structs below are host
+ * structs whose pointer fields are device pointers.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All work is
+ * enqueued on it in order.  Unless CABCD_FLAG_ASYNC is set, a call
+ * synchronises the stream before returning so that device-detected errors
+ * (non-SPD block, non-finite values) can be returned.
+ *
+ * Workspace.  Scratch memory is taken from a per-device pool that the library
+ * grows with hipMalloc and keeps until process exit, unless opts->workspace is
+ * given (then nothing is allocated and a too small workspace is CABCD_ENOMEM;
+ * cabcd_workspace_bytes() gives the size).  Concurrent calls on one device
+ * that use the library pool must be serialised by the caller.
+ *
+ * Errors.  Every entry point returns a cabcd_status; argument errors are found
+ * before anything is enqueued.  cabcd_last_error() returns a thread-local
+ * message for the most recent failure.
+ *
+ * Block sampler.  Blocks are drawn by the counter-based sampler specified at
+ * cabcd_sample(); block h (0-based global iteration) depends only on
+ * (seed, h), so a run can be split into several calls (opts->h0) and give the
+ * same iterates.
+ */
+#ifndef CABCD_H
+#define CABCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cabcd_status {
+  CABCD_OK = 0,
+  CABCD_EINVAL = -1,        /* invalid argument; nothing was enqueued            */
+  CABCD_ENOTSPD = -2,       /* a b x b diagonal block had a pivot <= 0 or NaN     */
+  CABCD_EHIP = -3,          /* a HIP runtime call failed                          */
+  CABCD_ENOMEM = -4,        /* allocation failed or caller workspace too small    */
+  CABCD_EUNSUPPORTED = -5,  /* valid but unsupported combination (see message)    */
+  CABCD_ENONFINITE = -6     /* a monitored objective became NaN or Inf            */
+} cabcd_status;
+
+typedef enum cabcd_kind { CABCD_DENSE = 0, CABCD_CSR = 1 } cabcd_kind;
+
+typedef enum cabcd_dtype {
+  CABCD_F64 = 0,       /* IEEE binary64                                         */
+  CABCD_BF16 = 1,      /* bfloat16 storage, value = bf16 * row_scale            */
+  CABCD_FP8_E4M3 = 2   /* OCP FP8 E4M3 storage, value = e4m3 * row_scale        */
+} cabcd_dtype;
+
+/*
+ * A, the matrix whose rows are the samplable coordinates.
+ * Dense: row-major, element (i, k) at data[i*ld + k]; ld >= cols.
+ *   row_scale (FP32, length rows) multiplies row i for BF16 / FP8 storage; NULL
+ *   means 1.  F64 ignores it.
+ * CSR: rowptr (int64, rows+1, rowptr[0] = 0), colidx (int32, nnz, strictly
+ *   increasing within a row, in [0, cols)), vals (FP64, nnz).  CSR is F64 only.
+ */
+typedef struct cabcd_matrix {
+  int32_t kind;              /* cabcd_kind                                        */
+  int32_t dtype;             /* cabcd_dtype                                       */
+  int64_t rows;              /* number of samplable coordinates                   */
+  int64_t cols;              /* length of a row (the Gram's reduction length)     */
+  const void* data;          /* dense values                                      */
+  int64_t ld;                /* dense leading dimension in elements               */
+  const float* row_scale;    /* dense low-precision row scales or NULL            */
+  const int64_t* rowptr;     /* CSR                                               */
+  const int32_t* colidx;     /* CSR                                               */
+  const double* vals;        /* CSR                                               */
+  int64_t nnz;               /* CSR                                               */
+} cabcd_matrix;
+
+/* flags */
+#define CABCD_FLAG_STATE_VALID 1u  /* primal: r already holds X^T w - y on entry;
+                                      dual: w already holds -X a/(lambda n)       */
+#define CABCD_FLAG_ASYNC 2u        /* do not synchronise; device status is lost   */
+
+typedef struct cabcd_opts {
+  int64_t h0;                /* global index of the first inner iteration (resume) */
+  uint32_t flags;            /* CABCD_FLAG_*                                        */
+  int32_t resid_every;       /* recompute the companion vector exactly from A every
+                                this many outer steps (0 = never)                   */
+  int32_t monitor_every;     /* write the primal objective f(w) to trace every this
+                                many outer steps (0 = never)                        */
+  int32_t reserved0;
+  const int32_t* explicit_idx; /* optional H*b device indices replacing the sampler:
+                                  block of iteration h0+i is explicit_idx[i*b ..]  */
+  double* trace;             /* device, trace_len doubles (monitor output)          */
+  int64_t trace_len;
+  void* workspace;           /* optional caller workspace (device)                  */
+  size_t workspace_bytes;
+  double* timing;            /* optional HOST array of 2*CABCD_NPHASES doubles: when
+                                set, every phase is bracketed by HIP events on
+                                `stream`; timing[p] accumulates its milliseconds and
+                                timing[CABCD_NPHASES+p] its launch count.  Needs a
+                                synchronising call (no CABCD_FLAG_ASYNC).           */
+} cabcd_opts;
+
+/* Phases reported through cabcd_opts.timing (the breakdown of one outer step). */
+#define CABCD_PHASE_SAMPLE 0    /* block sampler                                   */
+#define CABCD_PHASE_GRAM 1      /* gathered-row Gram + Y u (split-K kernel)        */
+#define CABCD_PHASE_REDUCE 2    /* sum of the Gram partials, scale and overlap     */
+#define CABCD_PHASE_SOLVE 3     /* s Cholesky solves + recurrence + x[idx] += d    */
+#define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta                 */
+#define CABCD_PHASE_RECOMPUTE 5 /* exact companion recomputation                   */
+#define CABCD_PHASE_MONITOR 6   /* objective evaluation                            */
+#define CABCD_NPHASES 7
+
+/* Fill *o with defaults: h0 0, no flags, no recompute, no monitor, sampler on. */
+void cabcd_opts_init(cabcd_opts* o);
+
+/*
+ * Block sampler (Section 1 footnote and Alg. 1-4: b indices uniformly at random
+ * without replacement; Section 3.1 after eq. (recur): one shared seed).
+ * Writes idx[i*b + m], i < count, m < b: the block of global iteration h0+i,
+ * b distinct integers in [0, range).  Definition (integer-only):
+ *   out(seed, t)  = mix64(seed + 0x9E3779B97F4A7C15 * (t+1))   [SplitMix64]
+ *   key           = out(seed, h);   word t = out(key, t) >> 32
+ *   bounded(m)    = Lemire multiply-shift with rejection on successive words
+ *   block         = Floyd: for j = range-b .. range-1: v = bounded(j+1);
+ *                   append (v already drawn ? j : v)   (insertion order)
+ * Requires 1 <= b <= range <= 2^31-1, count >= 0.
+ */
+cabcd_status cabcd_sample(uint64_t seed, int64_t h0, int64_t count, int32_t b,
+                          int64_t range, int32_t* idx, void* stream);
+
+/*
+ * Gram of gathered rows (Alg. 2 Gram step, Alg. 4 Gram step; Section 4,
+ * Thm. cabcd1dcol): with Y the m x cols matrix of rows idx[0..m) of A,
+ *   G  = scale * Y Y^T + shift * I     (m x m, row-major, both triangles, ld m)
+ *   Yu = Y u                           (m; only if u and Yu are non-NULL)
+ * Primal CA-BCD uses scale 1/n, shift lambda; dual uses 1/(lambda n^2), 1/n.
+ * Dense F64 / BF16 / FP8 and CSR F64.  Low-precision rows are multiplied in
+ * their storage type with FP32 accumulation; the row scales and the
+ * cross-tile sum are applied in FP64.  Indices may repeat.  m >= 1.
+ */
+cabcd_status cabcd_gram(const cabcd_matrix* A, const int32_t* idx, int32_t m,
+                        double scale, double shift, const double* u, double* G,
+                        double* Yu, void* stream);
+
+/*
+ * Primal CA-BCD (Alg. 2; s = 1 is BCD, Alg. 1), H inner iterations.
+ *   X      A = X, d x n (rows = features)
+ *   y      n labels
+ *   w      in: w_0, out: w_H (d)
+ *   r      in (only with CABCD_FLAG_STATE_VALID): X^T w_0 - y; out: the residual
+ *          z_H - y maintained by the recurrence (n).  The paper's z = X^T w is
+ *          kept as r = z - y.
+ * The outer loop runs ceil(H/s) steps; the last has H - s*(ceil(H/s)-1) inner
+ * iterations.  Blocks come from the sampler over [0, d) or opts->explicit_idx.
+ * 1 <= b <= d, s >= 1, s*b <= 1024, H >= 0, lambda > 0.
+ */
+cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lambda,
+                              int32_t b, int32_t s, int64_t H, uint64_t seed,
+                              double* w, double* r, const cabcd_opts* opts,
+                              void* stream);
+
+/*
+ * Dual CA-BDCD (Alg. 4; s = 1 is BDCD, Alg. 3), H inner iterations.
+ *   XT     A = X^T, n x d (rows = data points)
+ *   y      n labels
+ *   alpha  in: a_0, out: a_H (n)
+ *   w      in (only with CABCD_FLAG_STATE_VALID): -X a_0/(lambda n);
+ *          out: w_H maintained by the recurrence (d)
+ * 1 <= b <= n, s >= 1, s*b <= 1024, H >= 0, lambda > 0.
+ */
+cabcd_status cabcd_dual_bcd(const cabcd_matrix* XT, const double* y, double lambda,
+                            int32_t b, int32_t s, int64_t H, uint64_t seed,
+                            double* alpha, double* w, const cabcd_opts* opts,
+                            void* stream);
+
+/*
+ * Exact primal residual and objective (Section 5.1.5: the full residual is
+ * recomputed occasionally; eq. primal): given A = X (d x n),
+ *   r = X^T w - y (n, FP64 accumulation)   and   *f = f(w)  (device scalar).
+ * Either output may be NULL.
+ */
+cabcd_status cabcd_primal_objective(const cabcd_matrix* X, const double* y,
+                                    double lambda, const double* w, double* r,
+                                    double* f, void* stream);
+
+/*
+ * Primal objective f(w) evaluated with A = X^T (n x d, the dual layout):
+ * r = A w - y, *f = 1/(2n)||r||^2 + lambda/2 ||w||^2.  Outputs may be NULL.
+ */
+cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y,
+                                      double lambda, const double* w, double* r,
+                                      double* f, void* stream);
+
+/*
+ * Primal-dual map (eq. 3) with A = X^T (n x d): w = -X a / (lambda n) (d).
+ */
+cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha,
+                                  double lambda, double* w, void* stream);
+
+/* Workspace bytes a call of cabcd_primal_bcd / cabcd_dual_bcd with these
+ * arguments needs when opts->workspace is supplied. */
+size_t cabcd_workspace_bytes(const cabcd_matrix* A, int32_t b, int32_t s);
+
+/* Thread-local message describing the most recent failing call ("" if none). */
+const char* cabcd_last_error(void);
+
+/* Library version string. */
+const char* cabcd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CABCD_H */

@@ -1,0 +1,271 @@
+"""Python binding of libcabcd (CA-BCD / CA-BDCD on MI355X).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libcabcd.so.  Device memory and streams come from PyTorch tensors.  The
+functions mirror the C entry points of include/cabcd.h without the `cabcd_`
+prefix.  Loading fails loudly when the built library is missing; there is no
+CPU fallback.
+"""
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcabcd.so")
+
+OK, EINVAL, ENOTSPD, EHIP, ENOMEM, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+DENSE, CSR = 0, 1
+F64, BF16, FP8_E4M3 = 0, 1, 2
+FLAG_STATE_VALID, FLAG_ASYNC = 1, 2
+
+_STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOTSPD: "ENOTSPD", EHIP: "EHIP",
+                 ENOMEM: "ENOMEM", EUNSUPPORTED: "EUNSUPPORTED", ENONFINITE: "ENONFINITE"}
+
+
+class CabcdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("data", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("row_scale", ctypes.c_void_p),
+                ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p),
+                ("vals", ctypes.c_void_p), ("nnz", ctypes.c_int64)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("h0", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("resid_every", ctypes.c_int32), ("monitor_every", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32),
+                ("explicit_idx", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("trace_len", ctypes.c_int64),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("timing", ctypes.POINTER(ctypes.c_double))]
+
+
+NPHASES = 7
+PHASES = ["sample", "gram", "reduce", "solve", "update", "recompute", "monitor"]
+
+
+_lib = None
+
+
+def load():
+    """Load libcabcd.so (built by build.py).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_1612_04003_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64, D, U32 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.c_uint64, ctypes.c_double, ctypes.c_uint32)
+    MP = ctypes.POINTER(Matrix)
+    OP = ctypes.POINTER(Opts)
+    sigs = {
+        "cabcd_opts_init": (None, [OP]),
+        "cabcd_sample": (I32, [U64, I64, I64, I32, I64, P, P]),
+        "cabcd_gram": (I32, [MP, P, I32, D, D, P, P, P, P]),
+        "cabcd_primal_bcd": (I32, [MP, P, D, I32, I32, I64, U64, P, P, OP, P]),
+        "cabcd_dual_bcd": (I32, [MP, P, D, I32, I32, I64, U64, P, P, OP, P]),
+        "cabcd_primal_objective": (I32, [MP, P, D, P, P, P, P]),
+        "cabcd_primal_objective_t": (I32, [MP, P, D, P, P, P, P]),
+        "cabcd_dual_to_primal": (I32, [MP, P, D, P, P]),
+        "cabcd_workspace_bytes": (ctypes.c_size_t, [MP, I32, I32]),
+        "cabcd_last_error": (ctypes.c_char_p, []),
+        "cabcd_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names of the C entry points this binding expects the library to export."""
+    return ["cabcd_opts_init", "cabcd_sample", "cabcd_gram", "cabcd_primal_bcd",
+            "cabcd_dual_bcd", "cabcd_primal_objective", "cabcd_primal_objective_t",
+            "cabcd_dual_to_primal", "cabcd_workspace_bytes", "cabcd_last_error",
+            "cabcd_version"]
+
+
+def _check(status):
+    if status != OK:
+        msg = load().cabcd_last_error()
+        raise CabcdError(status, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, name, numel=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def dense(A):
+    """Describe a row-major 2-D FP64 CUDA tensor (rows = samplable coordinates)."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("dense matrix must be 2-D with unit column stride")
+    if not A.is_cuda:
+        raise TypeError("matrix must live on the GPU")
+    if A.dtype != torch.float64:
+        raise TypeError("dense matrix must be float64")
+    m = Matrix()
+    m.kind, m.dtype = DENSE, F64
+    m.rows, m.cols = A.shape
+    m.data = A.data_ptr()
+    m.ld = A.stride(0)
+    m.row_scale = None
+    m._keep = A
+    return m
+
+
+def new_timing():
+    """Host array for per-phase timing (milliseconds, then launch counts)."""
+    return (ctypes.c_double * (2 * NPHASES))()
+
+
+def timing_dict(t):
+    return {name: {"ms": t[i], "launches": int(t[NPHASES + i])} for i, name in enumerate(PHASES)}
+
+
+def _opts(h0=0, flags=0, resid_every=0, monitor_every=0, explicit_idx=None, trace=None,
+          workspace=None, timing=None):
+    o = Opts()
+    load().cabcd_opts_init(ctypes.byref(o))
+    o.h0, o.flags = h0, flags
+    o.resid_every, o.monitor_every = resid_every, monitor_every
+    if explicit_idx is not None:
+        _need(explicit_idx, torch.int32, "explicit_idx")
+        o.explicit_idx = explicit_idx.data_ptr()
+    if trace is not None:
+        _need(trace, torch.float64, "trace")
+        o.trace, o.trace_len = trace.data_ptr(), trace.numel()
+    if workspace is not None:
+        _need(workspace, torch.uint8, "workspace")
+        o.workspace, o.workspace_bytes = workspace.data_ptr(), workspace.numel()
+    if timing is not None:
+        o.timing = ctypes.cast(timing, ctypes.POINTER(ctypes.c_double))
+    return o
+
+
+def _check_explicit(opt, H, b):
+    e = opt.get("explicit_idx")
+    if e is not None and e.numel() < H * b:
+        raise ValueError(f"explicit_idx holds {e.numel()} indices, need H*b = {H * b}")
+
+
+def sample(seed, h0, count, b, rng, out=None):
+    """Blocks of iterations h0 .. h0+count-1 as an int32 (count, b) tensor."""
+    if out is None:
+        out = torch.empty((count, b), dtype=torch.int32, device="cuda")
+    _need(out, torch.int32, "out", count * b)
+    _check(load().cabcd_sample(seed, h0, count, b, rng, _ptr(out), _stream()))
+    return out
+
+
+def gram(A, idx, scale, shift, u=None):
+    """(scale * Y Y^T + shift I, Y u) for the rows idx of the FP64 matrix A."""
+    M = dense(A)
+    _need(idx, torch.int32, "idx")
+    m = idx.numel()
+    G = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    Yu = None
+    if u is not None:
+        _need(u, torch.float64, "u", A.shape[1])
+        Yu = torch.empty(m, dtype=torch.float64, device=A.device)
+    _check(load().cabcd_gram(ctypes.byref(M), _ptr(idx), m, scale, shift, _ptr(u), _ptr(G),
+                             _ptr(Yu), _stream()))
+    return G, Yu
+
+
+def primal_bcd(X, y, lam, b, s, H, seed, w=None, r=None, **opt):
+    """Primal CA-BCD on A = X (d x n).  Returns (w_H, r_H = z_H - y)."""
+    M = dense(X)
+    d, n = X.shape
+    _need(y, torch.float64, "y", n)
+    if w is None:
+        w = torch.zeros(d, dtype=torch.float64, device=X.device)
+    _need(w, torch.float64, "w", d)
+    if r is None:
+        r = torch.empty(n, dtype=torch.float64, device=X.device)
+    _need(r, torch.float64, "r", n)
+    _check_explicit(opt, H, b)
+    o = _opts(**opt)
+    _check(load().cabcd_primal_bcd(ctypes.byref(M), _ptr(y), lam, b, s, H, seed, _ptr(w),
+                                   _ptr(r), ctypes.byref(o), _stream()))
+    return w, r
+
+
+def dual_bcd(XT, y, lam, b, s, H, seed, alpha=None, w=None, **opt):
+    """Dual CA-BDCD on A = X^T (n x d).  Returns (alpha_H, w_H)."""
+    M = dense(XT)
+    n, d = XT.shape
+    _need(y, torch.float64, "y", n)
+    if alpha is None:
+        alpha = torch.zeros(n, dtype=torch.float64, device=XT.device)
+    _need(alpha, torch.float64, "alpha", n)
+    if w is None:
+        w = torch.empty(d, dtype=torch.float64, device=XT.device)
+    _need(w, torch.float64, "w", d)
+    _check_explicit(opt, H, b)
+    o = _opts(**opt)
+    _check(load().cabcd_dual_bcd(ctypes.byref(M), _ptr(y), lam, b, s, H, seed, _ptr(alpha),
+                                 _ptr(w), ctypes.byref(o), _stream()))
+    return alpha, w
+
+
+def primal_objective(X, y, lam, w, r=None):
+    """(f(w), r = X^T w - y) from A = X."""
+    M = dense(X)
+    f = torch.empty(1, dtype=torch.float64, device=X.device)
+    if r is None:
+        r = torch.empty(X.shape[1], dtype=torch.float64, device=X.device)
+    _check(load().cabcd_primal_objective(ctypes.byref(M), _ptr(y), lam, _ptr(w), _ptr(r),
+                                         _ptr(f), _stream()))
+    return f, r
+
+
+def primal_objective_t(XT, y, lam, w, r=None):
+    """(f(w), r = X^T w - y) from A = X^T."""
+    M = dense(XT)
+    f = torch.empty(1, dtype=torch.float64, device=XT.device)
+    if r is None:
+        r = torch.empty(XT.shape[0], dtype=torch.float64, device=XT.device)
+    _check(load().cabcd_primal_objective_t(ctypes.byref(M), _ptr(y), lam, _ptr(w), _ptr(r),
+                                           _ptr(f), _stream()))
+    return f, r
+
+
+def dual_to_primal(XT, alpha, lam, w=None):
+    """w = -X alpha / (lambda n) from A = X^T."""
+    M = dense(XT)
+    if w is None:
+        w = torch.empty(XT.shape[1], dtype=torch.float64, device=XT.device)
+    _check(load().cabcd_dual_to_primal(ctypes.byref(M), _ptr(alpha), lam, _ptr(w), _stream()))
+    return w
+
+
+def workspace_bytes(A, b, s):
+    M = dense(A)
+    return int(load().cabcd_workspace_bytes(ctypes.byref(M), b, s))

@@ -1,0 +1,244 @@
+// Streaming vector passes over A (HBM-bound, FP64 accumulation).
+//
+// gemv_t: out = [beta base | out] + gamma * sum_p A[row(p)]^T v[p]
+//   * the deferred companion update of an outer step: primal z += X^T sum_t
+//     I_t dw_t (Alg. 2 update after eq. recur), dual w -= 1/(lambda n) X sum_t
+//     I_t da_t (Alg. 4 update), with row(p) = idx[p];
+//   * the exact recomputation of the full residual (Section 5.1.5): primal
+//     r = X^T w - y, dual w = -X a/(lambda n), with row(p) = p.
+//   Each thread owns two adjacent columns (16-byte loads) and walks its rows in
+//   order; when there are few columns the rows are split over workgroups and
+//   the row groups are summed afterwards in group order, so the result is
+//   deterministic.
+// gemv_n: out[p] = A[p] . v + beta base[p] (primal residual from the X^T
+//   layout), one wave per row.
+// objective: c1 ||a||^2 + c2 ||b||^2 in two deterministic passes.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace cabcd {
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kColsPerWG = 2 * kVecThreads;
+
+struct GemvT {
+  const double* A;
+  int64_t ld, cols;
+  const int32_t* idx;
+  int64_t m;
+  const double* v;
+  double gamma;
+  const double* base;
+  double beta;
+  int accumulate;
+  double* out;
+  double* scratch;   // rg x cols partials when the rows are split
+  int64_t rows_per_group;
+  int aligned;
+};
+
+__global__ __launch_bounds__(kVecThreads) void gemv_t_kernel(GemvT g) {
+  const int64_t k = ((int64_t)blockIdx.x * kVecThreads + threadIdx.x) * 2;
+  const int64_t p0 = (int64_t)blockIdx.y * g.rows_per_group;
+  const int64_t p1 = std::min(g.m, p0 + g.rows_per_group);
+  if (k >= g.cols) return;
+  const bool two = k + 1 < g.cols;
+  const bool vec = two && g.aligned;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t p = p0;
+  for (; p + 4 <= p1; p += 4) {
+    double2 x[4];
+    double c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = g.idx ? (int64_t)g.idx[p + q] : p + q;
+      const double* a = g.A + row * g.ld + k;
+      c[q] = g.v[p + q];
+      if (vec) {
+        x[q] = *reinterpret_cast<const double2*>(a);
+      } else {
+        x[q].x = a[0];
+        x[q].y = two ? a[1] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s0 = fma(x[q].x, c[q], s0);
+      s1 = fma(x[q].y, c[q], s1);
+    }
+  }
+  for (; p < p1; ++p) {
+    const int64_t row = g.idx ? (int64_t)g.idx[p] : p;
+    const double* a = g.A + row * g.ld + k;
+    const double c = g.v[p];
+    s0 = fma(a[0], c, s0);
+    if (two) s1 = fma(a[1], c, s1);
+  }
+  if (g.scratch != nullptr) {
+    double* o = g.scratch + (int64_t)blockIdx.y * g.cols + k;
+    o[0] = s0;
+    if (two) o[1] = s1;
+    return;
+  }
+  double* o = g.out + k;
+  const double b0 = g.accumulate ? o[0] : (g.base ? g.beta * g.base[k] : 0.0);
+  o[0] = b0 + g.gamma * s0;
+  if (two) {
+    const double b1 = g.accumulate ? o[1] : (g.base ? g.beta * g.base[k + 1] : 0.0);
+    o[1] = b1 + g.gamma * s1;
+  }
+}
+
+__global__ __launch_bounds__(kVecThreads) void gemv_t_combine_kernel(GemvT g, int groups) {
+  const int64_t k = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (k >= g.cols) return;
+  double s = 0.0;
+  for (int r = 0; r < groups; ++r) s += g.scratch[(int64_t)r * g.cols + k];
+  const double b0 = g.accumulate ? g.out[k] : (g.base ? g.beta * g.base[k] : 0.0);
+  g.out[k] = b0 + g.gamma * s;
+}
+
+int gemv_t_groups(int64_t m, int64_t cols) {
+  const int64_t tiles = (cols + kColsPerWG - 1) / kColsPerWG;
+  int64_t rg = (1024 + tiles - 1) / tiles;
+  rg = std::min<int64_t>(rg, std::max<int64_t>(1, m / 16));
+  rg = std::min<int64_t>(rg, 4096);
+  return (int)std::max<int64_t>(rg, 1);
+}
+
+__global__ __launch_bounds__(kVecThreads) void gemv_n_kernel(const double* __restrict__ A,
+                                                             int64_t ld, int64_t rows,
+                                                             int64_t cols,
+                                                             const double* __restrict__ v,
+                                                             const double* __restrict__ base,
+                                                             double beta,
+                                                             double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * (kVecThreads / 64) + (threadIdx.x >> 6);
+  if (p >= rows) return;
+  const double* a = A + p * ld;
+  double s = 0.0;
+  for (int64_t k = lane; k < cols; k += 64) s = fma(a[k], v[k], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[p] = s + (base ? beta * base[p] : 0.0);
+}
+
+constexpr int kObjBlocks = 512;
+
+__global__ __launch_bounds__(kVecThreads) void sumsq_kernel(const double* __restrict__ a,
+                                                            int64_t na,
+                                                            const double* __restrict__ b,
+                                                            int64_t nb,
+                                                            double* __restrict__ part) {
+  __shared__ double red[kVecThreads];
+  for (int which = 0; which < 2; ++which) {
+    const double* x = which == 0 ? a : b;
+    const int64_t n = which == 0 ? na : nb;
+    double s = 0.0;
+    if (x != nullptr)
+      for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+           i += (int64_t)gridDim.x * kVecThreads)
+        s = fma(x[i], x[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kVecThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[which * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kVecThreads) void objective_final_kernel(
+    const double* __restrict__ part, int blocks, double c1, double c2, double* __restrict__ out,
+    int* __restrict__ status) {
+  __shared__ double red[2][kVecThreads];
+  for (int which = 0; which < 2; ++which) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < blocks; i += kVecThreads) s += part[which * blocks + i];
+    red[which][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = kVecThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double f = c1 * red[0][0] + c2 * red[1][0];
+    *out = f;
+    if (status != nullptr && !isfinite(f)) *status = DEV_NONFINITE;
+  }
+}
+
+}  // namespace
+
+size_t gemv_t_scratch_doubles(int64_t m, int64_t cols) {
+  const int rg = gemv_t_groups(m, cols);
+  return rg > 1 ? (size_t)rg * (size_t)cols : 0;
+}
+
+hipError_t launch_gemv_t(const double* A, int64_t ld, int64_t cols, const int32_t* idx,
+                         int64_t m, const double* v, double gamma, const double* base,
+                         double beta, bool accumulate, double* out, double* scratch,
+                         hipStream_t st) {
+  if (cols <= 0) return hipSuccess;
+  GemvT g{};
+  g.A = A;
+  g.ld = ld;
+  g.cols = cols;
+  g.idx = idx;
+  g.m = m;
+  g.v = v;
+  g.gamma = gamma;
+  g.base = base;
+  g.beta = beta;
+  g.accumulate = accumulate ? 1 : 0;
+  g.out = out;
+  g.aligned = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (ld & 1) == 0) ? 1 : 0;
+  const int rg = gemv_t_groups(m, cols);
+  g.rows_per_group = (m + rg - 1) / rg;
+  g.scratch = rg > 1 ? scratch : nullptr;
+  if (rg > 1 && scratch == nullptr) return hipErrorInvalidValue;
+  const int64_t tiles = (cols + kColsPerWG - 1) / kColsPerWG;
+  hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)tiles, (unsigned)rg), dim3(kVecThreads), 0,
+                     st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || rg == 1) return e;
+  hipLaunchKernelGGL(gemv_t_combine_kernel,
+                     dim3((unsigned)((cols + kVecThreads - 1) / kVecThreads)),
+                     dim3(kVecThreads), 0, st, g, rg);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_n(const double* A, int64_t ld, int64_t rows, int64_t cols,
+                         const double* v, const double* base, double beta, double* out,
+                         hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int64_t per = kVecThreads / 64;
+  hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)((rows + per - 1) / per)), dim3(kVecThreads),
+                     0, st, A, ld, rows, cols, v, base, beta, out);
+  return hipGetLastError();
+}
+
+size_t objective_scratch_doubles(int64_t, int64_t) { return 2 * kObjBlocks; }
+
+hipError_t launch_objective(const double* a, int64_t na, double c1, const double* b,
+                            int64_t nb, double c2, double* out, double* scratch, int* status,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(sumsq_kernel, dim3(kObjBlocks), dim3(kVecThreads), 0, st, a, na, b, nb,
+                     scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(objective_final_kernel, dim3(1), dim3(kVecThreads), 0, st, scratch,
+                     kObjBlocks, c1, c2, out, status);
+  return hipGetLastError();
+}
+
+}  // namespace cabcd

@@ -1,0 +1,90 @@
+"""The C-ABI library: it loads, exports every entry point include/cabcd.h
+declares, and rejects invalid arguments before touching the GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1612_04003_amd as cabcd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cabcd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cabcd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(cabcd.exported_symbols())
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cabcd.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.cabcd_version().decode().startswith("cabcd")
+
+
+def test_struct_layout_matches_header():
+    # Field order and sizes of the two structs as the header declares them.
+    assert ctypes.sizeof(cabcd.Matrix) == 4 + 4 + 8 * 9
+    assert ctypes.sizeof(cabcd.Opts) == 8 + 4 + 4 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8
+
+
+def _fake_matrix(rows, cols, kind=cabcd.DENSE, dtype=cabcd.F64):
+    m = cabcd.Matrix()
+    m.kind, m.dtype, m.rows, m.cols = kind, dtype, rows, cols
+    m.data = 0x1000          # never dereferenced: validation fails first
+    m.ld = cols
+    return m
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(lam=0.0), cabcd.EINVAL),
+    (dict(lam=-1.0), cabcd.EINVAL),
+    (dict(lam=float("nan")), cabcd.EINVAL),
+    (dict(b=0), cabcd.EINVAL),
+    (dict(b=65), cabcd.EINVAL),        # b > d
+    (dict(s=0), cabcd.EINVAL),
+    (dict(H=-1), cabcd.EINVAL),
+    (dict(b=33), cabcd.EUNSUPPORTED),
+    (dict(b=16, s=17), cabcd.EUNSUPPORTED),
+])
+def test_primal_argument_errors(kw, status):
+    lib = cabcd.load()
+    args = dict(lam=1e-3, b=4, s=8, H=10)
+    args.update(kw)
+    M = _fake_matrix(64, 1024)
+    st = lib.cabcd_primal_bcd(ctypes.byref(M), ctypes.c_void_p(0x2000), args["lam"],
+                              args["b"], args["s"], args["H"], 1, ctypes.c_void_p(0x3000),
+                              ctypes.c_void_p(0x4000), None, None)
+    assert st == status
+    assert lib.cabcd_last_error().decode() != ""
+
+
+def test_matrix_errors():
+    lib = cabcd.load()
+    st = lib.cabcd_primal_bcd(None, None, 1.0, 1, 1, 1, 0, None, None, None, None)
+    assert st == cabcd.EINVAL
+    M = _fake_matrix(64, 1024)
+    M.ld = 100
+    assert lib.cabcd_dual_bcd(ctypes.byref(M), ctypes.c_void_p(8), 1.0, 1, 1, 1, 0,
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None) == cabcd.EINVAL
+    M = _fake_matrix(64, 1024, dtype=7)
+    assert lib.cabcd_gram(ctypes.byref(M), ctypes.c_void_p(8), 4, 1.0, 0.0, None,
+                          ctypes.c_void_p(8), None, None) == cabcd.EINVAL
+    assert lib.cabcd_sample(1, 0, 4, 5, 4, ctypes.c_void_p(8), None) == cabcd.EINVAL
+    assert lib.cabcd_sample(1, -1, 4, 1, 4, ctypes.c_void_p(8), None) == cabcd.EINVAL
+
+
+def test_workspace_bytes_grows_with_problem():
+    lib = cabcd.load()
+    a = lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(64, 1024)), 4, 8)
+    b = lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(2048, 262144)), 8, 32)
+    assert 0 < a < b
+    assert lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(64, 1024)), 16, 17) == 0
