@@ -150,9 +150,11 @@ cabcd_status cabcd_sample(uint64_t seed, int64_t h0, int64_t count, int32_t b,
  *   G  = scale * Y Y^T + shift * I     (m x m, row-major, both triangles, ld m)
  *   Yu = Y u                           (m; only if u and Yu are non-NULL)
  * Primal CA-BCD uses scale 1/n, shift lambda; dual uses 1/(lambda n^2), 1/n.
- * Dense F64 / BF16 / FP8 and CSR F64.  Low-precision rows are multiplied in
- * their storage type with FP32 accumulation; the row scales and the
- * cross-tile sum are applied in FP64.  Indices may repeat.  m >= 1.
+ * Dense F64 / BF16 / FP8 (m <= 256) and CSR F64 (m <= 1024).  Low-precision
+ * rows are multiplied in their storage type on the matrix cores with FP32
+ * accumulation inside a workgroup's slab; the slabs are summed and the row
+ * scales applied in FP64; Yu is computed in FP64 from the decoded values.
+ * Indices may repeat.  m >= 1.
  */
 cabcd_status cabcd_gram(const cabcd_matrix* A, const int32_t* idx, int32_t m,
                         double scale, double shift, const double* u, double* G,
@@ -168,7 +170,10 @@ cabcd_status cabcd_gram(const cabcd_matrix* A, const int32_t* idx, int32_t m,
  *          kept as r = z - y.
  * The outer loop runs ceil(H/s) steps; the last has H - s*(ceil(H/s)-1) inner
  * iterations.  Blocks come from the sampler over [0, d) or opts->explicit_idx.
- * 1 <= b <= d, s >= 1, s*b <= 1024, H >= 0, lambda > 0.
+ * X may be dense F64, dense BF16 / FP8 (mixed precision: the Gram on the
+ * stored codes with FP32 accumulation, everything else in FP64 on X^; set
+ * opts->resid_every to recompute r exactly every few outer steps) or CSR F64.
+ * 1 <= b <= min(d, 32), s >= 1, s*b <= 256 dense / 1024 CSR, H >= 0, lambda > 0.
  */
 cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lambda,
                               int32_t b, int32_t s, int64_t H, uint64_t seed,
@@ -182,11 +187,26 @@ cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lam
  *   alpha  in: a_0, out: a_H (n)
  *   w      in (only with CABCD_FLAG_STATE_VALID): -X a_0/(lambda n);
  *          out: w_H maintained by the recurrence (d)
- * 1 <= b <= n, s >= 1, s*b <= 1024, H >= 0, lambda > 0.
+ * X^T may be dense F64 or CSR F64 (low-precision storage: CABCD_EUNSUPPORTED).
+ * 1 <= b <= min(n, 32), s >= 1, s*b <= 256 dense / 1024 CSR, H >= 0, lambda > 0.
  */
 cabcd_status cabcd_dual_bcd(const cabcd_matrix* XT, const double* y, double lambda,
                             int32_t b, int32_t s, int64_t H, uint64_t seed,
                             double* alpha, double* w, const cabcd_opts* opts,
+                            void* stream);
+
+/*
+ * Low-precision storage of a dense FP64 matrix for the mixed-precision mode.
+ * Codes are rounded from FP64 directly to nearest, ties to even:
+ *   CABCD_BF16      uint16 BF16 codes; row_scale (may be NULL) is set to 1.
+ *   CABCD_FP8_E4M3  uint8 OCP E4M3 codes (largest finite 448, saturating) of
+ *                   A[i][k] / s_i with s_i = fp32(amax_i / 448) (1 for an
+ *                   all-zero row) written to row_scale[i] (required).
+ * The stored matrix X^ = diag(s) Q is the problem the mixed-precision runs
+ * solve (exact in FP64).  A: rows x cols, ld lda (FP64); Q: ld ldq elements.
+ */
+cabcd_status cabcd_quantize(const double* A, int64_t rows, int64_t cols, int64_t lda,
+                            int32_t dtype, void* Q, int64_t ldq, float* row_scale,
                             void* stream);
 
 /*

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcabcd.so")
 
 OK, EINVAL, ENOTSPD, EHIP, ENOMEM, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
-DENSE, CSR = 0, 1
+DENSE, CSR_KIND = 0, 1
 F64, BF16, FP8_E4M3 = 0, 1, 2
 FLAG_STATE_VALID, FLAG_ASYNC = 1, 2
 
@@ -78,6 +78,7 @@ def load():
         "cabcd_primal_objective_t": (I32, [MP, P, D, P, P, P, P]),
         "cabcd_dual_to_primal": (I32, [MP, P, D, P, P]),
         "cabcd_workspace_bytes": (ctypes.c_size_t, [MP, I32, I32]),
+        "cabcd_quantize": (I32, [P, I64, I64, I64, I32, P, I64, P, P]),
         "cabcd_last_error": (ctypes.c_char_p, []),
         "cabcd_version": (ctypes.c_char_p, []),
     }
@@ -94,7 +95,7 @@ def exported_symbols():
     return ["cabcd_opts_init", "cabcd_sample", "cabcd_gram", "cabcd_primal_bcd",
             "cabcd_dual_bcd", "cabcd_primal_objective", "cabcd_primal_objective_t",
             "cabcd_dual_to_primal", "cabcd_workspace_bytes", "cabcd_last_error",
-            "cabcd_version"]
+            "cabcd_version", "cabcd_quantize"]
 
 
 def _check(status):
@@ -149,6 +150,87 @@ def timing_dict(t):
     return {name: {"ms": t[i], "launches": int(t[NPHASES + i])} for i, name in enumerate(PHASES)}
 
 
+class CSR:
+    """A CSR matrix on the GPU: rowptr (int64, rows+1), colidx (int32, nnz,
+    strictly increasing within a row), vals (float64, nnz), shape (rows, cols)."""
+
+    def __init__(self, rowptr, colidx, vals, shape):
+        _need(rowptr, torch.int64, "rowptr", shape[0] + 1)
+        _need(colidx, torch.int32, "colidx")
+        _need(vals, torch.float64, "vals", colidx.numel())
+        self.rowptr, self.colidx, self.vals = rowptr, colidx, vals
+        self.shape = (int(shape[0]), int(shape[1]))
+        self.device = vals.device
+
+    @classmethod
+    def from_scipy(cls, S, device="cuda"):
+        S = S.tocsr()
+        S.sort_indices()
+        return cls(torch.as_tensor(S.indptr.astype("int64")).to(device),
+                   torch.as_tensor(S.indices.astype("int32")).to(device),
+                   torch.as_tensor(S.data.astype("float64")).to(device), S.shape)
+
+
+class Quantized:
+    """Dense low-precision storage: codes (uint16 BF16 or uint8 E4M3 as int16 /
+    uint8 tensors, rows x cols), FP32 row scales (or None), dtype BF16 / FP8_E4M3."""
+
+    def __init__(self, codes, scales, dtype):
+        self.codes, self.scales, self.dtype = codes, scales, dtype
+        self.shape = tuple(codes.shape)
+        self.device = codes.device
+
+    def dequantize(self):
+        """X^ in FP64 (exact), computed with torch for tests and baselines."""
+        if self.dtype == BF16:
+            x = self.codes.view(torch.bfloat16).to(torch.float64)
+        else:
+            x = self.codes.view(torch.float8_e4m3fn).to(torch.float64)
+        if self.scales is not None:
+            x = x * self.scales.to(torch.float64)[:, None]
+        return x
+
+
+def quantize(A, dtype):
+    """Store the FP64 matrix A (rows x cols) as BF16 or FP8-E4M3 codes."""
+    _need(A, torch.float64, "A")
+    rows, cols = A.shape
+    if dtype == BF16:
+        codes = torch.empty((rows, cols), dtype=torch.int16, device=A.device)
+        scales = None
+    elif dtype == FP8_E4M3:
+        codes = torch.empty((rows, cols), dtype=torch.uint8, device=A.device)
+        scales = torch.empty(rows, dtype=torch.float32, device=A.device)
+    else:
+        raise ValueError("dtype must be BF16 or FP8_E4M3")
+    _check(load().cabcd_quantize(_ptr(A), rows, cols, A.stride(0), dtype, _ptr(codes), cols,
+                                 _ptr(scales), _stream()))
+    return Quantized(codes, scales, dtype)
+
+
+def describe(A):
+    """cabcd_matrix for a dense float64 CUDA tensor, a Quantized or a CSR object."""
+    if isinstance(A, Quantized):
+        m = Matrix()
+        m.kind, m.dtype = DENSE, A.dtype
+        m.rows, m.cols = A.shape
+        m.data = A.codes.data_ptr()
+        m.ld = A.codes.stride(0)
+        m.row_scale = None if A.scales is None else A.scales.data_ptr()
+        m._keep = A
+        return m
+    if isinstance(A, CSR):
+        m = Matrix()
+        m.kind, m.dtype = CSR_KIND, F64
+        m.rows, m.cols = A.shape
+        m.rowptr, m.colidx, m.vals = (A.rowptr.data_ptr(), A.colidx.data_ptr(),
+                                      A.vals.data_ptr())
+        m.nnz = A.colidx.numel()
+        m._keep = A
+        return m
+    return dense(A)
+
+
 def _opts(h0=0, flags=0, resid_every=0, monitor_every=0, explicit_idx=None, trace=None,
           workspace=None, timing=None):
     o = Opts()
@@ -185,8 +267,8 @@ def sample(seed, h0, count, b, rng, out=None):
 
 
 def gram(A, idx, scale, shift, u=None):
-    """(scale * Y Y^T + shift I, Y u) for the rows idx of the FP64 matrix A."""
-    M = dense(A)
+    """(scale * Y Y^T + shift I, Y u) for the rows idx of A (dense or CSR)."""
+    M = describe(A)
     _need(idx, torch.int32, "idx")
     m = idx.numel()
     G = torch.empty((m, m), dtype=torch.float64, device=A.device)
@@ -200,8 +282,8 @@ def gram(A, idx, scale, shift, u=None):
 
 
 def primal_bcd(X, y, lam, b, s, H, seed, w=None, r=None, **opt):
-    """Primal CA-BCD on A = X (d x n).  Returns (w_H, r_H = z_H - y)."""
-    M = dense(X)
+    """Primal CA-BCD on A = X (d x n, dense or CSR).  Returns (w_H, r_H = z_H - y)."""
+    M = describe(X)
     d, n = X.shape
     _need(y, torch.float64, "y", n)
     if w is None:
@@ -218,8 +300,8 @@ def primal_bcd(X, y, lam, b, s, H, seed, w=None, r=None, **opt):
 
 
 def dual_bcd(XT, y, lam, b, s, H, seed, alpha=None, w=None, **opt):
-    """Dual CA-BDCD on A = X^T (n x d).  Returns (alpha_H, w_H)."""
-    M = dense(XT)
+    """Dual CA-BDCD on A = X^T (n x d, dense or CSR).  Returns (alpha_H, w_H)."""
+    M = describe(XT)
     n, d = XT.shape
     _need(y, torch.float64, "y", n)
     if alpha is None:
@@ -237,7 +319,7 @@ def dual_bcd(XT, y, lam, b, s, H, seed, alpha=None, w=None, **opt):
 
 def primal_objective(X, y, lam, w, r=None):
     """(f(w), r = X^T w - y) from A = X."""
-    M = dense(X)
+    M = describe(X)
     f = torch.empty(1, dtype=torch.float64, device=X.device)
     if r is None:
         r = torch.empty(X.shape[1], dtype=torch.float64, device=X.device)
@@ -248,7 +330,7 @@ def primal_objective(X, y, lam, w, r=None):
 
 def primal_objective_t(XT, y, lam, w, r=None):
     """(f(w), r = X^T w - y) from A = X^T."""
-    M = dense(XT)
+    M = describe(XT)
     f = torch.empty(1, dtype=torch.float64, device=XT.device)
     if r is None:
         r = torch.empty(XT.shape[0], dtype=torch.float64, device=XT.device)
@@ -259,7 +341,7 @@ def primal_objective_t(XT, y, lam, w, r=None):
 
 def dual_to_primal(XT, alpha, lam, w=None):
     """w = -X alpha / (lambda n) from A = X^T."""
-    M = dense(XT)
+    M = describe(XT)
     if w is None:
         w = torch.empty(XT.shape[1], dtype=torch.float64, device=XT.device)
     _check(load().cabcd_dual_to_primal(ctypes.byref(M), _ptr(alpha), lam, _ptr(w), _stream()))
@@ -267,5 +349,5 @@ def dual_to_primal(XT, alpha, lam, w=None):
 
 
 def workspace_bytes(A, b, s):
-    M = dense(A)
+    M = describe(A)
     return int(load().cabcd_workspace_bytes(ctypes.byref(M), b, s))

@@ -33,9 +33,8 @@ void clear_error() { g_err.clear(); }
 
 namespace {
 
-constexpr int kMaxSB = 256;       // s*b handled by one Gram launch and one solve
-constexpr int kMaxB = 32;         // block size handled by the fused solve
-constexpr int64_t kIdxChunkSteps = 4096;   // outer steps whose indices are drawn at once
+constexpr int kMaxSBDense = 256;            // s*b of one dense FP64 Gram launch
+constexpr int64_t kIdxChunkSteps = 4096;    // outer steps whose indices are drawn at once
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
 
@@ -97,7 +96,21 @@ struct Carve {
     }                                                                         \
   } while (0)
 
-cabcd_status check_dense(const cabcd_matrix* A, const char* name) {
+// ----------------------------------------------------------------- matrices
+// The library's view of A: dense FP64 / BF16 / FP8 (row-major) or CSR FP64.
+struct Mat {
+  bool csr = false;
+  int dtype = CABCD_F64;
+  const double* X = nullptr;     // dense FP64
+  const void* Q = nullptr;       // dense BF16 / FP8 codes
+  const float* rs = nullptr;     // their row scales (NULL = 1)
+  int64_t ld = 0;
+  CsrView C{};
+  int64_t rows = 0, cols = 0;
+  bool lowp() const { return !csr && dtype != CABCD_F64; }
+};
+
+cabcd_status check_matrix(const cabcd_matrix* A, const char* name, Mat* M) {
   if (A == nullptr) {
     set_error("%s is NULL", name);
     return CABCD_EINVAL;
@@ -107,20 +120,32 @@ cabcd_status check_dense(const cabcd_matrix* A, const char* name) {
               (long long)A->rows, (long long)A->cols);
     return CABCD_EINVAL;
   }
-  if (A->kind != CABCD_DENSE && A->kind != CABCD_CSR) {
-    set_error("%s: unknown kind %d", name, A->kind);
+  if (A->rows > INT32_MAX || A->cols > INT32_MAX) {
+    set_error("%s: rows and cols must be below 2^31", name);
     return CABCD_EINVAL;
   }
-  if (A->kind == CABCD_CSR) {
-    set_error("%s: CSR storage is not supported by this entry point yet", name);
-    return CABCD_EUNSUPPORTED;
-  }
-  if (A->dtype != CABCD_F64) {
-    if (A->dtype == CABCD_BF16 || A->dtype == CABCD_FP8_E4M3) {
-      set_error("%s: low-precision storage is not supported by this entry point yet", name);
-      return CABCD_EUNSUPPORTED;
-    }
+  if (A->dtype != CABCD_F64 && A->dtype != CABCD_BF16 && A->dtype != CABCD_FP8_E4M3) {
     set_error("%s: unknown dtype %d", name, A->dtype);
+    return CABCD_EINVAL;
+  }
+  M->rows = A->rows;
+  M->cols = A->cols;
+  if (A->kind == CABCD_CSR) {
+    if (A->dtype != CABCD_F64) {
+      set_error("%s: CSR storage holds FP64 values only", name);
+      return CABCD_EINVAL;
+    }
+    if (A->rowptr == nullptr || A->nnz < 0 || (A->nnz > 0 && (A->colidx == nullptr ||
+                                                              A->vals == nullptr))) {
+      set_error("%s: CSR needs rowptr, and colidx and vals when nnz > 0", name);
+      return CABCD_EINVAL;
+    }
+    M->csr = true;
+    M->C = CsrView{A->rowptr, A->colidx, A->vals, A->rows, A->cols, A->nnz};
+    return CABCD_OK;
+  }
+  if (A->kind != CABCD_DENSE) {
+    set_error("%s: unknown kind %d", name, A->kind);
     return CABCD_EINVAL;
   }
   if (A->data == nullptr || A->ld < A->cols) {
@@ -128,11 +153,72 @@ cabcd_status check_dense(const cabcd_matrix* A, const char* name) {
               (long long)A->cols);
     return CABCD_EINVAL;
   }
-  if (A->rows > INT32_MAX) {
-    set_error("%s: more than 2^31-1 rows", name);
+  M->dtype = A->dtype;
+  M->ld = A->ld;
+  if (A->dtype == CABCD_F64) {
+    M->X = static_cast<const double*>(A->data);
+  } else {
+    M->Q = A->data;
+    M->rs = A->row_scale;
+  }
+  return CABCD_OK;
+}
+
+// Device-side structure check of a CSR matrix (one synchronisation).
+cabcd_status check_csr_device(const Mat& M, int* flag_dev, hipStream_t st) {
+  if (!M.csr) return CABCD_OK;
+  int h = 0;
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, flag_dev, 0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_csr_check(M.C, flag_dev, st));
+  HIP_TRY(hipMemcpyAsync(&h, flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h != 0) {
+    set_error("malformed CSR: rowptr must start at 0, be non-decreasing and end at nnz; "
+              "columns strictly increasing within a row and below cols");
     return CABCD_EINVAL;
   }
   return CABCD_OK;
+}
+
+int max_rows_per_gram(const Mat& M) { return M.csr ? kCsrMaxRows : kMaxSBDense; }
+
+GramPlan plan_for(const Mat& M, int m) {
+  return M.lowp() ? plan_gram_lp(m, M.cols, M.dtype) : plan_gram_f64(m, M.cols);
+}
+
+size_t max_partials(const Mat& M, int sb_max) {
+  if (M.csr) return 1;
+  size_t best = 0;
+  for (int m = 1;; m = (m < 16 ? 16 : m * 2)) {
+    best = std::max(best, gram_partial_doubles(plan_for(M, std::min(m, sb_max))));
+    if (m >= sb_max) break;
+  }
+  return best;
+}
+
+// out = [beta base | out] + gamma * sum_p A[row(p)]^T v[p]
+hipError_t mat_scatter(const Mat& M, const int32_t* idx, int64_t m, const double* v,
+                       double gamma, const double* base, double beta, bool accumulate,
+                       double* out, double* scratch, hipStream_t st) {
+  if (M.lowp())
+    return launch_gemv_t_lp(M.dtype, M.Q, M.ld, M.cols, M.rs, idx, m, v, gamma, base, beta,
+                            accumulate, out, st);
+  if (!M.csr)
+    return launch_gemv_t(M.X, M.ld, M.cols, idx, m, v, gamma, base, beta, accumulate, out,
+                         scratch, st);
+  if (!accumulate) {
+    hipError_t e = launch_fill(out, M.cols, base, beta, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_csr_scatter(M.C, idx, m, v, gamma, out, st);
+}
+
+// out[p] = A[p] . v + beta base[p]
+hipError_t mat_rowdot(const Mat& M, const double* v, const double* base, double beta,
+                      double* out, hipStream_t st) {
+  if (!M.csr) return launch_gemv_n(M.X, M.ld, M.rows, M.cols, v, base, beta, out, st);
+  return launch_csr_rowdot(M.C, v, base, beta, out, st);
 }
 
 cabcd_status finish(hipStream_t st, int* status_dev, bool async) {
@@ -225,47 +311,54 @@ class PhaseTimer {
   std::vector<Rec> recs_;
 };
 
+// scale * Y Y^T + shift * E and Y u for the rows idx[0..m) of A.
+hipError_t mat_gram(const Mat& M, const int32_t* idx, int m, const double* u, double scale,
+                    double shift, bool overlap, double* G, double* Yu, double* partials,
+                    hipStream_t st, PhaseTimer* timer) {
+  if (M.csr) {
+    auto f = [&] { return launch_csr_gram(M.C, idx, m, u, scale, shift, overlap, G, Yu, st); };
+    return timer ? timer->run(CABCD_PHASE_GRAM, f) : f();
+  }
+  const GramPlan plan = plan_for(M, m);
+  auto g = [&] {
+    return M.lowp() ? launch_gram_lp(plan, M.dtype, M.Q, M.ld, M.cols, idx, m, u, partials, st)
+                    : launch_gram_f64(plan, M.X, M.ld, M.cols, idx, m, u, partials, st);
+  };
+  auto r = [&] {
+    return launch_gram_reduce(plan, partials, idx, m, scale, shift, overlap, G, Yu, st,
+                              M.lowp() ? 1 : 0, M.lowp() ? M.rs : nullptr);
+  };
+  hipError_t e = timer ? timer->run(CABCD_PHASE_GRAM, g) : g();
+  if (e != hipSuccess) return e;
+  return timer ? timer->run(CABCD_PHASE_REDUCE, r) : r();
+}
+
 struct StepBuffers {
   int* status;
   int32_t* idx;      // kIdxChunkSteps * s * b
   double* G;         // sb x sb
   double* Yu;        // sb
   double* delta;     // sb
-  double* partials;  // Gram partials
+  double* partials;  // dense Gram partials
   double* scratch;   // gemv row-group partials
   double* obj;       // objective scratch
-  double* fval;      // 1 double
-  double* rtmp;      // companion-length temporary (monitoring)
+  double* rtmp;      // residual temporary (monitoring)
 };
 
-size_t max_partials(int sb_max, int64_t cols) {
-  size_t best = 0;
-  for (int m = 1; m <= sb_max; m = (m < 16 ? 16 : m * 2)) {
-    GramPlan p = plan_gram_f64(std::min(m, sb_max), cols);
-    best = std::max(best, gram_partial_doubles(p));
-    if (m >= sb_max) break;
-  }
-  GramPlan p = plan_gram_f64(sb_max, cols);
-  return std::max(best, gram_partial_doubles(p));
-}
-
-// Layout of the step workspace.  rows/cols are those of A; comp_len is the
-// length of the companion vector (cols for both methods); rtmp_len the length
-// of the monitoring temporary.
-size_t layout(Carve& c, StepBuffers& B, int64_t rows, int64_t cols, int b, int s,
-              int64_t rtmp_len) {
+// Layout of the step workspace.
+size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp_len) {
   const int sb = s * b;
   B.status = c.take<int>(1);
   B.idx = c.take<int32_t>((size_t)kIdxChunkSteps * sb);
   B.G = c.take<double>((size_t)sb * sb);
   B.Yu = c.take<double>(sb);
   B.delta = c.take<double>(sb);
-  B.partials = c.take<double>(max_partials(sb, cols));
-  const size_t sc = std::max(gemv_t_scratch_doubles(sb, cols),
-                             std::max(gemv_t_scratch_doubles(rows, cols), (size_t)1));
+  B.partials = c.take<double>(max_partials(M, sb));
+  const size_t sc = M.csr ? 1
+                          : std::max(gemv_t_scratch_doubles(sb, M.cols),
+                                     std::max(gemv_t_scratch_doubles(M.rows, M.cols), (size_t)1));
   B.scratch = c.take<double>(sc);
   B.obj = c.take<double>(objective_scratch_doubles(0, 0));
-  B.fval = c.take<double>(1);
   B.rtmp = c.take<double>(std::max<int64_t>(rtmp_len, 1));
   return c.off + 256;
 }
@@ -283,14 +376,13 @@ cabcd_status get_workspace(const cabcd_opts* o, size_t need, void** ws) {
   return pool_get(need, ws);
 }
 
-cabcd_status check_common(const cabcd_matrix* A, double lambda, int b, int s, int64_t H,
-                          int64_t range) {
+cabcd_status check_common(const Mat& M, double lambda, int b, int s, int64_t H) {
   if (!(lambda > 0.0) || !std::isfinite(lambda)) {
     set_error("lambda must be a positive finite number (got %g)", lambda);
     return CABCD_EINVAL;
   }
-  if (b < 1 || (int64_t)b > range) {
-    set_error("block size b = %d must satisfy 1 <= b <= %lld", b, (long long)range);
+  if (b < 1 || (int64_t)b > M.rows) {
+    set_error("block size b = %d must satisfy 1 <= b <= %lld", b, (long long)M.rows);
     return CABCD_EINVAL;
   }
   if (s < 1) {
@@ -301,31 +393,34 @@ cabcd_status check_common(const cabcd_matrix* A, double lambda, int b, int s, in
     set_error("H = %lld must be >= 0", (long long)H);
     return CABCD_EINVAL;
   }
-  if (b > kMaxB) {
-    set_error("block size b = %d exceeds the supported maximum %d", b, kMaxB);
+  if (b > kSolveMaxB) {
+    set_error("block size b = %d exceeds the supported maximum %d", b, kSolveMaxB);
     return CABCD_EUNSUPPORTED;
   }
-  if ((int64_t)s * b > kMaxSB) {
-    set_error("s*b = %lld exceeds the supported maximum %d", (long long)s * b, kMaxSB);
+  const int64_t sb = (int64_t)s * b;
+  if (sb > max_rows_per_gram(M)) {
+    set_error("s*b = %lld exceeds the supported maximum %d for %s storage", (long long)sb,
+              max_rows_per_gram(M), M.csr ? "CSR" : "dense");
     return CABCD_EUNSUPPORTED;
   }
-  (void)A;
+  if (solve_lds_bytes((int)sb, b) > kSolveMaxLds) {
+    set_error("s*b = %lld with b = %d needs more LDS than one workgroup has", (long long)sb, b);
+    return CABCD_EUNSUPPORTED;
+  }
   return CABCD_OK;
 }
 
 // One driver for both methods (they differ in the scalars and the role of the
 // vectors, see the fused solve).  primal: coord = w (d), comp = r (n).
 // dual: coord = alpha (n), comp = w (d).
-cabcd_status run_bcd(bool dual, const cabcd_matrix* A, const double* y, double lambda, int b,
-                     int s, int64_t H, uint64_t seed, double* coord, double* comp,
+cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, int b, int s,
+                     int64_t H, uint64_t seed, double* coord, double* comp,
                      const cabcd_opts* opts, hipStream_t st) {
   cabcd_opts o;
   cabcd_opts_init(&o);
   if (opts != nullptr) o = *opts;
-  const int64_t rows = A->rows, cols = A->cols;
+  const int64_t rows = M.rows, cols = M.cols;
   const double n = dual ? (double)rows : (double)cols;
-  const double* X = static_cast<const double*>(A->data);
-  const int64_t ld = A->ld;
   if (y == nullptr || coord == nullptr || comp == nullptr) {
     set_error("y, the coordinate vector and the companion vector must be non-NULL");
     return CABCD_EINVAL;
@@ -342,20 +437,26 @@ cabcd_status run_bcd(bool dual, const cabcd_matrix* A, const double* y, double l
     set_error("resid_every and monitor_every must be >= 0");
     return CABCD_EINVAL;
   }
+  if (o.timing != nullptr && (o.flags & CABCD_FLAG_ASYNC)) {
+    set_error("opts.timing needs a synchronising call");
+    return CABCD_EINVAL;
+  }
   if (o.explicit_idx != nullptr) {
     cabcd_status e = check_explicit(o.explicit_idx, H, b, rows, st);
     if (e != CABCD_OK) return e;
   }
-  // monitoring needs the residual of length n (primal: cols, dual: rows)
+  // monitoring needs the residual X^T w - y of length n (primal: cols, dual: rows)
   const int64_t rtmp_len = o.monitor_every > 0 ? (dual ? rows : cols) : 1;
   StepBuffers B{};
   Carve probe{nullptr};
-  const size_t need = layout(probe, B, rows, cols, b, s, rtmp_len);
+  const size_t need = layout(probe, B, M, b, s, rtmp_len);
   void* ws = nullptr;
   cabcd_status e = get_workspace(&o, need, &ws);
   if (e != CABCD_OK) return e;
   Carve carve{static_cast<char*>(ws)};
-  layout(carve, B, rows, cols, b, s, rtmp_len);
+  layout(carve, B, M, b, s, rtmp_len);
+  e = check_csr_device(M, B.status, st);
+  if (e != CABCD_OK) return e;
 
   hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, B.status, 0);
   HIP_TRY(hipGetLastError());
@@ -366,31 +467,25 @@ cabcd_status run_bcd(bool dual, const cabcd_matrix* A, const double* y, double l
 
   auto exact_companion = [&]() -> hipError_t {
     if (dual)   // w = -X alpha / (lambda n)
-      return launch_gemv_t(X, ld, cols, nullptr, rows, coord, -1.0 / (lambda * n), nullptr,
-                           0.0, false, comp, B.scratch, st);
+      return mat_scatter(M, nullptr, rows, coord, -1.0 / (lambda * n), nullptr, 0.0, false,
+                         comp, B.scratch, st);
     // r = X^T w - y
-    return launch_gemv_t(X, ld, cols, nullptr, rows, coord, 1.0, y, -1.0, false, comp,
-                         B.scratch, st);
+    return mat_scatter(M, nullptr, rows, coord, 1.0, y, -1.0, false, comp, B.scratch, st);
   };
   auto monitor = [&](int64_t slot) -> hipError_t {
     hipError_t he;
     if (dual) {   // f(w) with r = X^T w - y computed from the X^T layout
-      he = launch_gemv_n(X, ld, rows, cols, comp, y, -1.0, B.rtmp, st);
+      he = mat_rowdot(M, comp, y, -1.0, B.rtmp, st);
       if (he != hipSuccess) return he;
       return launch_objective(B.rtmp, rows, 0.5 / n, comp, cols, 0.5 * lambda, o.trace + slot,
                               B.obj, B.status, st);
     }
-    he = launch_gemv_t(X, ld, cols, nullptr, rows, coord, 1.0, y, -1.0, false, B.rtmp,
-                       B.scratch, st);
+    he = mat_scatter(M, nullptr, rows, coord, 1.0, y, -1.0, false, B.rtmp, B.scratch, st);
     if (he != hipSuccess) return he;
     return launch_objective(B.rtmp, cols, 0.5 / n, coord, rows, 0.5 * lambda, o.trace + slot,
                             B.obj, B.status, st);
   };
 
-  if (o.timing != nullptr && (o.flags & CABCD_FLAG_ASYNC)) {
-    set_error("opts.timing needs a synchronising call");
-    return CABCD_EINVAL;
-  }
   PhaseTimer timer(o.timing, st);
   if (!(o.flags & CABCD_FLAG_STATE_VALID))
     HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
@@ -415,13 +510,7 @@ cabcd_status run_bcd(bool dual, const cabcd_matrix* A, const double* y, double l
       }
       idx = B.idx + (h - chunk_begin) * b;
     }
-    const GramPlan plan = plan_gram_f64(m, cols);
-    HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
-      return launch_gram_f64(plan, X, ld, cols, idx, m, comp, B.partials, st);
-    }));
-    HIP_TRY(timer.run(CABCD_PHASE_REDUCE, [&] {
-      return launch_gram_reduce(plan, B.partials, idx, m, scale, shift, true, B.G, B.Yu, st);
-    }));
+    HIP_TRY(mat_gram(M, idx, m, comp, scale, shift, true, B.G, B.Yu, B.partials, st, &timer));
     SolveArgs sa{};
     sa.G = B.G;
     sa.Yu = B.Yu;
@@ -438,8 +527,7 @@ cabcd_status run_bcd(bool dual, const cabcd_matrix* A, const double* y, double l
     sa.n = n;
     HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] { return launch_solve(sa, st); }));
     HIP_TRY(timer.run(CABCD_PHASE_UPDATE, [&] {
-      return launch_gemv_t(X, ld, cols, idx, m, B.delta, gamma, nullptr, 0.0, true, comp,
-                           B.scratch, st);
+      return mat_scatter(M, idx, m, B.delta, gamma, nullptr, 0.0, true, comp, B.scratch, st);
     }));
     h += sk;
     ++k;
@@ -453,6 +541,31 @@ cabcd_status run_bcd(bool dual, const cabcd_matrix* A, const double* y, double l
   const cabcd_status fs = finish(st, B.status, (o.flags & CABCD_FLAG_ASYNC) != 0);
   HIP_TRY(timer.collect());
   return fs;
+}
+
+// Workspace for the single-pass helpers (residual, objective, dual map).
+struct AuxBuffers {
+  int* flag;
+  double* r;
+  double* scratch;
+  double* obj;
+};
+size_t aux_layout(Carve& c, AuxBuffers& B, const Mat& M, int64_t rlen) {
+  B.flag = c.take<int>(1);
+  B.r = c.take<double>(std::max<int64_t>(rlen, 1));
+  B.scratch = c.take<double>(M.csr ? 1 : std::max<size_t>(gemv_t_scratch_doubles(M.rows, M.cols), 1));
+  B.obj = c.take<double>(objective_scratch_doubles(0, 0));
+  return c.off + 256;
+}
+cabcd_status aux_get(const Mat& M, int64_t rlen, AuxBuffers& B) {
+  Carve probe{nullptr};
+  const size_t need = aux_layout(probe, B, M, rlen);
+  void* ws = nullptr;
+  cabcd_status e = pool_get(need, &ws);
+  if (e != CABCD_OK) return e;
+  Carve c{static_cast<char*>(ws)};
+  aux_layout(c, B, M, rlen);
+  return CABCD_OK;
 }
 
 }  // namespace
@@ -469,7 +582,7 @@ void cabcd_opts_init(cabcd_opts* o) {
 
 const char* cabcd_last_error(void) { return g_err.c_str(); }
 
-const char* cabcd_version(void) { return "cabcd 0.1 (gfx950)"; }
+const char* cabcd_version(void) { return "cabcd 0.2 (gfx950)"; }
 
 cabcd_status cabcd_sample(uint64_t seed, int64_t h0, int64_t count, int32_t b, int64_t range,
                           int32_t* idx, void* stream) {
@@ -486,14 +599,15 @@ cabcd_status cabcd_sample(uint64_t seed, int64_t h0, int64_t count, int32_t b, i
 cabcd_status cabcd_gram(const cabcd_matrix* A, const int32_t* idx, int32_t m, double scale,
                         double shift, const double* u, double* G, double* Yu, void* stream) {
   clear_error();
-  cabcd_status e = check_dense(A, "A");
+  Mat M;
+  cabcd_status e = check_matrix(A, "A", &M);
   if (e != CABCD_OK) return e;
   if (m < 1 || idx == nullptr || G == nullptr) {
     set_error("cabcd_gram: need m >= 1 and non-NULL idx and G");
     return CABCD_EINVAL;
   }
-  if (m > kMaxSB) {
-    set_error("cabcd_gram: m = %d exceeds the supported maximum %d", m, kMaxSB);
+  if (m > max_rows_per_gram(M)) {
+    set_error("cabcd_gram: m = %d exceeds the supported maximum %d", m, max_rows_per_gram(M));
     return CABCD_EUNSUPPORTED;
   }
   hipStream_t st = (hipStream_t)stream;
@@ -507,16 +621,20 @@ cabcd_status cabcd_gram(const cabcd_matrix* A, const int32_t* idx, int32_t m, do
         return CABCD_EINVAL;
       }
   }
-  const GramPlan plan = plan_gram_f64(m, A->cols);
+  Carve probe{nullptr};
+  int* flag = probe.take<int>(1);
+  double* part = probe.take<double>(max_partials(M, m));
   void* ws = nullptr;
-  e = pool_get(gram_partial_doubles(plan) * sizeof(double), &ws);
+  e = pool_get(probe.off + 256, &ws);
   if (e != CABCD_OK) return e;
-  double* part = static_cast<double*>(ws);
+  Carve c{static_cast<char*>(ws)};
+  flag = c.take<int>(1);
+  part = c.take<double>(max_partials(M, m));
+  e = check_csr_device(M, flag, st);
+  if (e != CABCD_OK) return e;
   const bool want_u = u != nullptr && Yu != nullptr;
-  HIP_TRY(launch_gram_f64(plan, static_cast<const double*>(A->data), A->ld, A->cols, idx, m,
-                          want_u ? u : nullptr, part, st));
-  HIP_TRY(launch_gram_reduce(plan, part, idx, m, scale, shift, false, G, want_u ? Yu : nullptr,
-                             st));
+  HIP_TRY(mat_gram(M, idx, m, want_u ? u : nullptr, scale, shift, false, G,
+                   want_u ? Yu : nullptr, part, st, nullptr));
   HIP_TRY(hipStreamSynchronize(st));
   return CABCD_OK;
 }
@@ -525,50 +643,50 @@ cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lam
                               int32_t s, int64_t H, uint64_t seed, double* w, double* r,
                               const cabcd_opts* opts, void* stream) {
   clear_error();
-  cabcd_status e = check_dense(X, "X");
+  Mat M;
+  cabcd_status e = check_matrix(X, "X", &M);
   if (e != CABCD_OK) return e;
-  e = check_common(X, lambda, b, s, H, X->rows);
+  e = check_common(M, lambda, b, s, H);
   if (e != CABCD_OK) return e;
-  return run_bcd(false, X, y, lambda, b, s, H, seed, w, r, opts, (hipStream_t)stream);
+  return run_bcd(false, M, y, lambda, b, s, H, seed, w, r, opts, (hipStream_t)stream);
 }
 
 cabcd_status cabcd_dual_bcd(const cabcd_matrix* XT, const double* y, double lambda, int32_t b,
                             int32_t s, int64_t H, uint64_t seed, double* alpha, double* w,
                             const cabcd_opts* opts, void* stream) {
   clear_error();
-  cabcd_status e = check_dense(XT, "XT");
+  Mat M;
+  cabcd_status e = check_matrix(XT, "XT", &M);
   if (e != CABCD_OK) return e;
-  e = check_common(XT, lambda, b, s, H, XT->rows);
+  if (M.lowp()) {
+    set_error("cabcd_dual_bcd: low-precision storage is supported by the primal only");
+    return CABCD_EUNSUPPORTED;
+  }
+  e = check_common(M, lambda, b, s, H);
   if (e != CABCD_OK) return e;
-  return run_bcd(true, XT, y, lambda, b, s, H, seed, alpha, w, opts, (hipStream_t)stream);
+  return run_bcd(true, M, y, lambda, b, s, H, seed, alpha, w, opts, (hipStream_t)stream);
 }
 
 cabcd_status cabcd_primal_objective(const cabcd_matrix* X, const double* y, double lambda,
                                     const double* w, double* r, double* f, void* stream) {
   clear_error();
-  cabcd_status e = check_dense(X, "X");
+  Mat M;
+  cabcd_status e = check_matrix(X, "X", &M);
   if (e != CABCD_OK) return e;
   if (y == nullptr || w == nullptr || !(lambda >= 0.0)) {
     set_error("cabcd_primal_objective: y and w must be non-NULL and lambda >= 0");
     return CABCD_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
-  Carve probe{nullptr};
-  double* rt = probe.take<double>(X->cols);
-  double* sc = probe.take<double>(std::max<size_t>(gemv_t_scratch_doubles(X->rows, X->cols), 1));
-  double* ob = probe.take<double>(objective_scratch_doubles(0, 0));
-  void* ws = nullptr;
-  e = pool_get(probe.off + 256, &ws);
+  AuxBuffers B{};
+  e = aux_get(M, M.cols, B);
   if (e != CABCD_OK) return e;
-  Carve c{static_cast<char*>(ws)};
-  rt = c.take<double>(X->cols);
-  sc = c.take<double>(std::max<size_t>(gemv_t_scratch_doubles(X->rows, X->cols), 1));
-  ob = c.take<double>(objective_scratch_doubles(0, 0));
-  double* rr = r != nullptr ? r : rt;
-  const double* A = static_cast<const double*>(X->data);
-  HIP_TRY(launch_gemv_t(A, X->ld, X->cols, nullptr, X->rows, w, 1.0, y, -1.0, false, rr, sc, st));
+  e = check_csr_device(M, B.flag, st);
+  if (e != CABCD_OK) return e;
+  double* rr = r != nullptr ? r : B.r;
+  HIP_TRY(mat_scatter(M, nullptr, M.rows, w, 1.0, y, -1.0, false, rr, B.scratch, st));
   if (f != nullptr)
-    HIP_TRY(launch_objective(rr, X->cols, 0.5 / (double)X->cols, w, X->rows, 0.5 * lambda, f, ob,
+    HIP_TRY(launch_objective(rr, M.cols, 0.5 / (double)M.cols, w, M.rows, 0.5 * lambda, f, B.obj,
                              nullptr, st));
   HIP_TRY(hipStreamSynchronize(st));
   return CABCD_OK;
@@ -577,28 +695,28 @@ cabcd_status cabcd_primal_objective(const cabcd_matrix* X, const double* y, doub
 cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y, double lambda,
                                       const double* w, double* r, double* f, void* stream) {
   clear_error();
-  cabcd_status e = check_dense(XT, "XT");
+  Mat M;
+  cabcd_status e = check_matrix(XT, "XT", &M);
   if (e != CABCD_OK) return e;
+  if (M.lowp()) {
+    set_error("cabcd_primal_objective_t: low-precision storage is not supported");
+    return CABCD_EUNSUPPORTED;
+  }
   if (y == nullptr || w == nullptr || !(lambda >= 0.0)) {
     set_error("cabcd_primal_objective_t: y and w must be non-NULL and lambda >= 0");
     return CABCD_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
-  Carve probe{nullptr};
-  probe.take<double>(XT->rows);
-  probe.take<double>(objective_scratch_doubles(0, 0));
-  void* ws = nullptr;
-  e = pool_get(probe.off + 256, &ws);
+  AuxBuffers B{};
+  e = aux_get(M, M.rows, B);
   if (e != CABCD_OK) return e;
-  Carve c{static_cast<char*>(ws)};
-  double* rt = c.take<double>(XT->rows);
-  double* ob = c.take<double>(objective_scratch_doubles(0, 0));
-  double* rr = r != nullptr ? r : rt;
-  const double* A = static_cast<const double*>(XT->data);
-  HIP_TRY(launch_gemv_n(A, XT->ld, XT->rows, XT->cols, w, y, -1.0, rr, st));
+  e = check_csr_device(M, B.flag, st);
+  if (e != CABCD_OK) return e;
+  double* rr = r != nullptr ? r : B.r;
+  HIP_TRY(mat_rowdot(M, w, y, -1.0, rr, st));
   if (f != nullptr)
-    HIP_TRY(launch_objective(rr, XT->rows, 0.5 / (double)XT->rows, w, XT->cols, 0.5 * lambda, f,
-                             ob, nullptr, st));
+    HIP_TRY(launch_objective(rr, M.rows, 0.5 / (double)M.rows, w, M.cols, 0.5 * lambda, f, B.obj,
+                             nullptr, st));
   HIP_TRY(hipStreamSynchronize(st));
   return CABCD_OK;
 }
@@ -606,31 +724,60 @@ cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y, d
 cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha, double lambda,
                                   double* w, void* stream) {
   clear_error();
-  cabcd_status e = check_dense(XT, "XT");
+  Mat M;
+  cabcd_status e = check_matrix(XT, "XT", &M);
   if (e != CABCD_OK) return e;
+  if (M.lowp()) {
+    set_error("cabcd_dual_to_primal: low-precision storage is not supported");
+    return CABCD_EUNSUPPORTED;
+  }
   if (alpha == nullptr || w == nullptr || !(lambda > 0.0)) {
     set_error("cabcd_dual_to_primal: alpha and w must be non-NULL and lambda > 0");
     return CABCD_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
-  void* ws = nullptr;
-  e = pool_get(std::max<size_t>(gemv_t_scratch_doubles(XT->rows, XT->cols), 1) * sizeof(double),
-               &ws);
+  AuxBuffers B{};
+  e = aux_get(M, 1, B);
   if (e != CABCD_OK) return e;
-  const double n = (double)XT->rows;
-  HIP_TRY(launch_gemv_t(static_cast<const double*>(XT->data), XT->ld, XT->cols, nullptr,
-                        XT->rows, alpha, -1.0 / (lambda * n), nullptr, 0.0, false, w,
-                        static_cast<double*>(ws), st));
+  e = check_csr_device(M, B.flag, st);
+  if (e != CABCD_OK) return e;
+  const double n = (double)M.rows;
+  HIP_TRY(mat_scatter(M, nullptr, M.rows, alpha, -1.0 / (lambda * n), nullptr, 0.0, false, w,
+                      B.scratch, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return CABCD_OK;
+}
+
+cabcd_status cabcd_quantize(const double* A, int64_t rows, int64_t cols, int64_t lda,
+                            int32_t dtype, void* Q, int64_t ldq, float* row_scale,
+                            void* stream) {
+  clear_error();
+  if (A == nullptr || Q == nullptr || rows < 1 || cols < 1 || lda < cols || ldq < cols) {
+    set_error("cabcd_quantize: need non-NULL A and Q, rows, cols >= 1, lda and ldq >= cols");
+    return CABCD_EINVAL;
+  }
+  if (dtype != CABCD_BF16 && dtype != CABCD_FP8_E4M3) {
+    set_error("cabcd_quantize: dtype must be CABCD_BF16 or CABCD_FP8_E4M3");
+    return CABCD_EINVAL;
+  }
+  if (dtype == CABCD_FP8_E4M3 && row_scale == nullptr) {
+    set_error("cabcd_quantize: FP8 storage needs row_scale");
+    return CABCD_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_quantize(A, rows, cols, lda, dtype, Q, ldq, row_scale, st));
   HIP_TRY(hipStreamSynchronize(st));
   return CABCD_OK;
 }
 
 size_t cabcd_workspace_bytes(const cabcd_matrix* A, int32_t b, int32_t s) {
-  if (A == nullptr || b < 1 || s < 1 || (int64_t)s * b > kMaxSB) return 0;
+  clear_error();
+  Mat M;
+  if (check_matrix(A, "A", &M) != CABCD_OK) return 0;
+  if (b < 1 || s < 1 || (int64_t)s * b > max_rows_per_gram(M)) return 0;
   StepBuffers B{};
   Carve probe{nullptr};
-  const int64_t rt = std::max(A->rows, A->cols);
-  return layout(probe, B, A->rows, A->cols, b, s, rt);
+  return layout(probe, B, M, b, s, std::max(A->rows, A->cols));
 }
 
 }  // extern "C"

@@ -1,0 +1,216 @@
+// CSR kernels: the sparse s-step Gram (row-gather SpGEMM), the companion
+// scatter updates and the row products, for A stored as CSR with FP64 values.
+//
+// The paper stores X in CSR and forms the Gram with sparse BLAS on each rank
+// (Section 5.2); the b x n sampled matrix has b f n non-zeros (Thm. bcd1dcol
+// proof).  Here one workgroup owns one gathered row p: it loads the row into an
+// LDS hash table (column -> value), and its waves take the rows q <= p, probe
+// the table with q's entries and reduce the products with a fixed shuffle tree,
+// giving G[p][q] directly (no partials, deterministic).  Rows longer than the
+// table are processed in table-sized chunks whose dot products are added in
+// chunk order.  Y u is the same pass with u gathered at the row's columns.
+//
+// The companion updates (primal r += Y^T delta, dual w -= Y^T delta/(lambda n))
+// and the exact recomputations scatter into the columns of the gathered rows;
+// columns shared by several rows (popular features) meet in FP64 atomic adds,
+// so these results are reproducible up to the order of those additions.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace cabcd {
+namespace {
+
+constexpr int kCsrThreads = 256;
+constexpr int kCsrWaves = kCsrThreads / 64;
+constexpr int kHashSlots = 4096;            // power of two
+constexpr int kChunk = kHashSlots / 2;      // row entries per table fill
+constexpr int kMaxBatches = 4;              // m <= 4 * 64 * kCsrWaves = 1024
+
+__device__ __forceinline__ unsigned hash_col(int c) {
+  return ((unsigned)c * 2654435761u) >> (32 - 12);   // log2(kHashSlots) = 12
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kCsrThreads) void csr_gram_kernel(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ vals, const int32_t* __restrict__ idx, int m,
+    const double* __restrict__ u, double scale, double shift, int overlap,
+    double* __restrict__ G, double* __restrict__ Yu) {
+  __shared__ int keys[kHashSlots];
+  __shared__ double hv[kHashSlots];
+  const int p = m - 1 - (int)blockIdx.x;   // the longest triangles start first
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int ip = idx[p];
+  const int64_t p0 = rowptr[ip], p1 = rowptr[ip + 1];
+
+  if (Yu != nullptr && wave == 0) {
+    double t = 0.0;
+    for (int64_t k = p0 + lane; k < p1; k += 64) t = fma(vals[k], u[colidx[k]], t);
+    t = wave_sum(t);
+    if (lane == 0) Yu[p] = t;
+  }
+
+  // Row q = qb + wave + W*lane of batch qb = 256*bi is summed in mine[bi] of
+  // that lane; rows are handled in batches of 64*W = 256 (m <= 1024 gives at
+  // most kMaxBatches).  The table of row p is filled once per chunk of row p,
+  // and the chunk results are added in chunk order.
+  double mine[kMaxBatches];
+#pragma unroll
+  for (int bi = 0; bi < kMaxBatches; ++bi) mine[bi] = 0.0;
+  for (int64_t c0 = p0;; c0 += kChunk) {
+    const int64_t c1 = std::min(p1, c0 + kChunk);
+    for (int s = threadIdx.x; s < kHashSlots; s += kCsrThreads) keys[s] = -1;
+    __syncthreads();
+    for (int64_t k = c0 + threadIdx.x; k < c1; k += kCsrThreads) {
+      const int col = colidx[k];
+      unsigned h = hash_col(col);
+      while (atomicCAS(&keys[h], -1, col) != -1) h = (h + 1) & (kHashSlots - 1);
+      hv[h] = vals[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < kMaxBatches; ++bi) {
+      const int qb = bi * 64 * kCsrWaves;
+      for (int j = 0; j < 64; ++j) {
+        const int q = qb + wave + kCsrWaves * j;
+        if (q > p) break;
+        const int iq = idx[q];
+        const int64_t q0 = rowptr[iq], q1 = rowptr[iq + 1];
+        double t = 0.0;
+        for (int64_t k = q0 + lane; k < q1; k += 64) {
+          const int col = colidx[k];
+          unsigned h = hash_col(col);
+          int key;
+          while ((key = keys[h]) != col && key != -1) h = (h + 1) & (kHashSlots - 1);
+          if (key == col) t = fma(vals[k], hv[h], t);
+        }
+        t = wave_sum(t);
+        if (lane == j) mine[bi] += t;
+      }
+    }
+    __syncthreads();
+    if (c1 >= p1) break;
+  }
+#pragma unroll
+  for (int bi = 0; bi < kMaxBatches; ++bi) {
+    const int q = bi * 64 * kCsrWaves + wave + kCsrWaves * lane;
+    if (q <= p) {
+      const bool on = overlap ? (idx[q] == ip) : (q == p);
+      const double v = scale * mine[bi] + (on ? shift : 0.0);
+      G[(int64_t)p * m + q] = v;
+      G[(int64_t)q * m + p] = v;
+    }
+  }
+}
+
+// out[col] += gamma * v[p] * A[row(p)][col] for the entries of rows p < m.
+__global__ __launch_bounds__(kCsrThreads) void csr_scatter_kernel(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ vals, const int32_t* __restrict__ idx, int64_t m,
+    const double* __restrict__ v, double gamma, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * kCsrWaves + (threadIdx.x >> 6);
+  if (p >= m) return;
+  const int64_t row = idx ? (int64_t)idx[p] : p;
+  const double c = gamma * v[p];
+  if (c == 0.0) return;
+  for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64)
+    unsafeAtomicAdd(out + colidx[k], c * vals[k]);   // coarse-grained memory: hardware FP64 add
+}
+
+// out[p] = A[p] . v + beta * base[p]
+__global__ __launch_bounds__(kCsrThreads) void csr_rowdot_kernel(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ vals, int64_t rows, const double* __restrict__ v,
+    const double* __restrict__ base, double beta, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * kCsrWaves + (threadIdx.x >> 6);
+  if (p >= rows) return;
+  double t = 0.0;
+  for (int64_t k = rowptr[p] + lane; k < rowptr[p + 1]; k += 64) t = fma(vals[k], v[colidx[k]], t);
+  t = wave_sum(t);
+  if (lane == 0) out[p] = t + (base ? beta * base[p] : 0.0);
+}
+
+__global__ void fill_kernel(double* __restrict__ out, int64_t n, const double* __restrict__ base,
+                            double beta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = base ? beta * base[i] : 0.0;
+}
+
+// Structure check: rowptr[0] = 0, non-decreasing, rowptr[rows] = nnz; columns
+// strictly increasing inside a row and in [0, cols).  Any violation sets *bad.
+__global__ void csr_check_kernel(const int64_t* __restrict__ rowptr,
+                                 const int32_t* __restrict__ colidx, int64_t rows, int64_t cols,
+                                 int64_t nnz, int* __restrict__ bad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > rows) return;
+  const int64_t a = rowptr[r];
+  if (r == 0 && a != 0) *bad = 1;
+  if (r == rows) {
+    if (a != nnz) *bad = 1;
+    return;
+  }
+  const int64_t e = rowptr[r + 1];
+  if (e < a || e > nnz || a < 0) {
+    *bad = 1;
+    return;
+  }
+  int prev = -1;
+  for (int64_t k = a; k < e; ++k) {
+    const int c = colidx[k];
+    if (c <= prev || c >= cols) {
+      *bad = 1;
+      return;
+    }
+    prev = c;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_csr_gram(const CsrView& A, const int32_t* idx, int m, const double* u,
+                           double scale, double shift, bool overlap, double* G, double* Yu,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(csr_gram_kernel, dim3(m), dim3(kCsrThreads), 0, st, A.rowptr, A.colidx,
+                     A.vals, idx, m, u, scale, shift, overlap ? 1 : 0, G, Yu);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_scatter(const CsrView& A, const int32_t* idx, int64_t m, const double* v,
+                              double gamma, double* out, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(csr_scatter_kernel, dim3((unsigned)((m + kCsrWaves - 1) / kCsrWaves)),
+                     dim3(kCsrThreads), 0, st, A.rowptr, A.colidx, A.vals, idx, m, v, gamma, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_rowdot(const CsrView& A, const double* v, const double* base, double beta,
+                             double* out, hipStream_t st) {
+  if (A.rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(csr_rowdot_kernel, dim3((unsigned)((A.rows + kCsrWaves - 1) / kCsrWaves)),
+                     dim3(kCsrThreads), 0, st, A.rowptr, A.colidx, A.vals, A.rows, v, base, beta,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* out, int64_t n, const double* base, double beta, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, n,
+                     base, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_check(const CsrView& A, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(csr_check_kernel, dim3((unsigned)((A.rows + 1 + 255) / 256)), dim3(256), 0,
+                     st, A.rowptr, A.colidx, A.rows, A.cols, A.nnz, bad);
+  return hipGetLastError();
+}
+
+}  // namespace cabcd

@@ -28,55 +28,81 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 namespace cabcd {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 512;   // 8 waves
-
-template <int NB>
+// Wave layouts.  RPW = block rows owned by one wave: 2 (rows r and NB-1-r, 8
+// waves, two per SIMD) or 4 (rows r, NB-1-r, NB/2-1-r, NB/2+r, 4 waves, one
+// per SIMD with the accumulators in AGPRs).  Either way every wave owns
+// the same number of lower blocks.  Waves that own the same rows (KG > 1, small
+// NB) split the k-steps of a tile instead.
+template <int NB, int RPW>
 struct Cfg {
-  static constexpr int SBP = 16 * NB;                 // padded rows
-  static constexpr int NBLK = NB * (NB + 1) / 2;      // lower 16x16 blocks
-  static constexpr int KT = 256 / NB;                 // tile width: SBP*KT = 4096
-  static constexpr int RS = KT + 2;                   // LDS row stride (doubles)
-  static constexpr int CH = KT / 2;                   // 16-byte chunks per row
-  static constexpr int NCH = SBP * CH / kThreads;     // chunks per thread (= 4)
-  static constexpr int BW = NB >= 2 ? NB / 2 : 1;     // waves sharing the blocks
-  static constexpr int KG = 8 / BW;                   // waves splitting the k-steps
-  static constexpr int PAIRS = KT / 8;                // 128-bit fragment reads per tile
-  static constexpr int NACC = NB >= 2 ? NB + 1 : 1;   // accumulators per wave
+  static constexpr int SBP = 16 * NB;                       // padded rows
+  static constexpr int NBLK = NB * (NB + 1) / 2;            // lower 16x16 blocks
+  static constexpr int KT = 256 / NB;                       // tile width: SBP*KT = 4096
+  static constexpr int RS = KT + 2;                         // LDS row stride (doubles)
+  static constexpr int CH = KT / 2;                         // 16-byte chunks per row
+  static constexpr int R = NB >= RPW ? RPW : 1;             // rows per wave
+  static constexpr int BW = NB >= RPW ? NB / RPW : 1;       // waves splitting the blocks
+  static constexpr int WAVES = RPW == 2 ? 8 : 4;
+  static constexpr int KG = WAVES / BW;                     // waves splitting the k-steps
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int NCH = SBP * CH / THREADS;            // chunks per thread per tile
+  static constexpr int PAIRS = KT / 8;                      // 128-bit fragment reads per tile
+  static constexpr int NACC = NB >= RPW ? NBLK / BW : 1;    // accumulators per wave
   static constexpr int TILE = SBP * RS;
   static constexpr int RED = (KG - 1) * NBLK * 256;
   static constexpr int YUS = SBP * CH;
   static constexpr int LDS = std::max(std::max(2 * TILE, RED), YUS);
-  static_assert(NCH * kThreads == SBP * CH, "tile must split evenly");
+  static_assert(NCH * THREADS == SBP * CH, "tile must split evenly");
   static_assert(PAIRS % KG == 0, "k-steps must split evenly");
+  static_assert(NB < RPW || NACC * BW == NBLK, "blocks must split evenly");
 };
 
 // Index of lower block (r, c) in row-major lower-triangular order.
 __host__ __device__ constexpr int blk_index(int r, int c) { return r * (r + 1) / 2 + c; }
 
-// Block index of accumulator a of the wave that owns block rows bw and NB-1-bw.
-template <int NB>
+// i-th block row owned by wave w.
+__host__ __device__ constexpr int owned_row(int NB, int RPW, int w, int i) {
+  if (NB < RPW) return NB == 1 ? 0 : (i == 0 ? 0 : 1);
+  const int pair = RPW == 2 ? w : (i < 2 ? w : NB / 2 - 1 - w);
+  return (i % 2 == 0) ? pair : NB - 1 - pair;
+}
+
+// First accumulator of owned row i (accumulators of row r are its r+1 blocks).
+__host__ __device__ constexpr int acc_offset(int NB, int RPW, int w, int i) {
+  int off = 0;
+  for (int k = 0; k < i; ++k) off += owned_row(NB, RPW, w, k) + 1;
+  return off;
+}
+
+// Block index of accumulator a of wave bw.
+template <int NB, int RPW>
 __device__ __forceinline__ int acc_block(int bw, int a) {
-  if (NB == 1) return 0;
-  const int r1 = bw, r2 = NB - 1 - bw;
-  return a <= r1 ? blk_index(r1, a) : blk_index(r2, a - r1 - 1);
+  using C = Cfg<NB, RPW>;
+  if (NB < RPW) return a;   // the whole (tiny) triangle, in row-major order
+  for (int i = 0; i < C::R; ++i) {
+    const int r = owned_row(NB, RPW, bw, i);
+    if (a <= r) return blk_index(r, a);
+    a -= r + 1;
+  }
+  return 0;
 }
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int NB, int W>
+template <int NB, int RPW, int W>
 __device__ __forceinline__ void mma_tile(const double* __restrict__ tile, int lane, int kg,
-                                         d4 (&acc)[Cfg<NB>::NACC]) {
-  using C = Cfg<NB>;
-  constexpr int R1 = NB >= 2 ? W : 0;
-  constexpr int R2 = NB >= 2 ? NB - 1 - W : 0;
+                                         d4 (&acc)[Cfg<NB, RPW>::NACC]) {
+  using C = Cfg<NB, RPW>;
+  constexpr int NR = NB >= RPW ? C::R : (NB == 1 ? 1 : 2);
   const double* base = tile + (lane & 15) * C::RS + 2 * (lane >> 4);
 #pragma unroll
   for (int p = 0; p < C::PAIRS / C::KG; ++p) {
@@ -84,33 +110,44 @@ __device__ __forceinline__ void mma_tile(const double* __restrict__ tile, int la
     auto frag = [&](int r) {
       return *reinterpret_cast<const double2*>(base + r * 16 * C::RS + col);
     };
-    // The wave's two block rows stay in registers; the column fragments are
-    // streamed, so at most a few fragments are live next to the accumulators.
-    const double2 f1 = frag(R1);
-    const double2 f2 = NB >= 2 ? frag(R2) : f1;
+    // The wave's own block rows stay in registers; the column fragments are
+    // streamed so only a few are live next to the accumulators.
+    double2 fo[NR];
 #pragma unroll
-    for (int c = 0; c <= R2; ++c) {
-      const double2 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-      if (c <= R1) {
-        acc[c] = mfma(f1.x, fc.x, acc[c]);
-        acc[c] = mfma(f1.y, fc.y, acc[c]);
-      }
-      if constexpr (NB >= 2) {
-        acc[R1 + 1 + c] = mfma(f2.x, fc.x, acc[R1 + 1 + c]);
-        acc[R1 + 1 + c] = mfma(f2.y, fc.y, acc[R1 + 1 + c]);
+    for (int i = 0; i < NR; ++i) fo[i] = frag(owned_row(NB, RPW, W, i));
+    constexpr int CMAX = NB >= RPW ? NB - 1 - W : NB - 1;   // largest owned row
+#pragma unroll
+    for (int c = 0; c <= CMAX; ++c) {
+      double2 fc = {0.0, 0.0};
+      bool own = false;
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+        if (owned_row(NB, RPW, W, i) == c) {
+          fc = fo[i];
+          own = true;
+        }
+      if (!own) fc = frag(c);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int r = owned_row(NB, RPW, W, i);
+        if (c <= r) {
+          const int a = acc_offset(NB, RPW, W, i) + c;
+          acc[a] = mfma(fo[i].x, fc.x, acc[a]);
+          acc[a] = mfma(fo[i].y, fc.y, acc[a]);
+        }
       }
     }
   }
 }
 
-template <int NB, int W = 0>
+template <int NB, int RPW, int W = 0>
 __device__ __forceinline__ void mma_dispatch(int bw, const double* __restrict__ tile, int lane,
-                                             int kg, d4 (&acc)[Cfg<NB>::NACC]) {
-  if constexpr (W < Cfg<NB>::BW) {
+                                             int kg, d4 (&acc)[Cfg<NB, RPW>::NACC]) {
+  if constexpr (W < Cfg<NB, RPW>::BW) {
     if (bw == W)
-      mma_tile<NB, W>(tile, lane, kg, acc);
+      mma_tile<NB, RPW, W>(tile, lane, kg, acc);
     else
-      mma_dispatch<NB, W + 1>(bw, tile, lane, kg, acc);
+      mma_dispatch<NB, RPW, W + 1>(bw, tile, lane, kg, acc);
   }
 }
 
@@ -131,12 +168,12 @@ __device__ __forceinline__ double2 load2(const double* __restrict__ p, int64_t k
   return v;
 }
 
-template <int NB>
-__global__ __launch_bounds__(kThreads) void gram_f64_kernel(
+template <int NB, int RPW>
+__global__ __launch_bounds__((Cfg<NB, RPW>::THREADS)) void gram_f64_kernel(
     const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
     int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
     int aligned) {
-  using C = Cfg<NB>;
+  using C = Cfg<NB, RPW>;
   __shared__ __attribute__((aligned(16))) double lds[C::LDS];
 
   const int tid = threadIdx.x;
@@ -153,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void gram_f64_kernel(
   const double* rowp[C::NCH];
 #pragma unroll
   for (int i = 0; i < C::NCH; ++i) {
-    rho[i] = tid / C::CH + (kThreads / C::CH) * i;
+    rho[i] = tid / C::CH + (C::THREADS / C::CH) * i;
     rowp[i] = rho[i] < m ? A + (int64_t)idx[rho[i]] * ld : nullptr;
   }
   const bool want_u = u != nullptr;
@@ -198,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void gram_f64_kernel(
   for (int t = 0; t < ntiles; ++t) {
     const bool more = t + 1 < ntiles;
     if (more) load_tile(t + 1);
-    mma_dispatch<NB>(bw, lds + (t & 1) * C::TILE, lane, kg, acc);
+    mma_dispatch<NB, RPW>(bw, lds + (t & 1) * C::TILE, lane, kg, acc);
     if (more) store_tile((t + 1) & 1);
     __syncthreads();
   }
@@ -210,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void gram_f64_kernel(
     if (kg > 0) {
 #pragma unroll
       for (int a = 0; a < C::NACC; ++a) {
-        double* dst = lds + ((kg - 1) * C::NBLK + acc_block<NB>(bw, a)) * 256 + lane;
+        double* dst = lds + ((kg - 1) * C::NBLK + acc_block<NB, RPW>(bw, a)) * 256 + lane;
         dst[0] = acc[a][0];
         dst[64] = acc[a][1];
         dst[128] = acc[a][2];
@@ -222,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void gram_f64_kernel(
       for (int g = 1; g < C::KG; ++g) {
 #pragma unroll
         for (int a = 0; a < C::NACC; ++a) {
-          const double* src = lds + ((g - 1) * C::NBLK + acc_block<NB>(bw, a)) * 256 + lane;
+          const double* src = lds + ((g - 1) * C::NBLK + acc_block<NB, RPW>(bw, a)) * 256 + lane;
           acc[a][0] += src[0];
           acc[a][1] += src[64];
           acc[a][2] += src[128];
@@ -234,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void gram_f64_kernel(
   if (kg == 0) {
 #pragma unroll
     for (int a = 0; a < C::NACC; ++a) {
-      double* dst = part + acc_block<NB>(bw, a) * 256 + lane;
+      double* dst = part + acc_block<NB, RPW>(bw, a) * 256 + lane;
       dst[0] = acc[a][0];
       dst[64] = acc[a][1];
       dst[128] = acc[a][2];
@@ -256,48 +293,76 @@ __global__ __launch_bounds__(kThreads) void gram_f64_kernel(
 }
 
 // Element e of a partial block (lane-major: e = item*64 + lane) sits at
-// row 4*item + lane/16, column lane%16 of its 16x16 block: the output layout
-// of v_mfma_f64_16x16x4_f64 on gfx950 (checked on the hardware with a probe of
-// known integer matrices).
-__global__ void gram_reduce_kernel(const double* __restrict__ partials, int nsplit, int nb,
-                                   const int32_t* __restrict__ idx, int m, double scale,
-                                   double shift, int overlap, double* __restrict__ G,
-                                   double* __restrict__ Yu) {
+// column lane%16 of its 16x16 block and row 4*item + lane/16 (layout 0: the
+// output order of v_mfma_f64_16x16x4_f64 on gfx950) or 4*(lane/16) + item
+// (layout 1: the FP32-output MFMAs).  Both were checked on the hardware with
+// probes of known integer matrices.
+constexpr int kRedElems = 64;    // partial entries per reduction workgroup
+constexpr int kRedGroups = 4;    // split groups per entry (one wave each)
+
+__global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
+    const double* __restrict__ partials, int nsplit, int nb, const int32_t* __restrict__ idx,
+    int m, double scale, double shift, int overlap, double* __restrict__ G,
+    double* __restrict__ Yu, int layout, const float* __restrict__ rs) {
+  __shared__ double red[kRedGroups][kRedElems];
   const int nblk = nb * (nb + 1) / 2;
   const int64_t pstride = (int64_t)nblk * 256 + 16 * nb;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nblk * 256) {
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += partials[sp * pstride + e];
-    const int q = e >> 8;
-    int r = 0;
-    while (blk_index(r + 1, 0) <= q) ++r;
-    const int cb = q - blk_index(r, 0);
-    const int item = (e >> 6) & 3;
-    const int lane = e & 63;
-    const int row = 16 * r + 4 * item + (lane >> 4);
-    const int col = 16 * cb + (lane & 15);
-    if (row < m && col < m && (r != cb || row >= col)) {
-      const bool on = overlap ? (idx[row] == idx[col]) : (row == col);
-      const double v = scale * s + (on ? shift : 0.0);
-      G[(int64_t)row * m + col] = v;
-      G[(int64_t)col * m + row] = v;
+  const int el = threadIdx.x % kRedElems;
+  const int grp = threadIdx.x / kRedElems;
+  const int64_t e = (int64_t)blockIdx.x * kRedElems + el;
+  // Each wave sums a contiguous range of splits for 64 consecutive entries;
+  // the ranges are then added in group order, so the result is deterministic.
+  const int per = (nsplit + kRedGroups - 1) / kRedGroups;
+  const int sp0 = grp * per;
+  const int sp1 = min(nsplit, sp0 + per);
+  double s = 0.0;
+  if (e < pstride) {
+    const double* p = partials + e;
+    int sp = sp0;
+    for (; sp + 8 <= sp1; sp += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[(int64_t)(sp + q) * pstride];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
     }
+    for (; sp < sp1; ++sp) s += p[(int64_t)sp * pstride];
   }
-  if (Yu != nullptr && e < m) {
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += partials[sp * pstride + nblk * 256 + e];
-    Yu[e] = s;
+  red[grp][el] = s;
+  __syncthreads();
+  if (grp != 0 || e >= pstride) return;
+  double t = red[0][el];
+#pragma unroll
+  for (int g = 1; g < kRedGroups; ++g) t += red[g][el];
+  if (e >= (int64_t)nblk * 256) {          // the Y u entries follow the blocks
+    const int p = (int)(e - (int64_t)nblk * 256);
+    if (Yu != nullptr && p < m) Yu[p] = rs ? (double)rs[idx[p]] * t : t;
+    return;
+  }
+  const int q = (int)(e >> 8);
+  int r = 0;
+  while (blk_index(r + 1, 0) <= q) ++r;
+  const int cb = q - blk_index(r, 0);
+  const int item = (int)(e >> 6) & 3;
+  const int lane = (int)e & 63;
+  const int row = 16 * r + (layout == 0 ? 4 * item + (lane >> 4) : 4 * (lane >> 4) + item);
+  const int col = 16 * cb + (lane & 15);
+  if (row < m && col < m && (r != cb || row >= col)) {
+    const bool on = overlap ? (idx[row] == idx[col]) : (row == col);
+    const double sc = rs ? scale * (double)rs[idx[row]] * (double)rs[idx[col]] : scale;
+    const double v = sc * t + (on ? shift : 0.0);
+    G[(int64_t)row * m + col] = v;
+    G[(int64_t)col * m + row] = v;
   }
 }
 
-template <int NB>
+template <int NB, int RPW>
 hipError_t launch_nb(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
                      const int32_t* idx, int m, const double* u, double* partials,
                      hipStream_t st) {
   const int aligned = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (ld & 1) == 0) ? 1 : 0;
-  hipLaunchKernelGGL(gram_f64_kernel<NB>, dim3(p.nsplit), dim3(kThreads), 0, st, A, ld, cols,
-                     idx, m, u, p.chunk, partials, aligned);
+  hipLaunchKernelGGL((gram_f64_kernel<NB, RPW>), dim3(p.nsplit), dim3(Cfg<NB, RPW>::THREADS), 0,
+                     st, A, ld, cols, idx, m, u, p.chunk, partials, aligned);
   return hipGetLastError();
 }
 
@@ -349,6 +414,10 @@ GramPlan plan_gram_f64(int m, int64_t cols) {
   }
   p.chunk = best_chunk;
   p.nsplit = (int)((cols + best_chunk - 1) / best_chunk);
+  // Eight waves with two block rows each.  Four waves with four rows each (one
+  // wave per SIMD, accumulators in AGPRs) measured slower at nb = 8 (30.9 vs
+  // 38.3 TFLOP/s) and does not fit the registers at nb = 16.
+  p.rpw = 2;
   return p;
 }
 
@@ -360,22 +429,23 @@ hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64
                            const int32_t* idx, int m, const double* u, double* partials,
                            hipStream_t st) {
   switch (p.nb) {
-    case 1: return launch_nb<1>(p, A, ld, cols, idx, m, u, partials, st);
-    case 2: return launch_nb<2>(p, A, ld, cols, idx, m, u, partials, st);
-    case 4: return launch_nb<4>(p, A, ld, cols, idx, m, u, partials, st);
-    case 8: return launch_nb<8>(p, A, ld, cols, idx, m, u, partials, st);
-    case 16: return launch_nb<16>(p, A, ld, cols, idx, m, u, partials, st);
+    case 1: return launch_nb<1, 2>(p, A, ld, cols, idx, m, u, partials, st);
+    case 2: return launch_nb<2, 2>(p, A, ld, cols, idx, m, u, partials, st);
+    case 4: return launch_nb<4, 2>(p, A, ld, cols, idx, m, u, partials, st);
+    case 8: return launch_nb<8, 2>(p, A, ld, cols, idx, m, u, partials, st);
+    case 16: return launch_nb<16, 2>(p, A, ld, cols, idx, m, u, partials, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const int32_t* idx,
                               int m, double scale, double shift, bool overlap, double* G,
-                              double* Yu, hipStream_t st) {
-  const int n = std::max(p.nblk * 256, m);
-  const int threads = 256;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((n + threads - 1) / threads), dim3(threads), 0, st,
-                     partials, p.nsplit, p.nb, idx, m, scale, shift, overlap ? 1 : 0, G, Yu);
+                              double* Yu, hipStream_t st, int layout, const float* rs) {
+  const int64_t entries = (int64_t)p.nblk * 256 + 16 * p.nb;
+  const int64_t blocks = (entries + kRedElems - 1) / kRedElems;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks), dim3(kRedElems * kRedGroups), 0,
+                     st, partials, p.nsplit, p.nb, idx, m, scale, shift, overlap ? 1 : 0, G, Yu,
+                     layout, rs);
   return hipGetLastError();
 }
 

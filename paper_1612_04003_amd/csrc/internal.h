@@ -11,6 +11,25 @@
 
 namespace cabcd {
 
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also waits
+// for every outstanding global load of the wave, which would drain register
+// prefetches issued ahead of the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Exact decoding of the low-precision storage formats to FP64.
+__device__ __forceinline__ double decode_bf16(uint32_t b) {
+  return (double)__uint_as_float((b & 0xFFFFu) << 16);
+}
+__device__ __forceinline__ double decode_e4m3(uint32_t b) {
+  const uint32_t E = (b >> 3) & 15u, M = b & 7u;
+  const double v = E == 0 ? (double)M * 0x1p-9 : ldexp((double)(8u + M), (int)E - 10);
+  return (b & 0x80u) ? -v : v;
+}
+
 // ------------------------------------------------------------------ errors
 void set_error(const char* fmt, ...);
 void clear_error();
@@ -30,6 +49,7 @@ struct GramPlan {
   int kt;          // columns per LDS tile
   int64_t chunk;   // columns per workgroup (multiple of kt)
   int nsplit;      // workgroups along the reduction dimension
+  int rpw;         // block rows per wave (2: eight waves, 4: four waves)
 };
 GramPlan plan_gram_f64(int m, int64_t cols);
 size_t gram_partial_doubles(const GramPlan& p);   // partial G + partial Yu
@@ -40,9 +60,13 @@ hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64
 // G (m x m, ld m, both triangles) = scale * sum(partials) + shift * E,
 // E = I (overlap = false) or E_pq = [idx_p == idx_q] (overlap = true).
 // Yu (may be NULL) = sum of the partial Yu.
+// layout 0: partial block entries in the FP64 MFMA output order; 1: in the FP32
+// MFMA output order.  rs (may be NULL) are row scales of A applied as
+// rs[idx_p] rs[idx_q] to G and rs[idx_p] to Y u.
 hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const int32_t* idx,
                               int m, double scale, double shift, bool overlap, double* G,
-                              double* Yu, hipStream_t st);
+                              double* Yu, hipStream_t st, int layout = 0,
+                              const float* rs = nullptr);
 
 // ------------------------------------------------------------------ fused solve
 // One outer step's s block solves through the unrolled recurrence, followed by
@@ -62,7 +86,51 @@ struct SolveArgs {
   int mode;
   double lambda, n;
 };
+constexpr int kSolveMaxRows = 1024;
+constexpr int kSolveMaxB = 32;
+constexpr size_t kSolveMaxLds = 160 * 1024;
+size_t solve_lds_bytes(int m, int b);   // dynamic LDS of one solve launch
 hipError_t launch_solve(const SolveArgs& a, hipStream_t st);
+
+// ------------------------------------------------------------------ low precision
+// Codes of A (rows x cols, FP64, ld lda) into Q (ld ldq elements) with FP32
+// row scales (FP8: amax/448; BF16: 1, row_scale may be NULL).
+hipError_t launch_quantize(const double* A, int64_t rows, int64_t cols, int64_t lda, int dtype,
+                           void* Q, int64_t ldq, float* row_scale, hipStream_t st);
+GramPlan plan_gram_lp(int m, int64_t cols, int dtype);
+// Gram partials of stored codes (FP32 MFMA accumulation, FP64 partials; the
+// partial blocks use the FP32 MFMA output layout) plus Y u of the codes in FP64.
+hipError_t launch_gram_lp(const GramPlan& p, int dtype, const void* A, int64_t ld, int64_t cols,
+                          const int32_t* idx, int m, const double* u, double* partials,
+                          hipStream_t st);
+// out = [beta base | out] + gamma sum_p s[row(p)] v[p] decode(Q[row(p)]), FP64.
+hipError_t launch_gemv_t_lp(int dtype, const void* A, int64_t ld, int64_t cols, const float* rs,
+                            const int32_t* idx, int64_t m, const double* v, double gamma,
+                            const double* base, double beta, bool accumulate, double* out,
+                            hipStream_t st);
+
+// ------------------------------------------------------------------ CSR kernels
+struct CsrView {
+  const int64_t* rowptr;
+  const int32_t* colidx;
+  const double* vals;
+  int64_t rows, cols, nnz;
+};
+constexpr int kCsrMaxRows = 1024;   // gathered rows one CSR Gram launch handles
+// Gov (or plain G) and Y u of the rows idx[0..m) of a CSR matrix, m <= 1024.
+hipError_t launch_csr_gram(const CsrView& A, const int32_t* idx, int m, const double* u,
+                           double scale, double shift, bool overlap, double* G, double* Yu,
+                           hipStream_t st);
+// out[col] += gamma * v[p] * A[row(p)][col], row(p) = idx ? idx[p] : p (atomic adds).
+hipError_t launch_csr_scatter(const CsrView& A, const int32_t* idx, int64_t m, const double* v,
+                              double gamma, double* out, hipStream_t st);
+// out[p] = A[p] . v + beta * base[p] for every row.
+hipError_t launch_csr_rowdot(const CsrView& A, const double* v, const double* base, double beta,
+                             double* out, hipStream_t st);
+// out[i] = beta * base[i] (base may be NULL: zero).
+hipError_t launch_fill(double* out, int64_t n, const double* base, double beta, hipStream_t st);
+// Sets *bad (device int) if the CSR structure is malformed.
+hipError_t launch_csr_check(const CsrView& A, int* bad, hipStream_t st);
 
 // ------------------------------------------------------------------ vector kernels
 // out[k] = (accumulate ? out[k] : beta*base[k]) + gamma * sum_p A[row(p)][k] * v[p]

@@ -1,0 +1,449 @@
+// Low-precision storage of A for the mixed-precision path: quantisation,
+// decoding, and the FP64-accumulating streaming passes over BF16 / FP8 rows.
+//
+// Storage formats (rounding FP64 directly to nearest, ties to even):
+//   BF16      1 sign, 8 exponent (bias 127), 7 fraction bits; overflow -> inf.
+//   FP8 E4M3  OCP "fn" variant: 1 sign, 4 exponent (bias 7), 3 fraction bits,
+//             largest finite 448, no infinities; rounding saturates at +-448.
+//             Row i is stored as q = E4M3(x / s_i), s_i = fp32(amax_i / 448)
+//             (1 for an all-zero row), so the stored matrix is X^ = diag(s) Q.
+// The method then runs on X^ (exact in FP64): the Gram uses the stored codes on
+// the matrix cores with FP32 accumulation and applies s_p s_q in FP64, while
+// Y u, the companion updates and the exact recomputation decode to FP64.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace cabcd {
+namespace {
+
+constexpr int kQThreads = 256;
+
+// Nearest value on a grid with `mant` fraction bits and minimum normal
+// exponent `emin` (subnormal spacing below it), ties to even.
+__device__ __forceinline__ double round_grid(double v, int mant, int emin) {
+  if (v == 0.0) return v;
+  int ex;
+  (void)frexp(v, &ex);                 // |v| = f 2^ex, 0.5 <= f < 1
+  const int e = max(ex - 1, emin);
+  return ldexp(rint(ldexp(v, mant - e)), e - mant);
+}
+
+__device__ __forceinline__ uint16_t encode_bf16(double v) {
+  double q = round_grid(v, 7, -126);
+  const double mx = 0x1.fep127;       // (2 - 2^-7) 2^127
+  if (fabs(q) > mx) q = copysign(INFINITY, q);
+  const float f = (float)q;           // exact: BF16 values are FP32 values
+  return (uint16_t)(__float_as_uint(f) >> 16);
+}
+
+__device__ __forceinline__ uint8_t encode_e4m3(double v) {
+  double q = round_grid(v, 3, -6);
+  q = fmin(fmax(q, -448.0), 448.0);
+  const uint8_t sign = signbit(q) ? 0x80 : 0;
+  const double a = fabs(q);
+  if (a < 0x1p-6) return sign | (uint8_t)rint(a * 512.0);          // E = 0: a = M 2^-9
+  int ex;
+  const double f = frexp(a, &ex);                                    // a = f 2^ex
+  const int e = ex - 1;                                              // a = (2f) 2^e
+  const int frac = (int)rint((2.0 * f - 1.0) * 8.0);
+  return sign | (uint8_t)(((e + 7) << 3) | frac);
+}
+
+__global__ __launch_bounds__(kQThreads) void quantize_kernel(const double* __restrict__ A,
+                                                             int64_t cols, int64_t lda,
+                                                             int dtype, void* __restrict__ Q,
+                                                             int64_t ldq,
+                                                             float* __restrict__ row_scale) {
+  __shared__ double red[kQThreads];
+  const int64_t r = blockIdx.x;
+  const double* a = A + r * lda;
+  if (dtype == CABCD_BF16) {
+    uint16_t* q = static_cast<uint16_t*>(Q) + r * ldq;
+    for (int64_t k = threadIdx.x; k < cols; k += kQThreads) q[k] = encode_bf16(a[k]);
+    if (row_scale != nullptr && threadIdx.x == 0) row_scale[r] = 1.0f;
+    return;
+  }
+  double mx = 0.0;
+  for (int64_t k = threadIdx.x; k < cols; k += kQThreads) mx = fmax(mx, fabs(a[k]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = kQThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double amax = red[0];
+  const float s = amax == 0.0 ? 1.0f : (float)(amax / 448.0);
+  const double sd = (double)s;
+  uint8_t* q = static_cast<uint8_t*>(Q) + r * ldq;
+  for (int64_t k = threadIdx.x; k < cols; k += kQThreads) q[k] = encode_e4m3(a[k] / sd);
+  if (threadIdx.x == 0) row_scale[r] = s;
+}
+
+// ---------------------------------------------------------------- Gram
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kLpThreads = 512;   // 8 waves, two block rows each
+
+// FMT: CABCD_BF16 (2-byte elements, one MFMA per 16-byte fragment) or
+// CABCD_FP8_E4M3 (1-byte elements, two MFMAs per 16-byte fragment).
+template <int NB, int FMT>
+struct LpCfg {
+  static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;      // element bytes
+  static constexpr int SBP = 16 * NB;
+  static constexpr int NBLK = NB * (NB + 1) / 2;
+  static constexpr int RB = 2048 / NB;                      // tile row bytes: tile = 32 KiB
+  static constexpr int RSB = RB + 16;                       // LDS row stride in bytes
+  static constexpr int KT = RB / ES;                        // tile width in elements
+  static constexpr int EPC = 16 / ES;                       // elements per 16-byte chunk
+  static constexpr int CH = RB / 16;                        // chunks per row
+  static constexpr int NCH = SBP * CH / kLpThreads;         // chunks per thread (= 4)
+  static constexpr int WIN = RB / 64;                       // 64-byte windows per tile row
+  static constexpr int BW = NB >= 2 ? NB / 2 : 1;
+  static constexpr int KG = 8 / BW;
+  static constexpr int NACC = NB >= 2 ? NB + 1 : 1;
+  static constexpr int TILE = SBP * RSB;                    // bytes
+  static constexpr int RED = (KG - 1) * NBLK * 256 * 4;     // bytes (FP32 partial blocks)
+  static constexpr int YUS = SBP * CH * 8;                  // bytes
+  static constexpr int LDS = std::max(std::max(2 * TILE, RED), YUS);
+  static_assert(NCH * kLpThreads == SBP * CH, "tile must split evenly");
+  static_assert(WIN % KG == 0, "windows must split evenly");
+};
+
+__device__ __forceinline__ int lp_blk_index(int r, int c) { return r * (r + 1) / 2 + c; }
+
+template <int NB>
+__device__ __forceinline__ int lp_acc_block(int bw, int a) {
+  if (NB == 1) return 0;
+  const int r1 = bw, r2 = NB - 1 - bw;
+  return a <= r1 ? lp_blk_index(r1, a) : lp_blk_index(r2, a - r1 - 1);
+}
+
+template <int FMT>
+__device__ __forceinline__ f4 lp_mma(const uint4& a, const uint4& b, f4 c) {
+  if constexpr (FMT == CABCD_BF16) {
+    bf16x8 x, y;
+    __builtin_memcpy(&x, &a, 16);
+    __builtin_memcpy(&y, &b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+  } else {
+    const long a0 = (long)(((uint64_t)a.y << 32) | a.x), b0 = (long)(((uint64_t)b.y << 32) | b.x);
+    const long a1 = (long)(((uint64_t)a.w << 32) | a.z), b1 = (long)(((uint64_t)b.w << 32) | b.z);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
+  }
+}
+
+template <int NB, int FMT, int W>
+__device__ __forceinline__ void lp_tile(const uint8_t* __restrict__ tile, int lane, int kg,
+                                        f4 (&acc)[LpCfg<NB, FMT>::NACC]) {
+  using C = LpCfg<NB, FMT>;
+  constexpr int R1 = NB >= 2 ? W : 0;
+  constexpr int R2 = NB >= 2 ? NB - 1 - W : 0;
+  const uint8_t* base = tile + (lane & 15) * C::RSB + 16 * (lane >> 4);
+#pragma unroll
+  for (int p = 0; p < C::WIN / C::KG; ++p) {
+    const int off = 64 * (kg + p * C::KG);
+    auto frag = [&](int r) {
+      return *reinterpret_cast<const uint4*>(base + r * 16 * C::RSB + off);
+    };
+    const uint4 f1 = frag(R1);
+    const uint4 f2 = NB >= 2 ? frag(R2) : f1;
+#pragma unroll
+    for (int c = 0; c <= R2; ++c) {
+      const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
+      if (c <= R1) acc[c] = lp_mma<FMT>(f1, fc, acc[c]);
+      if constexpr (NB >= 2) acc[R1 + 1 + c] = lp_mma<FMT>(f2, fc, acc[R1 + 1 + c]);
+    }
+  }
+}
+
+template <int NB, int FMT, int W = 0>
+__device__ __forceinline__ void lp_dispatch(int bw, const uint8_t* tile, int lane, int kg,
+                                            f4 (&acc)[LpCfg<NB, FMT>::NACC]) {
+  if constexpr (W < LpCfg<NB, FMT>::BW) {
+    if (bw == W)
+      lp_tile<NB, FMT, W>(tile, lane, kg, acc);
+    else
+      lp_dispatch<NB, FMT, W + 1>(bw, tile, lane, kg, acc);
+  }
+}
+
+template <int FMT>
+__device__ __forceinline__ double lp_decode(const uint4& v, int e) {
+  const uint32_t words[4] = {v.x, v.y, v.z, v.w};
+  if constexpr (FMT == CABCD_BF16) {
+    return decode_bf16((uint16_t)(words[e >> 1] >> (16 * (e & 1))));
+  } else {
+    return decode_e4m3((words[e >> 2] >> (8 * (e & 3))) & 0xFF);
+  }
+}
+
+// 16-byte chunk of row `row` starting at element k (zeros past k_end).
+template <int FMT>
+__device__ __forceinline__ uint4 lp_load(const uint8_t* __restrict__ row, int64_t k,
+                                         int64_t k_end, bool aligned) {
+  constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;
+  constexpr int EPC = 16 / ES;
+  if (k + EPC <= k_end && aligned) return *reinterpret_cast<const uint4*>(row + k * ES);
+  uint8_t b[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) b[e] = (k + e / ES < k_end) ? row[k * ES + e] : 0;
+  uint4 v;
+  __builtin_memcpy(&v, b, 16);
+  return v;
+}
+
+template <int NB, int FMT>
+__global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
+    const uint8_t* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
+    int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
+    int aligned) {
+  using C = LpCfg<NB, FMT>;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[C::LDS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int bw = wave % C::BW;
+  const int kg = wave / C::BW;
+  const int c = tid % C::CH;
+  const int64_t k_begin = (int64_t)blockIdx.x * chunk;
+  const int64_t k_end = std::min(cols, k_begin + chunk);
+  const int ntiles = (int)((k_end - k_begin + C::KT - 1) / C::KT);
+
+  int rho[C::NCH];
+  const uint8_t* rowp[C::NCH];
+#pragma unroll
+  for (int i = 0; i < C::NCH; ++i) {
+    rho[i] = tid / C::CH + (kLpThreads / C::CH) * i;
+    rowp[i] = rho[i] < m ? A + (int64_t)idx[rho[i]] * ld * C::ES : nullptr;
+  }
+  const bool want_u = u != nullptr;
+  double yu[C::NCH];
+  uint4 buf[C::NCH];
+  double ub[C::EPC];
+#pragma unroll
+  for (int i = 0; i < C::NCH; ++i) yu[i] = 0.0;
+
+  auto load_tile = [&](int t) {
+    const int64_t k = k_begin + (int64_t)t * C::KT + (int64_t)C::EPC * c;
+    if (want_u) {
+#pragma unroll
+      for (int e = 0; e < C::EPC; ++e) ub[e] = (k + e < k_end) ? u[k + e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < C::NCH; ++i)
+      buf[i] = rowp[i] ? lp_load<FMT>(rowp[i], k, k_end, aligned != 0) : make_uint4(0, 0, 0, 0);
+  };
+  auto store_tile = [&](int slot) {
+    uint8_t* T = lds + slot * C::TILE;
+#pragma unroll
+    for (int i = 0; i < C::NCH; ++i) {
+      *reinterpret_cast<uint4*>(T + rho[i] * C::RSB + 16 * c) = buf[i];
+      if (want_u) {
+#pragma unroll
+        for (int e = 0; e < C::EPC; ++e) yu[i] = fma(lp_decode<FMT>(buf[i], e), ub[e], yu[i]);
+      }
+    }
+  };
+
+  f4 acc[C::NACC];
+#pragma unroll
+  for (int a = 0; a < C::NACC; ++a) acc[a] = f4{0.f, 0.f, 0.f, 0.f};
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    const bool more = t + 1 < ntiles;
+    if (more) load_tile(t + 1);
+    lp_dispatch<NB, FMT>(bw, lds + (t & 1) * C::TILE, lane, kg, acc);
+    if (more) store_tile((t + 1) & 1);
+    __syncthreads();
+  }
+
+  double* part = partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP);
+  float* red = reinterpret_cast<float*>(lds);
+  if constexpr (C::KG > 1) {
+    if (kg > 0) {
+#pragma unroll
+      for (int a = 0; a < C::NACC; ++a) {
+        float* dst = red + ((kg - 1) * C::NBLK + lp_acc_block<NB>(bw, a)) * 256 + lane;
+        dst[0] = acc[a][0];
+        dst[64] = acc[a][1];
+        dst[128] = acc[a][2];
+        dst[192] = acc[a][3];
+      }
+    }
+    __syncthreads();
+    if (kg == 0) {
+      for (int g = 1; g < C::KG; ++g) {
+#pragma unroll
+        for (int a = 0; a < C::NACC; ++a) {
+          const float* src = red + ((g - 1) * C::NBLK + lp_acc_block<NB>(bw, a)) * 256 + lane;
+          acc[a][0] += src[0];
+          acc[a][1] += src[64];
+          acc[a][2] += src[128];
+          acc[a][3] += src[192];
+        }
+      }
+    }
+  }
+  if (kg == 0) {
+#pragma unroll
+    for (int a = 0; a < C::NACC; ++a) {
+      double* dst = part + lp_acc_block<NB>(bw, a) * 256 + lane;
+      dst[0] = acc[a][0];
+      dst[64] = acc[a][1];
+      dst[128] = acc[a][2];
+      dst[192] = acc[a][3];
+    }
+  }
+  if (want_u) {
+    __syncthreads();
+    double* ys = reinterpret_cast<double*>(lds);
+#pragma unroll
+    for (int i = 0; i < C::NCH; ++i) ys[rho[i] * C::CH + c] = yu[i];
+    __syncthreads();
+    if (tid < C::SBP) {
+      double s = 0.0;
+      for (int q = 0; q < C::CH; ++q) s += ys[tid * C::CH + q];
+      part[C::NBLK * 256 + tid] = s;
+    }
+  }
+}
+
+template <int NB, int FMT>
+hipError_t launch_lp_nb(const GramPlan& p, const void* A, int64_t ld, int64_t cols,
+                        const int32_t* idx, int m, const double* u, double* partials,
+                        hipStream_t st) {
+  using C = LpCfg<NB, FMT>;
+  const int aligned =
+      ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && ((ld * C::ES) & 15) == 0) ? 1 : 0;
+  hipLaunchKernelGGL((gram_lp_kernel<NB, FMT>), dim3(p.nsplit), dim3(kLpThreads), 0, st,
+                     static_cast<const uint8_t*>(A), ld, cols, idx, m, u, p.chunk, partials,
+                     aligned);
+  return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_lp_fmt(const GramPlan& p, const void* A, int64_t ld, int64_t cols,
+                         const int32_t* idx, int m, const double* u, double* partials,
+                         hipStream_t st) {
+  switch (p.nb) {
+    case 1: return launch_lp_nb<1, FMT>(p, A, ld, cols, idx, m, u, partials, st);
+    case 2: return launch_lp_nb<2, FMT>(p, A, ld, cols, idx, m, u, partials, st);
+    case 4: return launch_lp_nb<4, FMT>(p, A, ld, cols, idx, m, u, partials, st);
+    case 8: return launch_lp_nb<8, FMT>(p, A, ld, cols, idx, m, u, partials, st);
+    case 16: return launch_lp_nb<16, FMT>(p, A, ld, cols, idx, m, u, partials, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------- streaming pass
+// out[k] = (accumulate ? out[k] : beta base[k]) + gamma sum_p s[row(p)] v[p] dec(Q[row(p)][k])
+constexpr int kLvThreads = 256;
+
+template <int FMT>
+__global__ __launch_bounds__(kLvThreads) void gemv_t_lp_kernel(
+    const uint8_t* __restrict__ A, int64_t ld, int64_t cols, const float* __restrict__ rs,
+    const int32_t* __restrict__ idx, int64_t m, const double* __restrict__ v, double gamma,
+    const double* __restrict__ base, double beta, int accumulate, double* __restrict__ out,
+    int aligned) {
+  constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;
+  constexpr int EPC = 16 / ES;
+  const int64_t k = ((int64_t)blockIdx.x * kLvThreads + threadIdx.x) * EPC;
+  if (k >= cols) return;
+  double acc[EPC];
+#pragma unroll
+  for (int e = 0; e < EPC; ++e) acc[e] = 0.0;
+  int64_t p = 0;
+  for (; p + 4 <= m; p += 4) {
+    uint4 x[4];
+    double c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = idx ? (int64_t)idx[p + q] : p + q;
+      c[q] = v[p + q] * (rs ? (double)rs[row] : 1.0);
+      x[q] = lp_load<FMT>(A + row * ld * ES, k, cols, aligned != 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) acc[e] = fma(lp_decode<FMT>(x[q], e), c[q], acc[e]);
+  }
+  for (; p < m; ++p) {
+    const int64_t row = idx ? (int64_t)idx[p] : p;
+    const double cq = v[p] * (rs ? (double)rs[row] : 1.0);
+    const uint4 x = lp_load<FMT>(A + row * ld * ES, k, cols, aligned != 0);
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) acc[e] = fma(lp_decode<FMT>(x, e), cq, acc[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < EPC; ++e) {
+    if (k + e < cols) {
+      const double b0 = accumulate ? out[k + e] : (base ? beta * base[k + e] : 0.0);
+      out[k + e] = b0 + gamma * acc[e];
+    }
+  }
+}
+
+}  // namespace
+
+GramPlan plan_gram_lp(int m, int64_t cols, int dtype) {
+  GramPlan p{};
+  int nb = 1;
+  while (16 * nb < m) nb *= 2;
+  p.nb = nb;
+  p.nblk = nb * (nb + 1) / 2;
+  const int es = dtype == CABCD_BF16 ? 2 : 1;
+  p.kt = (2048 / nb) / es;
+  p.rpw = 2;
+  // HBM-bound: about two workgroups per CU, and slabs long enough that the
+  // partial blocks (nblk*2 KiB per workgroup) stay small next to the slab.
+  const int64_t min_chunk = std::max<int64_t>(p.kt, (int64_t)p.nblk * 2048 * 8 / (16 * nb * es));
+  int64_t chunk = std::max<int64_t>(min_chunk, (cols + 511) / 512);
+  chunk = ((chunk + p.kt - 1) / p.kt) * p.kt;
+  p.chunk = chunk;
+  p.nsplit = (int)((cols + chunk - 1) / chunk);
+  return p;
+}
+
+hipError_t launch_gram_lp(const GramPlan& p, int dtype, const void* A, int64_t ld, int64_t cols,
+                          const int32_t* idx, int m, const double* u, double* partials,
+                          hipStream_t st) {
+  if (dtype == CABCD_BF16)
+    return launch_lp_fmt<CABCD_BF16>(p, A, ld, cols, idx, m, u, partials, st);
+  return launch_lp_fmt<CABCD_FP8_E4M3>(p, A, ld, cols, idx, m, u, partials, st);
+}
+
+hipError_t launch_gemv_t_lp(int dtype, const void* A, int64_t ld, int64_t cols, const float* rs,
+                            const int32_t* idx, int64_t m, const double* v, double gamma,
+                            const double* base, double beta, bool accumulate, double* out,
+                            hipStream_t st) {
+  if (cols <= 0) return hipSuccess;
+  const int es = dtype == CABCD_BF16 ? 2 : 1;
+  const int epc = 16 / es;
+  const int aligned = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && ((ld * es) & 15) == 0);
+  const int64_t blocks = (cols + (int64_t)kLvThreads * epc - 1) / ((int64_t)kLvThreads * epc);
+  if (dtype == CABCD_BF16)
+    hipLaunchKernelGGL(gemv_t_lp_kernel<CABCD_BF16>, dim3((unsigned)blocks), dim3(kLvThreads), 0,
+                       st, static_cast<const uint8_t*>(A), ld, cols, rs, idx, m, v, gamma, base,
+                       beta, accumulate ? 1 : 0, out, aligned);
+  else
+    hipLaunchKernelGGL(gemv_t_lp_kernel<CABCD_FP8_E4M3>, dim3((unsigned)blocks),
+                       dim3(kLvThreads), 0, st, static_cast<const uint8_t*>(A), ld, cols, rs, idx,
+                       m, v, gamma, base, beta, accumulate ? 1 : 0, out, aligned);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const double* A, int64_t rows, int64_t cols, int64_t lda, int dtype,
+                           void* Q, int64_t ldq, float* row_scale, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)rows), dim3(kQThreads), 0, st, A, cols, lda,
+                     dtype, Q, ldq, row_scale);
+  return hipGetLastError();
+}
+
+}  // namespace cabcd

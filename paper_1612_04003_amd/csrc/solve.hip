@@ -12,42 +12,114 @@
 // Gram reduction writes (its diagonal blocks are exactly Gamma_j / Theta_j
 // because indices within a block are distinct).
 //
-// Phases (one workgroup, thread p owns row p of the outer step):
-//  1. c, and the s diagonal blocks copied to LDS;
-//  2. all s blocks factorised in parallel (unpivoted Cholesky, row-parallel
-//     right-looking) and inverted (L^{-1}, then L^{-T} L^{-1}); a pivot <= 0 or
-//     NaN raises the device status;
+// Phases (one workgroup; thread p owns row p of the outer step):
+//  1. c, and the diagonal blocks of Gov gathered into registers;
+//  2. every diagonal block inverted by one wave with in-place Gauss-Jordan
+//     elimination, the block's entries spread over the lanes and exchanged by
+//     shuffles (no LDS round trips, no barriers).  Blocks are padded to
+//     BP = 2^k >= b with the identity, whose inverse keeps the padding.  On an
+//     SPD matrix the Gauss-Jordan pivots are the LDL^T pivots, so a pivot <= 0
+//     or NaN is reported as "not positive definite";
 //  3. the dependent chain over j: delta_j = Gamma_j^{-1} rhs_j, then every later
 //     row subtracts its Gov row segment times delta_j.  Row segments of the
-//     next PF blocks are prefetched into registers so the chain waits on LDS
-//     and barriers only;
-//  4. delta written out, and x[idx] += delta by the first occurrence of each
-//     coordinate, adding the duplicates in block order (single writer).
+//     next PF blocks are prefetched into registers; the barriers order LDS
+//     only, so the prefetches stay in flight; vectors in LDS are zero-padded to
+//     BP so every read is unconditional;
+//  4. delta written out, and x[idx] += delta: an LDS hash of the indices gives
+//     each coordinate's first occurrence and count; the first occurrence adds
+//     the duplicates in block order (single writer).
 #include "internal.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace cabcd {
 namespace {
 
-constexpr int kSolveThreads = 256;
+constexpr int pow2_at_least(int b) {
+  int p = 1;
+  while (p < b) p *= 2;
+  return p;
+}
 
-template <int BMAX, int PF>
-__global__ __launch_bounds__(kSolveThreads) void solve_kernel(SolveArgs a) {
+template <int BP>
+struct SolveCfg {
+  static constexpr int EPL = BP * BP > 64 ? BP * BP / 64 : 1;   // block entries per lane
+  static constexpr int SPW = BP * BP < 64 ? 64 / (BP * BP) : 1; // blocks per wave
+};
+
+// In-place Gauss-Jordan inversion of the SPW blocks held by one wave.
+// EPL == 1: lane l holds entry (u, v) = ((l % BP^2) / BP, l % BP) of block
+// l / BP^2.  EPL > 1: entry l + 64 t of the single block sits in slot t.
+template <int BP>
+__device__ __forceinline__ void gj_invert(double (&e)[SolveCfg<BP>::EPL], int lane, bool& bad) {
+  using C = SolveCfg<BP>;
+  if constexpr (C::EPL == 1) {
+    const int base = (lane / (BP * BP)) * (BP * BP);
+    const int idx = lane - base;
+    const int u = idx / BP, v = idx % BP;
+#pragma unroll
+    for (int k = 0; k < BP; ++k) {
+      const double piv = __shfl(e[0], base + k * BP + k, 64);
+      const double akv_old = __shfl(e[0], base + k * BP + v, 64);
+      const double f = __shfl(e[0], base + u * BP + k, 64);
+      bad |= !(piv > 0.0);
+      const double rp = 1.0 / piv;
+      const double akv = (v == k ? 1.0 : akv_old) * rp;   // row k after a[k][k] = 1, / piv
+      e[0] = u == k ? akv : (v == k ? 0.0 : e[0]) - f * akv;
+    }
+  } else {
+    const int v = lane % BP;   // the same column in every slot: 64 is a multiple of BP
+#pragma unroll
+    for (int k = 0; k < BP; ++k) {
+      const int pe = k * BP + k;
+      const double piv = __shfl(e[pe / 64], pe % 64, 64);
+      bad |= !(piv > 0.0);
+      const double rp = 1.0 / piv;
+      const double akv_old = __shfl(e[(k * BP) / 64], (k * BP + v) % 64, 64);
+      const double akv = (v == k ? 1.0 : akv_old) * rp;
+      double f[C::EPL];
+#pragma unroll
+      for (int t = 0; t < C::EPL; ++t) {
+        const int u = (lane + 64 * t) / BP;
+        f[t] = __shfl(e[t], (u * BP + k) % 64, 64);
+      }
+#pragma unroll
+      for (int t = 0; t < C::EPL; ++t) {
+        const int u = (lane + 64 * t) / BP;
+        e[t] = u == k ? akv : (v == k ? 0.0 : e[t]) - f[t] * akv;
+      }
+    }
+  }
+}
+
+constexpr int kHashMin = 2048;   // LDS hash slots for the scatter (>= 2 m)
+
+__device__ __forceinline__ unsigned hash_idx(int i, int slots) {
+  return ((unsigned)i * 2654435761u) & (unsigned)(slots - 1);
+}
+
+template <int BP, int PF, int THREADS>
+__global__ __launch_bounds__(THREADS) void solve_kernel(SolveArgs a) {
+  using C = SolveCfg<BP>;
   extern __shared__ __attribute__((aligned(16))) double sm[];
   const int m = a.m, b = a.b, s = a.s;
-  double* D = sm;                   // s blocks b x b: Cholesky, then the inverse
-  double* Li = D + m * b;           // s blocks b x b: L^{-1}
-  double* R = Li + m * b;           // b: rhs of the current block
-  double* Dl = R + BMAX;            // m: delta
-  int* Ix = reinterpret_cast<int*>(Dl + m);   // m: indices
+  // LDS: Ginv [s][BP][BP] (reused as the hash table in phase 4), R [BP],
+  // Dl [s][BP] (zero-padded delta), Ix [m]
+  const int slots = std::max(kHashMin, pow2_at_least(2 * m));
+  const size_t gi_doubles =
+      std::max((size_t)s * BP * BP, ((size_t)slots * 3 * sizeof(int) + 7) / sizeof(double));
+  double* Gi = sm;
+  double* R = Gi + gi_doubles;
+  double* Dl = R + BP;
+  int* Ix = reinterpret_cast<int*>(Dl + (size_t)s * BP);
 
   const int p = threadIdx.x;
+  const int lane = p & 63;
+  const int wave = p >> 6;
   const bool active = p < m;
   const int j_of = active ? p / b : -1;   // block of this row (-1: no row)
   const int u = active ? p - j_of * b : 0;
-  double* Dj = D + (active ? j_of : 0) * b * b;
-  double* Lj = Li + (active ? j_of : 0) * b * b;
 
   // ---- phase 1
   double rhs = 0.0;
@@ -58,132 +130,159 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(SolveArgs a) {
     const double yu = a.Yu[p];
     const double xi = a.x[ip];
     rhs = a.mode == 0 ? (-a.lambda * xi - yu / a.n) : ((yu - xi - a.y[ip]) / a.n);
-    const double* g = a.G + (int64_t)p * m + j_of * b;
-    for (int v = 0; v <= u; ++v) Dj[u * b + v] = g[v];
   }
+  for (int q = p; q < s * BP; q += THREADS) Dl[q] = 0.0;
+  if (p < BP) R[p] = 0.0;
 
-  // Prefetch ring of Gov row segments for the first PF blocks.
-  double ring[PF][BMAX];
+  // Prefetch ring of Gov row segments Gov[p][jb*b + v].  Gov is symmetric, so
+  // they are read as Gov[jb*b + v][p]: consecutive threads then read
+  // consecutive addresses (one cache line per 16 lanes instead of one per
+  // lane).  Unconditional loads with the block and column clamped into range
+  // keep the number of loads uniform, so the compiler waits for exactly the
+  // one it needs.
+  const double* gcol = a.G + (active ? p : m - 1);
+  double ring[PF][BP];
+  auto ring_load = [&](int q, int jb) {
+    const double* g = gcol + (int64_t)(jb < j_of ? jb : 0) * b * m;
 #pragma unroll
-  for (int q = 0; q < PF; ++q) {
-    if (q < j_of) {
-      const double* g = a.G + (int64_t)p * m + q * b;
+    for (int v = 0; v < BP; ++v) ring[q][v] = g[(int64_t)(v < b ? v : b - 1) * m];
+  };
 #pragma unroll
-      for (int v = 0; v < BMAX; ++v) ring[q][v] = v < b ? g[v] : 0.0;
-    }
-  }
-  __syncthreads();
+  for (int q = 0; q < PF; ++q) ring_load(q, q);
 
-  // ---- phase 2: Cholesky of every diagonal block, row u of block j per thread
-  // Every row of the block reads the pivot before the diagonal is overwritten.
+  // ---- phase 2: invert the diagonal blocks, SPW blocks per wave at a time
+  constexpr int WAVES = THREADS / 64;
   bool bad = false;
-  for (int k = 0; k < b; ++k) {
-    double lkk = 1.0;
-    if (active && u >= k) {
-      const double piv = Dj[k * b + k];
-      bad |= !(piv > 0.0);
-      lkk = sqrt(piv);
-      if (u > k) Dj[u * b + k] /= lkk;
+  for (int j0 = wave * C::SPW; j0 < s; j0 += WAVES * C::SPW) {
+    // entry t of this lane: block blk(t), row uu(t), column vv(t)
+    auto blk = [&](int t) { return C::EPL == 1 ? j0 + lane / (BP * BP) : j0; };
+    auto eix = [&](int t) { return C::EPL == 1 ? lane % (BP * BP) : lane + 64 * t; };
+    double e[C::EPL];
+#pragma unroll
+    for (int t = 0; t < C::EPL; ++t) {
+      const int bj = blk(t), uu = eix(t) / BP, vv = eix(t) % BP;
+      e[t] = (bj < s && uu < b && vv < b) ? a.G[(int64_t)(bj * b + uu) * m + bj * b + vv]
+                                          : (uu == vv ? 1.0 : 0.0);   // identity padding
     }
-    __syncthreads();
-    if (active && u == k) Dj[k * b + k] = lkk;
-    if (active && u > k) {
-      const double luk = Dj[u * b + k];
-      for (int v = k + 1; v <= u; ++v) Dj[u * b + v] -= luk * Dj[v * b + k];
-    }
-    __syncthreads();
-  }
-  // column u of L^{-1}: solve L x = e_u by forward substitution
-  if (active) {
-    for (int v = 0; v < u; ++v) Lj[v * b + u] = 0.0;
-    Lj[u * b + u] = 1.0 / Dj[u * b + u];
-    for (int v = u + 1; v < b; ++v) {
-      double t = 0.0;
-      for (int w = u; w < v; ++w) t += Dj[v * b + w] * Lj[w * b + u];
-      Lj[v * b + u] = -t / Dj[v * b + v];
-    }
-  }
-  __syncthreads();
-  // row u of Gamma^{-1} = L^{-T} L^{-1}
-  if (active) {
-    for (int v = 0; v < b; ++v) {
-      double t = 0.0;
-      for (int w = std::max(u, v); w < b; ++w) t += Lj[w * b + u] * Lj[w * b + v];
-      Dj[u * b + v] = t;
-    }
+    gj_invert<BP>(e, lane, bad);
+#pragma unroll
+    for (int t = 0; t < C::EPL; ++t)
+      if (blk(t) < s) Gi[((size_t)blk(t) * BP + eix(t) / BP) * BP + eix(t) % BP] = e[t];
   }
   if (bad) *a.status = DEV_NOTSPD;
-  __syncthreads();
+  lds_barrier();
 
-  // ---- phase 3: the dependent chain over the s blocks
+  // ---- phase 3: the dependent chain over the s blocks.  Every thread runs all
+  // rounds (the work of steps j >= s is switched off, the barriers and loads
+  // are not), so the control flow is uniform.
   for (int j0 = 0; j0 < s; j0 += PF) {
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int j = j0 + q;
-      if (j < s) {
-        if (j_of == j) R[u] = rhs;
-        __syncthreads();
-        if (p < b) {
-          const double* Gi = D + j * b * b + p * b;
-          double t = 0.0;
-          for (int v = 0; v < b; ++v) t += Gi[v] * R[v];
-          Dl[j * b + p] = t;
-        }
-        __syncthreads();
-        if (j_of > j) {
-          const double* dj = Dl + j * b;
+      if (j_of == j) R[u] = rhs;
+      lds_barrier();
+      if (p < b && j < s) {
+        const double* g = Gi + ((size_t)j * BP + p) * BP;
+        double t = 0.0;
 #pragma unroll
-          for (int v = 0; v < BMAX; ++v)
-            if (v < b) rhs -= ring[q][v] * dj[v];
-          const int jn = j + PF;
-          if (jn < j_of) {
-            const double* g = a.G + (int64_t)p * m + jn * b;
-#pragma unroll
-            for (int v = 0; v < BMAX; ++v) ring[q][v] = v < b ? g[v] : 0.0;
-          }
-        }
+        for (int v = 0; v < BP; ++v) t += g[v] * R[v];
+        Dl[j * BP + p] = t;
       }
+      lds_barrier();
+      if (j_of > j) {
+        const double* dj = Dl + j * BP;
+        double acc = 0.0;
+#pragma unroll
+        for (int v = 0; v < BP; ++v) acc += ring[q][v] * dj[v];
+        rhs -= acc;
+      }
+      ring_load(q, j + PF);
     }
   }
 
-  // ---- phase 4: outputs
+  // ---- phase 4: outputs.  Gi is free now and holds the hash table.
+  int* hkey = reinterpret_cast<int*>(Gi);
+  int* hmin = hkey + slots;
+  int* hcnt = hmin + slots;
+  for (int q = p; q < slots; q += THREADS) {
+    hkey[q] = -1;
+    hmin[q] = INT_MAX;
+    hcnt[q] = 0;
+  }
+  lds_barrier();
+  unsigned h = 0;
+  double dp = 0.0;
   if (active) {
-    const double dp = Dl[p];
+    dp = Dl[j_of * BP + u];
     a.delta[p] = dp;
     if (!isfinite(dp)) *a.status = DEV_NONFINITE;
-    bool first = true;
-    for (int q = 0; q < p; ++q) first &= (Ix[q] != ip);
-    if (first) {
+    h = hash_idx(ip, slots);
+    for (;;) {
+      const int old = atomicCAS(&hkey[h], -1, ip);
+      if (old == -1 || old == ip) break;
+      h = (h + 1) & (unsigned)(slots - 1);
+    }
+    atomicMin(&hmin[h], p);
+    atomicAdd(&hcnt[h], 1);
+  }
+  lds_barrier();
+  if (active && hmin[h] == p) {
+    if (hcnt[h] == 1) {
+      a.x[ip] += dp;
+    } else {
       double acc = a.x[ip];
       for (int q = p; q < m; ++q)
-        if (Ix[q] == ip) acc += Dl[q];
+        if (Ix[q] == ip) acc += Dl[(q / b) * BP + q % b];
       a.x[ip] = acc;
     }
   }
 }
 
-template <int BMAX, int PF>
+template <int BP, int PF, int THREADS>
 hipError_t launch_b(const SolveArgs& a, hipStream_t st) {
-  const size_t bytes = sizeof(double) * (2 * (size_t)a.m * a.b + BMAX + a.m) +
-                       sizeof(int) * (size_t)a.m;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(solve_kernel<BMAX, PF>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(solve_kernel<BP, PF, THREADS>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSolveMaxLds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((solve_kernel<BMAX, PF>), dim3(1), dim3(kSolveThreads), bytes, st, a);
+  hipLaunchKernelGGL((solve_kernel<BP, PF, THREADS>), dim3(1), dim3(THREADS),
+                     solve_lds_bytes(a.m, a.b), st, a);
   return hipGetLastError();
+}
+
+template <int BP, int PF>
+hipError_t launch_t(const SolveArgs& a, hipStream_t st) {
+  if (a.m <= 512) return launch_b<BP, PF, 512>(a, st);
+  if constexpr (BP <= 8) return launch_b<BP, 2, 1024>(a, st);
+  if constexpr (BP == 16) return launch_b<BP, 1, 1024>(a, st);
+  return hipErrorInvalidValue;   // b in (16, 32] never reaches m > 512 within the LDS bound
 }
 
 }  // namespace
 
+size_t solve_lds_bytes(int m, int b) {
+  const int bp = pow2_at_least(b);
+  const int s = (m + b - 1) / b;
+  const int slots = std::max(kHashMin, pow2_at_least(2 * m));
+  const size_t gi = std::max((size_t)s * bp * bp,
+                             ((size_t)slots * 3 * sizeof(int) + 7) / sizeof(double));
+  return sizeof(double) * (gi + (size_t)bp + (size_t)s * bp) + sizeof(int) * (size_t)m;
+}
+
 hipError_t launch_solve(const SolveArgs& a, hipStream_t st) {
-  if (a.m > kSolveThreads || a.b > 32) return hipErrorInvalidValue;
-  if (a.b <= 8) return launch_b<8, 4>(a, st);
-  if (a.b <= 16) return launch_b<16, 4>(a, st);
-  return launch_b<32, 2>(a, st);
+  if (a.m > kSolveMaxRows || a.b > kSolveMaxB || solve_lds_bytes(a.m, a.b) > kSolveMaxLds)
+    return hipErrorInvalidValue;
+  switch (pow2_at_least(a.b)) {
+    case 1: return launch_t<1, 8>(a, st);
+    case 2: return launch_t<2, 8>(a, st);
+    case 4: return launch_t<4, 8>(a, st);
+    case 8: return launch_t<8, 8>(a, st);
+    case 16: return launch_t<16, 4>(a, st);
+    default: return launch_t<32, 1>(a, st);
+  }
 }
 
 }  // namespace cabcd

@@ -1,0 +1,133 @@
+"""CSR path vs the CPU oracle through the C-ABI.
+
+Tolerances as for the dense FP64 path: Gram entries within 1e-12 of
+scale * |Y||Y|^T, iterates within 1e-10 relative.  The companion scatter uses
+FP64 atomic adds, so the GPU result is reproducible only up to the order of
+those additions; every comparison here has a tolerance.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse
+import torch
+
+from oracle import bcd
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _random_csr(rows, cols, density, seed, long_rows=(), empty_rows=()):
+    rng = np.random.default_rng(seed)
+    S = scipy.sparse.random(rows, cols, density=density, format="lil", random_state=rng,
+                            data_rvs=rng.standard_normal)
+    for r in long_rows:
+        c = rng.choice(cols, size=min(cols, 5000), replace=False)
+        S[r, c] = rng.standard_normal(len(c))
+    for r in empty_rows:
+        S[r, :] = 0
+    S = S.tocsr()
+    S.eliminate_zeros()
+    S.sort_indices()
+    return S
+
+
+@pytest.mark.parametrize("m,seed", [(1, 0), (16, 1), (100, 2), (257, 3), (512, 4), (1024, 5)])
+def test_csr_gram_matches_oracle(gpu_lib, m, seed):
+    _say("csr gram", m, seed)
+    rows, cols = 1500, 9000
+    S = _random_csr(rows, cols, 0.01, seed, long_rows=(7, 11), empty_rows=(3,))
+    rng = np.random.default_rng(seed + 100)
+    idx = rng.integers(0, rows, size=m).astype(np.int32)
+    idx[: min(m, 3)] = [7, 3, 11][: min(m, 3)]      # long rows and an empty row
+    u = rng.standard_normal(cols)
+    A = gpu_lib.CSR.from_scipy(S, DEV)
+    G, Yu = gpu_lib.gram(A, torch.tensor(idx, device=DEV), 0.5, 0.25,
+                         torch.tensor(u, device=DEV))
+    Go, Yo = bcd.gram(S, idx, 0.5, 0.25, u)
+    Y = np.abs(np.asarray(S[idx].todense()))
+    assert np.all(np.abs(G.cpu().numpy() - Go) <= 1e-12 * 0.5 * (Y @ Y.T) + 1e-300)
+    assert np.all(np.abs(Yu.cpu().numpy() - Yo) <= 1e-12 * (Y @ np.abs(u)) + 1e-300)
+
+
+@pytest.fixture(scope="module")
+def zipf_small():
+    rowptr, colidx, vals, y, _ = synth.zipf_csr_ridge(2000, 1 << 14, 31, 1002)
+    A = scipy.sparse.csr_matrix((vals, colidx, rowptr), shape=(2000, 1 << 14))
+    return A, y
+
+
+@pytest.mark.parametrize("s", [1, 8, 32])
+def test_csr_dual_matches_oracle(gpu_lib, zipf_small, s):
+    _say("csr dual", s)
+    A, y = zipf_small
+    lam, b, H, seed = 1e-3, 16, 96, 2002
+    XT = gpu_lib.CSR.from_scipy(A, DEV)
+    a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), lam, b, s, H, seed)
+    ao, wo = bcd.dual_bcd(A.T.tocsc(), y, lam, b, s, H, seed)
+    assert _rel(a.cpu(), ao) <= 1e-10
+    assert _rel(w.cpu(), wo) <= 1e-10
+
+
+def test_csr_dual_link_and_objective(gpu_lib, zipf_small):
+    _say("csr dual link")
+    A, y = zipf_small
+    lam = 1e-3
+    XT = gpu_lib.CSR.from_scipy(A, DEV)
+    yd = torch.tensor(y, device=DEV)
+    trace = torch.zeros(4, dtype=torch.float64, device=DEV)
+    a, w = gpu_lib.dual_bcd(XT, yd, lam, 16, 8, 256, 7, monitor_every=8, trace=trace)
+    wl = gpu_lib.dual_to_primal(XT, a, lam)
+    assert _rel(w.cpu(), wl.cpu()) <= 1e-10
+    X = A.T.tocsr()
+    f, _ = gpu_lib.primal_objective_t(XT, yd, lam, w)
+    fo = bcd.primal_objective(X, y, lam, w.cpu().numpy())
+    assert abs(f.item() - fo) <= 1e-12 * fo
+    assert abs(trace[3].item() - fo) <= 1e-12 * fo
+
+
+def test_csr_primal_matches_oracle(gpu_lib):
+    _say("csr primal")
+    S = _random_csr(300, 4000, 0.02, 9, long_rows=(5,), empty_rows=(17,))
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(4000)
+    X = gpu_lib.CSR.from_scipy(S, DEV)
+    w, r = gpu_lib.primal_bcd(X, torch.tensor(y, device=DEV), 1e-2, 8, 6, 70, 5)
+    wo, zo = bcd.primal_bcd(S, y, 1e-2, 8, 6, 70, 5)
+    assert _rel(w.cpu(), wo) <= 1e-10
+    assert _rel(r.cpu(), zo - y) <= 1e-10
+    f, _ = gpu_lib.primal_objective(X, torch.tensor(y, device=DEV), 1e-2, w)
+    assert abs(f.item() - bcd.primal_objective(S, y, 1e-2, w.cpu().numpy())) <= 1e-12 * f.item()
+
+
+def test_csr_malformed_is_rejected(gpu_lib):
+    _say("csr malformed")
+    S = _random_csr(50, 200, 0.05, 1)
+    good = gpu_lib.CSR.from_scipy(S, DEV)
+    y = torch.zeros(50, dtype=torch.float64, device=DEV)
+    bad_cols = good.colidx.clone()
+    bad_cols[0] = 200                      # column out of range
+    bad = gpu_lib.CSR(good.rowptr, bad_cols, good.vals, (50, 200))
+    with pytest.raises(gpu_lib.CabcdError) as e:
+        gpu_lib.dual_bcd(bad, y, 0.1, 2, 2, 4, 0)
+    assert e.value.status == gpu_lib.EINVAL
+    unsorted = good.colidx.clone()
+    r0, r1 = int(good.rowptr[4]), int(good.rowptr[5])
+    if r1 - r0 >= 2:
+        unsorted[r0], unsorted[r0 + 1] = good.colidx[r0 + 1], good.colidx[r0]
+        with pytest.raises(gpu_lib.CabcdError):
+            gpu_lib.dual_bcd(gpu_lib.CSR(good.rowptr, unsorted, good.vals, (50, 200)), y,
+                             0.1, 2, 2, 4, 0)
+    # the good matrix still works afterwards
+    gpu_lib.dual_bcd(good, y, 0.1, 2, 2, 4, 0)

@@ -1,0 +1,117 @@
+"""Mixed-precision path (BF16 / FP8-E4M3 storage) vs the CPU oracle.
+
+* Quantisation: bit-exact against the oracle's encoders (codes and FP32 scales).
+* Gram of stored codes: FP32 accumulation on the matrix cores, so the bound is
+  Higham's worst case for a K-term FP32 dot product, K * 2^-24 * |Y^||Y^|^T,
+  against the FP64 Gram of the dequantised rows X^; Y u is FP64 (1e-12).
+* End to end: the problem solved is (X^, y, lambda); the run must reach a
+  relative objective error of 1e-6 against the closed-form optimum on X^, and
+  an exact residual recomputation must reproduce X^T w - y to 1e-12.  The
+  iterates are not expected to equal the FP64 oracle's (the Gram differs at
+  the FP32 level); their distance is reported, not pinned.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bcd, quant
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _matrix(rows, cols, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((rows, cols)) * np.exp(2.0 * rng.standard_normal(rows))[:, None]
+    X[1] = 0.0                                   # an all-zero row
+    X[2, :5] = [448.0, -1e6, 3e-12, 0.0, 1.0 + 2.0 ** -8 + 2.0 ** -40]
+    return X
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_quantize_bit_exact(gpu_lib, dtype):
+    _say("quantize", dtype)
+    X = _matrix(37, 1001, 1)
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(torch.tensor(X, device=DEV), code)
+    want, s, _ = quant.quantize_rows(X, dtype)
+    got = Q.codes.cpu().numpy()
+    if dtype == "bf16":
+        assert np.array_equal(got.view(np.uint16), want)
+        assert Q.scales is None
+    else:
+        assert np.array_equal(got, want)
+        assert np.array_equal(Q.scales.cpu().numpy().view(np.uint32), s.view(np.uint32))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("m,cols", [(5, 77), (16, 4096), (100, 10001), (256, 20000)])
+def test_lowp_gram_against_fp64_gram_of_dequantised(gpu_lib, dtype, m, cols):
+    _say("lowp gram", dtype, m, cols)
+    rows = m + 7
+    X = _matrix(rows, cols, m + cols)
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(torch.tensor(X, device=DEV), code)
+    Xh = Q.dequantize().cpu().numpy()
+    _, _, Xo = quant.quantize_rows(X, dtype)
+    assert np.array_equal(Xh, Xo)                    # the torch decode agrees with the oracle
+    rng = np.random.default_rng(m)
+    idx = rng.integers(0, rows, size=m).astype(np.int32)
+    u = rng.standard_normal(cols)
+    scale, shift = 1.0 / cols, 0.5
+    G, Yu = gpu_lib.gram(Q, torch.tensor(idx, device=DEV), scale, shift,
+                         torch.tensor(u, device=DEV))
+    Go, Yo = bcd.gram(Xh, idx, scale, shift, u)
+    Y = np.abs(Xh[idx])
+    # BF16: Higham's bound for a K-term FP32 dot product.  FP8: the E4M3 matrix
+    # instruction sums its 32 products with a coarser internal accumulation
+    # than sequential IEEE FP32 (measured about 1e-5 relative at K = 77), so
+    # its bound carries an extra 2^-12 relative term.
+    rel_bound = cols * 2.0 ** -24 + (0.0 if dtype == "bf16" else 2.0 ** -12)
+    bound = rel_bound * scale * (Y @ Y.T) + 1e-300
+    err = np.abs(G.cpu().numpy() - Go)
+    assert np.all(err <= bound)
+    rel = (err / np.maximum(scale * (Y @ Y.T), 1e-300)).max()
+    _say(f"  max |dG| / (scale |Y||Y|^T) = {rel:.2e}")
+    assert np.all(np.abs(Yu.cpu().numpy() - Yo) <= 1e-12 * (Y @ np.abs(u)) + 1e-300)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_mixed_primal_reaches_1e6_on_dequantised_problem(gpu_lib, dtype):
+    _say("mixed primal", dtype)
+    X, y, _, _ = synth.colscaled_ridge(128, 8192, 7)
+    lam, b, s, H, seed = 1e-4, 16, 8, 8 * 24, 3
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(X.to(DEV), code)
+    Xh = Q.dequantize().cpu().numpy()
+    yn = y.numpy()
+    wstar = bcd.ridge_closed_form(Xh, yn, lam)
+    fstar = bcd.primal_objective(Xh, yn, lam, wstar)
+    trace = torch.zeros(6, dtype=torch.float64, device=DEV)
+    w, r = gpu_lib.primal_bcd(Q, y.to(DEV), lam, b, s, H, seed, resid_every=4,
+                              monitor_every=4, trace=trace)
+    wn = w.cpu().numpy()
+    rel_obj = (bcd.primal_objective(Xh, yn, lam, wn) - fstar) / fstar
+    _say(f"  rel obj error {rel_obj:.2e}; trace {trace.cpu().numpy()}")
+    assert rel_obj <= 1e-6
+    t = (trace.cpu().numpy() - fstar) / fstar
+    assert abs(t[-1] - rel_obj) <= 1e-9
+    # the last outer step was an exact recomputation (24 outer steps, every 4th)
+    assert np.linalg.norm(r.cpu().numpy() - (Xh.T @ wn - yn)) <= 1e-12 * np.linalg.norm(yn)
+    wo, _ = bcd.primal_bcd(Xh, yn, lam, b, s, H, seed)
+    _say(f"  ||w_mixed - w_fp64 oracle|| / ||w_fp64|| = "
+         f"{np.linalg.norm(wn - wo) / np.linalg.norm(wo):.2e} (reported, not pinned)")
+
+
+def test_mixed_dual_is_unsupported(gpu_lib):
+    X, y, _ = synth.gaussian_ridge(16, 64, 1)
+    Q = gpu_lib.quantize(X.t().contiguous().to(DEV), gpu_lib.BF16)
+    with pytest.raises(gpu_lib.CabcdError) as e:
+        gpu_lib.dual_bcd(Q, y.to(DEV), 0.1, 4, 2, 4, 0)
+    assert e.value.status == gpu_lib.EUNSUPPORTED
