@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the CA-BCD s-step hot path on one MI355X.
 
-Workload (default): dense primal ridge regression in FP64, X = U diag(sigma) V^T
+Headline workload: dense primal ridge regression in FP64, X = U diag(sigma) V^T
 with d = 2048 features, n = 262144 samples, sigma log-spaced over [1, 1e3],
 lambda = 1e-4, b = 8, s = 32 (s*b = 256).  A step is one outer s-step of
 CA-BCD (Alg. 2): sample the s blocks, gather the rows and form the Gram with
@@ -10,11 +10,20 @@ deferred w / residual updates.  Inputs are resident in HBM before timing.
 
 value = algorithmic Gram flops of the timed steps (n*sb*(sb+1) per step: the
 lower triangle with its diagonal) / wall time of the whole steps, in TFLOP/s.
-The roofline entry times the Gram kernel alone with HIP events on the stream it
-runs on.  The CPU baseline runs the FP64 oracle on a bounded number of outer
-steps of the same problem on the host.
+roofline: the Gram kernel alone, timed with HIP events on the stream it runs
+on.  cpu_baseline: the FP64 oracle on a bounded number of outer steps of the
+same problem on the host.
 
-Prints one JSON line.  Single GPU only: --gpus above 1 exits with a message.
+time_to_tol: wall time from the first s-step until a monitor point (every 4
+outer steps, each with an exact residual recomputation) shows a relative
+objective error <= 1e-6, on the column-scaled workload d = 4096, n = 2^20,
+lambda = 1e-4, b = 16, s = 16: FP64 CA-BCD on the dequantised matrix X^ versus
+the mixed-precision runs on the BF16 / FP8 storage of the same X^.
+
+extra: shorter records of the other configurations (s sweep of the headline,
+the dense dual on X^T, the sparse dual on a Zipf CSR matrix).
+
+Prints one JSON line on stdout (progress goes to stderr).  Single GPU only.
 """
 
 import argparse
@@ -30,6 +39,10 @@ PEAK_FP64_MATRIX_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,13 +55,14 @@ def parse():
     ap.add_argument("--lam", type=float, default=1e-4)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tol", action="store_true", help="skip the time-to-1e-6 runs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra records")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per Gram launch measured by rocprofv3 counters")
     return ap.parse_args()
 
 
 def cpu_baseline(X, y, lam, b, s, steps, seed):
-    import numpy as np
     from oracle import bcd
     try:
         from threadpoolctl import threadpool_info
@@ -63,8 +77,6 @@ def cpu_baseline(X, y, lam, b, s, steps, seed):
                    monitor=lambda h, w, z: stamps.append(time.perf_counter()))
     d, n = Xh.shape
     sb = s * b
-    # per-step time from the first step's start (after the oracle's one-off
-    # X^T w_0 and X y products) to the last step's end
     per_step = (stamps[-1] - t0) / steps
     flops = n * sb * (sb + 1)
     return {"value": flops / per_step / 1e12, "unit": "TFLOP/s", "cores": int(threads),
@@ -73,47 +85,35 @@ def cpu_baseline(X, y, lam, b, s, steps, seed):
                       f"d={d} x n={n} problem; {per_step:.3f} s per step"}
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (no collectives); "
-              f"--gpus {args.gpus} is not supported", file=sys.stderr)
-        sys.exit(2)
+def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False):
+    """Warm up, then time `steps` outer steps; returns (elapsed s, phase dict)."""
+    rows, cols = X.shape
+    coord = torch.zeros(rows, dtype=torch.float64, device=y.device)
+    comp = torch.empty(cols, dtype=torch.float64, device=y.device)
+    run = cabcd.dual_bcd if dual else cabcd.primal_bcd
+    if dual:
+        kw0 = dict(alpha=coord, w=comp)
+    else:
+        kw0 = dict(w=coord, r=comp)
+    run(X, y, lam, b, s, warmup * s, seed, **kw0)
+    torch.cuda.synchronize()
+    tm = cabcd.new_timing()
+    t0 = time.perf_counter()
+    run(X, y, lam, b, s, steps * s, seed, h0=warmup * s, flags=cabcd.FLAG_STATE_VALID,
+        timing=tm, **kw0)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, cabcd.timing_dict(tm)
 
-    import torch
-    import paper_1612_04003_amd as cabcd
-    import synth
 
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    cabcd.load()
+def headline(args, cabcd, torch, synth):
     dev = "cuda:0"
     d, n, b, s, lam = args.d, args.n, args.b, args.s, args.lam
     sb = s * b
-    seed = 2001
-    print(f"[bench] generating X ({d} x {n}, FP64) on the GPU", file=sys.stderr, flush=True)
+    log(f"generating X ({d} x {n}, FP64) on the GPU")
     X, y, _ = synth.spectral_ridge(d, n, 1001, device=dev)
     torch.cuda.synchronize()
-
-    w = torch.zeros(d, dtype=torch.float64, device=dev)
-    r = torch.empty(n, dtype=torch.float64, device=dev)
-    print("[bench] warmup", file=sys.stderr, flush=True)
-    cabcd.primal_bcd(X, y, lam, b, s, args.warmup * s, seed, w=w, r=r)
-    torch.cuda.synchronize()
-
-    tm = cabcd.new_timing()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cabcd.primal_bcd(X, y, lam, b, s, args.steps * s, seed, w=w, r=r,
-                     h0=args.warmup * s, flags=cabcd.FLAG_STATE_VALID, timing=tm)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    ph = cabcd.timing_dict(tm)
-
+    log(f"timing {args.steps} steps")
+    elapsed, ph = timed_primal(cabcd, torch, X, y, lam, b, s, args.steps, args.warmup, 2001)
     gram_flops = n * sb * (sb + 1)
     value = gram_flops * args.steps / elapsed / 1e12
     g = ph["gram"]
@@ -123,9 +123,7 @@ def main():
     traffic = None
     try:
         with open(args.traffic_json) as fh:
-            tj = json.load(fh)
-        key = f"gram_f64_d{d}_n{n}_sb{sb}"
-        traffic = tj.get(key)
+            traffic = json.load(fh).get(f"gram_f64_d{d}_n{n}_sb{sb}")
     except (OSError, ValueError):
         pass
     if mfma_bound:
@@ -137,9 +135,8 @@ def main():
         achieved = ybytes / (gram_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
-    roof["kernel"] = "gram_f64_kernel<16>" if sb > 128 else "gram_f64_kernel"
+    roof["kernel"] = "gram_f64_kernel<16,2>" if sb > 128 else "gram_f64_kernel"
     roof["per_launch"] = {"flops": gram_flops, "bytes": ybytes, "ms": round(gram_ms, 4)}
-
     out = {
         "metric": "CA-BCD Gram TFLOP/s (% peak) + time-to-1e-6 rel obj error, FP64 vs mixed",
         "value": round(value, 3),
@@ -160,11 +157,142 @@ def main():
         "phases_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in ph.items()
                                if v["launches"]},
     }
+    return out, X, y
+
+
+def extra_records(args, cabcd, torch, synth, X, y):
+    rec = {}
+    d, n, lam = args.d, args.n, args.lam
+    for s in (1, 4, 16):
+        sb = s * args.b
+        el, ph = timed_primal(cabcd, torch, X, y, lam, args.b, s, 20, 2, 2001)
+        g = ph["gram"]["ms"] / max(ph["gram"]["launches"], 1)
+        rec[f"primal_s{s}"] = {"ms_per_step": round(el / 20 * 1e3, 4),
+                               "gram_ms": round(g, 4),
+                               "gram_tflops": round(n * sb * (sb + 1) / (g * 1e-3) / 1e12, 3),
+                               "gram_gbs": round(sb * n * 8 / (g * 1e-3) / 1e9, 1)}
+        log(f"primal s={s}: {rec[f'primal_s{s}']}")
+    XT = X.t().contiguous()
+    el, ph = timed_primal(cabcd, torch, XT, y, lam, args.b, args.s, 20, 2, 2001, dual=True)
+    g = ph["gram"]["ms"] / max(ph["gram"]["launches"], 1)
+    sb = args.s * args.b
+    rec["dual_s32"] = {"ms_per_step": round(el / 20 * 1e3, 4), "gram_ms": round(g, 4),
+                       "gram_tflops": round(d * sb * (sb + 1) / (g * 1e-3) / 1e12, 3)}
+    log(f"dual: {rec['dual_s32']}")
+    del XT
+    # sparse dual: A = X^T in CSR, 20000 rows x 2^20 columns, 315 Zipf(1.1) features per row
+    import numpy as np
+    log("generating the sparse problem (CSR, 20000 x 2^20)")
+    rowptr, colidx, vals, ys, _ = synth.zipf_csr_ridge(20000, 1 << 20, 315, 1002)
+    A = cabcd.CSR(torch.tensor(rowptr, device="cuda"), torch.tensor(colidx, device="cuda"),
+                  torch.tensor(vals, device="cuda"), (20000, 1 << 20))
+    yd = torch.tensor(ys, device="cuda")
+    for s in (1, 8, 32):
+        b = 16
+        el, ph = timed_primal(cabcd, torch, A, yd, 1e-5, b, s, 20, 2, 2002, dual=True)
+        g = ph["gram"]["ms"] / max(ph["gram"]["launches"], 1)
+        # algorithmic Gram work of the sampled rows: 2 sum_c nnz_c(I)^2 flops over the
+        # nnz of the gathered rows (12 bytes each), averaged over the timed steps
+        idx = cabcd.sample(2002, 2 * s, 20 * s, b, 20000).cpu().numpy().reshape(20, s * b)
+        fl, by = [], []
+        for blk in idx:
+            cols = np.concatenate([colidx[rowptr[i]:rowptr[i + 1]] for i in blk])
+            cnt = np.bincount(cols)
+            fl.append(2.0 * float((cnt.astype(np.float64) ** 2).sum()))
+            by.append(12.0 * len(cols))
+        rec[f"sparse_dual_s{s}"] = {
+            "ms_per_step": round(el / 20 * 1e3, 4), "gram_ms": round(g, 4),
+            "gram_gflops": round(np.mean(fl) / (g * 1e-3) / 1e9, 2),
+            "gram_gbs": round(np.mean(by) / (g * 1e-3) / 1e9, 2)}
+        log(f"sparse dual s={s}: {rec[f'sparse_dual_s{s}']}")
+    return rec
+
+
+def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, lam=1e-4,
+                chunk=4, max_steps=400):
+    log(f"time-to-{tol:g}: generating X ({d} x {n}) on the GPU")
+    X, y, _, _ = synth.colscaled_ridge(d, n, 1003, device="cuda")
+    torch.cuda.synchronize()
+    res = {"workload": f"column-scaled dense primal, d={d} n={n} lambda={lam:g} b={b} s={s}, "
+                       f"exact residual + objective every {chunk} outer steps",
+           "tol": tol}
+
+    def closed_form_fstar(Xh):
+        M = Xh @ Xh.t()
+        M /= n
+        M.diagonal().add_(lam)
+        L = torch.linalg.cholesky(M)
+        rhs = (Xh @ y) / n
+        w = torch.cholesky_solve(rhs[:, None], L)[:, 0]
+        del M, L
+        f, _ = cabcd.primal_objective(Xh, y, lam, w)
+        return f.item()
+
+    def run(A, fstar):
+        w = torch.zeros(d, dtype=torch.float64, device="cuda")
+        r = torch.empty(n, dtype=torch.float64, device="cuda")
+        trace = torch.zeros(1, dtype=torch.float64, device="cuda")
+        # r_0 = X^T w_0 - y outside the timed region (a residual the caller holds)
+        cabcd.primal_bcd(A, y, lam, b, s, 0, 7, w=w, r=r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, err = 0, float("inf")
+        while steps < max_steps:
+            cabcd.primal_bcd(A, y, lam, b, s, chunk * s, 7, w=w, r=r, h0=steps * s,
+                             flags=cabcd.FLAG_STATE_VALID, resid_every=chunk,
+                             monitor_every=chunk, trace=trace)
+            steps += chunk
+            err = (trace.item() - fstar) / fstar
+            if err <= tol:
+                break
+        return time.perf_counter() - t0, steps, err
+
+    for name, code in (("bf16", cabcd.BF16), ("fp8", cabcd.FP8_E4M3)):
+        Q = cabcd.quantize(X, code)
+        Xh = Q.dequantize()
+        fstar = closed_form_fstar(Xh)
+        t64, st64, e64 = run(Xh, fstar)
+        del Xh
+        torch.cuda.empty_cache()
+        tq, stq, eq = run(Q, fstar)
+        res[name] = {"fp64_on_xhat_s": round(t64, 5), "fp64_outer_steps": st64,
+                     "fp64_rel_err": e64,
+                     "mixed_s": round(tq, 5), "mixed_outer_steps": stq, "mixed_rel_err": eq,
+                     "speedup": round(t64 / tq, 3)}
+        log(f"time-to-tol {name}: {res[name]}")
+        del Q
+        torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (no collectives); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1612_04003_amd as cabcd
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cabcd.load()
+    out, X, y = headline(args, cabcd, torch, synth)
     if not args.no_cpu_baseline:
-        print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(X, y, lam, b, s, args.cpu_steps, seed)
+        log("CPU baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(X, y, args.lam, args.b, args.s, args.cpu_steps, 2001)
     else:
         out["cpu_baseline"] = None
+    if not args.no_extra:
+        out["extra"] = extra_records(args, cabcd, torch, synth, X, y)
+    del X, y
+    torch.cuda.empty_cache()
+    if not args.no_tol:
+        out["time_to_tol"] = time_to_tol(cabcd, torch, synth)
     print(json.dumps(out), flush=True)
 
 

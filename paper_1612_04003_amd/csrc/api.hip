@@ -472,8 +472,13 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     // r = X^T w - y
     return mat_scatter(M, nullptr, rows, coord, 1.0, y, -1.0, false, comp, B.scratch, st);
   };
-  auto monitor = [&](int64_t slot) -> hipError_t {
+  // f(w) at a monitor point.  fresh: the primal residual comp was recomputed
+  // exactly in this outer step, so it is used instead of another full pass.
+  auto monitor = [&](int64_t slot, bool fresh) -> hipError_t {
     hipError_t he;
+    if (!dual && fresh)
+      return launch_objective(comp, cols, 0.5 / n, coord, rows, 0.5 * lambda, o.trace + slot,
+                              B.obj, B.status, st);
     if (dual) {   // f(w) with r = X^T w - y computed from the X^T layout
       he = mat_rowdot(M, comp, y, -1.0, B.rtmp, st);
       if (he != hipSuccess) return he;
@@ -531,11 +536,11 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     }));
     h += sk;
     ++k;
-    if (o.resid_every > 0 && k % o.resid_every == 0)
-      HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
+    const bool fresh = o.resid_every > 0 && k % o.resid_every == 0;
+    if (fresh) HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
     if (o.monitor_every > 0 && k % o.monitor_every == 0 && slot < o.trace_len) {
       const int64_t sl = slot++;
-      HIP_TRY(timer.run(CABCD_PHASE_MONITOR, [&] { return monitor(sl); }));
+      HIP_TRY(timer.run(CABCD_PHASE_MONITOR, [&] { return monitor(sl, fresh); }));
     }
   }
   const cabcd_status fs = finish(st, B.status, (o.flags & CABCD_FLAG_ASYNC) != 0);
