@@ -233,6 +233,97 @@ cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y,
 cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha,
                                   double lambda, double* w, void* stream);
 
+/*
+ * Batched primal CA-BCD: many independent ridge problems (Alg. 2 each, with
+ * its own X, y, lambda, b, s and seed) advanced together.  One ROUND runs one
+ * outer step of every problem that is still running; a round is ONE persistent
+ * kernel launch for the whole batch (Gram slabs of all problems from one work
+ * queue; the last slab of a problem to finish sums its partials, runs the
+ * fused solve and records the step).  The companion update r += Y^T delta of a
+ * step is applied by the next round's slabs on their own columns.  Every
+ * monitor_every rounds a second persistent launch recomputes r = X^T w - y
+ * exactly and the objective f(w), and retires problems that reached f_target.
+ * Both launches are captured once into a hipGraph and replayed.
+ *
+ * Per problem, the iterates are those of cabcd_primal_bcd with the same X, y,
+ * lambda, b, s, seed and H (the same blocks), up to rounding order.
+ */
+typedef struct cabcd_problem {
+  cabcd_matrix X;            /* dense F64, rows d = features, cols n = samples     */
+  const double* y;           /* n labels                                           */
+  double lambda;             /* > 0                                                */
+  int32_t b;                 /* block size, 1..16; 0: chosen by the autotuner      */
+  int32_t s;                 /* unrolling, s*b <= 256; 0: chosen by the autotuner  */
+  uint64_t seed;             /* sampler seed (blocks over [0, d))                  */
+  int64_t H;                 /* inner-iteration budget; <= 0: unlimited            */
+  double f_target;           /* > 0: retire at the first monitor point with
+                                f(w) <= f_target; otherwise never                  */
+  double* w;                 /* d: in w_0, out w                                   */
+  double* r;                 /* n: out X^T w - y (exact after a monitor point,
+                                maintained by the recurrence otherwise)            */
+} cabcd_problem;
+
+#define CABCD_BATCH_NO_GRAPH 1u    /* launch every kernel directly (no hipGraph)   */
+
+typedef struct cabcd_batch_opts {
+  int32_t monitor_every;     /* rounds between exact recomputations (default 4;
+                                0: never, then only the budgets H end problems)    */
+  uint32_t flags;            /* CABCD_BATCH_*                                      */
+} cabcd_batch_opts;
+
+/* What the plan chose for one problem and where it stands. */
+typedef struct cabcd_batch_info {
+  int32_t b, s;              /* block size and unrolling in use                    */
+  int32_t nslab;             /* column slabs (work items) per round                */
+  int32_t active;            /* 1 while the problem still runs                     */
+  int64_t chunk;             /* columns per slab                                   */
+  int64_t h;                 /* inner iterations done                              */
+  int64_t steps;             /* outer steps done                                   */
+  double objective;          /* f(w) at the last monitor point (NaN before one)    */
+  int32_t status;            /* CABCD_OK, CABCD_ENOTSPD or CABCD_ENONFINITE        */
+  int32_t reserved;
+} cabcd_batch_info;
+
+typedef struct cabcd_batch_plan* cabcd_batch;
+
+/*
+ * Plan a batch of P problems: validate, choose b and s where they are 0 (the
+ * autotuner balances the rounds each problem needs per pass over its
+ * coordinates against a cost model of the round), choose the column slabs,
+ * allocate the plan's workspace (hipMalloc; released by cabcd_batch_destroy),
+ * compute r = X^T w_0 - y and f(w_0), and capture the hipGraphs.  The problem
+ * arrays stay owned by the caller and must outlive the plan.  Synchronises
+ * `stream`.  *out is NULL on failure.
+ */
+cabcd_status cabcd_batch_create(const cabcd_problem* problems, int32_t P,
+                                const cabcd_batch_opts* opts, void* stream,
+                                cabcd_batch* out);
+
+/*
+ * Run `rounds` rounds (>= 0).  On return r of every problem holds its current
+ * residual (a pending companion update is flushed).  If active is non-NULL the
+ * stream is synchronised and *active receives the number of problems still
+ * running; device-detected errors are then returned (the first problem with a
+ * non-OK status).
+ */
+cabcd_status cabcd_batch_run(cabcd_batch plan, int64_t rounds, void* stream,
+                             int32_t* active);
+
+/* Copy the state of problem p (synchronises `stream`). */
+cabcd_status cabcd_batch_query(cabcd_batch plan, int32_t p, cabcd_batch_info* info,
+                               void* stream);
+
+/* Release the plan (synchronises the device first).  NULL is ignored. */
+cabcd_status cabcd_batch_destroy(cabcd_batch plan);
+
+/*
+ * One-shot batched solve: plan, run until no problem is active or max_rounds
+ * rounds have run, destroy.  Returns the first error found.
+ */
+cabcd_status cabcd_primal_bcd_batched(const cabcd_problem* problems, int32_t P,
+                                      int64_t max_rounds, const cabcd_batch_opts* opts,
+                                      void* stream);
+
 /* Workspace bytes a call of cabcd_primal_bcd / cabcd_dual_bcd with these
  * arguments needs when opts->workspace is supplied. */
 size_t cabcd_workspace_bytes(const cabcd_matrix* A, int32_t b, int32_t s);

@@ -49,6 +49,26 @@ class Opts(ctypes.Structure):
                 ("timing", ctypes.POINTER(ctypes.c_double))]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("X", Matrix), ("y", ctypes.c_void_p), ("lam", ctypes.c_double),
+                ("b", ctypes.c_int32), ("s", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("H", ctypes.c_int64), ("f_target", ctypes.c_double),
+                ("w", ctypes.c_void_p), ("r", ctypes.c_void_p)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("monitor_every", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_int32), ("s", ctypes.c_int32), ("nslab", ctypes.c_int32),
+                ("active", ctypes.c_int32), ("chunk", ctypes.c_int64), ("h", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("objective", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+BATCH_NO_GRAPH = 1
+
 NPHASES = 7
 PHASES = ["sample", "gram", "reduce", "solve", "update", "recompute", "monitor"]
 
@@ -79,6 +99,13 @@ def load():
         "cabcd_dual_to_primal": (I32, [MP, P, D, P, P]),
         "cabcd_workspace_bytes": (ctypes.c_size_t, [MP, I32, I32]),
         "cabcd_quantize": (I32, [P, I64, I64, I64, I32, P, I64, P, P]),
+        "cabcd_batch_create": (I32, [ctypes.POINTER(Problem), I32, ctypes.POINTER(BatchOpts), P,
+                                     ctypes.POINTER(P)]),
+        "cabcd_batch_run": (I32, [P, I64, P, ctypes.POINTER(I32)]),
+        "cabcd_batch_query": (I32, [P, I32, ctypes.POINTER(BatchInfo), P]),
+        "cabcd_batch_destroy": (I32, [P]),
+        "cabcd_primal_bcd_batched": (I32, [ctypes.POINTER(Problem), I32, I64,
+                                           ctypes.POINTER(BatchOpts), P]),
         "cabcd_last_error": (ctypes.c_char_p, []),
         "cabcd_version": (ctypes.c_char_p, []),
     }
@@ -95,7 +122,8 @@ def exported_symbols():
     return ["cabcd_opts_init", "cabcd_sample", "cabcd_gram", "cabcd_primal_bcd",
             "cabcd_dual_bcd", "cabcd_primal_objective", "cabcd_primal_objective_t",
             "cabcd_dual_to_primal", "cabcd_workspace_bytes", "cabcd_last_error",
-            "cabcd_version", "cabcd_quantize"]
+            "cabcd_version", "cabcd_quantize", "cabcd_batch_create", "cabcd_batch_run",
+            "cabcd_batch_query", "cabcd_batch_destroy", "cabcd_primal_bcd_batched"]
 
 
 def _check(status):
@@ -351,3 +379,96 @@ def dual_to_primal(XT, alpha, lam, w=None):
 def workspace_bytes(A, b, s):
     M = describe(A)
     return int(load().cabcd_workspace_bytes(ctypes.byref(M), b, s))
+
+
+# ------------------------------------------------------------------ batched
+
+
+def _problems(problems):
+    """ctypes array of cabcd_problem from dicts with keys X, y, lam and optional
+    b, s (0: autotuned), seed, H (<= 0: unlimited), f_target (<= 0: none), w, r."""
+    arr = (Problem * len(problems))()
+    keep = []
+    for i, q in enumerate(problems):
+        X, y = q["X"], q["y"]
+        d, n = X.shape
+        _need(y, torch.float64, f"problems[{i}].y", n)
+        w = q.get("w")
+        if w is None:
+            w = torch.zeros(d, dtype=torch.float64, device=X.device)
+            q["w"] = w
+        _need(w, torch.float64, f"problems[{i}].w", d)
+        r = q.get("r")
+        if r is None:
+            r = torch.empty(n, dtype=torch.float64, device=X.device)
+            q["r"] = r
+        _need(r, torch.float64, f"problems[{i}].r", n)
+        M = describe(X)
+        arr[i].X = M
+        arr[i].y, arr[i].lam = y.data_ptr(), float(q["lam"])
+        arr[i].b, arr[i].s = int(q.get("b", 0)), int(q.get("s", 0))
+        arr[i].seed, arr[i].H = int(q.get("seed", 0)), int(q.get("H", 0))
+        arr[i].f_target = float(q.get("f_target", 0.0))
+        arr[i].w, arr[i].r = w.data_ptr(), r.data_ptr()
+        keep.append((M, X, y, w, r))
+    return arr, keep
+
+
+class Batch:
+    """A plan of many primal ridge problems solved by batched CA-BCD: one
+    persistent launch per round for the whole batch, captured in a hipGraph.
+    `problems` is a list of dicts (see _problems); w and r are created when
+    absent and written in place (q["w"], q["r"])."""
+
+    def __init__(self, problems, monitor_every=4, graph=True):
+        self.problems = problems
+        arr, self._keep = _problems(problems)
+        o = BatchOpts()
+        o.monitor_every, o.flags = monitor_every, 0 if graph else BATCH_NO_GRAPH
+        h = ctypes.c_void_p()
+        _check(load().cabcd_batch_create(arr, len(problems), ctypes.byref(o), _stream(),
+                                         ctypes.byref(h)))
+        self._h = h
+
+    def run(self, rounds, sync=True):
+        """Run `rounds` rounds; with sync, return the number of active problems."""
+        act = ctypes.c_int32(-1)
+        _check(load().cabcd_batch_run(self._h, rounds, _stream(),
+                                      ctypes.byref(act) if sync else None))
+        return act.value if sync else None
+
+    def info(self, p):
+        i = BatchInfo()
+        _check(load().cabcd_batch_query(self._h, p, ctypes.byref(i), _stream()))
+        return {"b": i.b, "s": i.s, "nslab": i.nslab, "active": bool(i.active),
+                "chunk": i.chunk, "h": i.h, "steps": i.steps, "objective": i.objective,
+                "status": i.status}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            load().cabcd_batch_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def primal_bcd_batched(problems, max_rounds, monitor_every=4, graph=True):
+    """One-shot batched solve (plan, run until no problem is active or
+    max_rounds, release).  Results are written to each problem's w and r."""
+    arr, keep = _problems(problems)
+    o = BatchOpts()
+    o.monitor_every, o.flags = monitor_every, 0 if graph else BATCH_NO_GRAPH
+    _check(load().cabcd_primal_bcd_batched(arr, len(problems), max_rounds, ctypes.byref(o),
+                                           _stream()))
+    del keep
+    return problems

@@ -1,0 +1,886 @@
+// Batched primal CA-BCD: many independent ridge problems (Alg. 2 each) advanced
+// together, one persistent launch per outer step ("round") for the whole batch.
+//
+// A round is a work queue of column slabs (problem p, slab q).  A workgroup
+// that takes a slab
+//   1. draws the blocks of the problem's current outer step (the sampler is
+//      keyed by (seed, h), so every slab of the problem gets the same ones);
+//   2. applies the problem's pending companion update r += Y_prev^T delta_prev
+//      on the slab's columns (the deferred residual update of the previous
+//      outer step, Alg. 2), so the update's HBM traffic lands in the same pass
+//      as the next Gram instead of a pass of its own;
+//   3. computes the slab's Gram partial and Y r partial (the split-K slab of the
+//      one-problem Gram kernel);
+//   4. counts its arrival; the workgroup that completes the problem's set of
+//      slabs sums the partials in slab order (deterministic), runs the fused
+//      solve of the s blocks (Cholesky/recurrence, w[idx] += delta) and records
+//      the step.  No workgroup ever waits for another.
+// A second persistent kernel recomputes r = X^T w - y exactly and f(w) (the
+// periodic full residual of the paper's stopping discussion) or flushes the
+// pending update.  The plan captures both into a hipGraph.
+#include "gram_dev.h"
+#include "solve_dev.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace cabcd {
+namespace {
+
+constexpr int kBT = 512;           // threads of the batched kernels (8 waves)
+constexpr int kBMaxRows = 256;     // s*b of one problem (Gram classes nb <= 16)
+constexpr int kBMaxB = 16;
+constexpr int kBMaxSlabs = 64;
+
+struct BProb {                     // constant per problem (device copy)
+  const double* A;
+  int64_t ld, d, n;
+  const double* y;
+  double* w;
+  double* r;
+  double lambda;
+  double f_target;
+  uint64_t seed;
+  int64_t H;                       // inner-iteration budget (INT64_MAX: none)
+  int64_t chunk;                   // columns per slab
+  int b, s, bp, nb;
+  int nslab, aligned;
+  double* partials;                // nslab x (nblk*256 + 16 nb)
+  double* G;                       // (s b)^2
+  double* Yu;                      // s b
+  double* delta;                   // s b: the last step's delta
+  double* objp;                    // nslab partial sums of r^2
+};
+
+struct BState {                    // mutable per problem
+  int64_t h;                       // inner iterations done
+  int64_t h_prev;                  // first iteration of the step with a pending update
+  int64_t steps;                   // outer steps done
+  double obj;                      // f(w) at the last monitor point
+  int m_prev;                      // rows of the pending companion update (0: none)
+  int active;                      // still iterating
+  int arrive;                      // slab arrivals in the current launch
+  int status;                      // DeviceStatus (sticky)
+  int fresh;                       // r exact and obj current
+  int pad[3];
+};
+
+struct BItem {
+  int prob, slab;
+};
+
+struct BQueue {
+  int ticket, exited;
+};
+
+// -------------------------------------------------------------- device helpers
+
+// out[k] = (base ? beta base[k] : out[k]) + sum_{q < mq} A[row(q)][k] coef[q],
+// k in [k0, k1), row(q) = rows ? rows[q] : q; the sum runs in q order.
+// Returns this thread's sum of the new out[k]^2.
+__device__ __forceinline__ double slab_rows_dot(const double* __restrict__ A, int64_t ld,
+                                                int64_t k0, int64_t k1, const int32_t* rows,
+                                                const double* coef, int mq,
+                                                const double* __restrict__ base, double beta,
+                                                double* __restrict__ out, int aligned) {
+  const gptr<const double> Ag = glb(A);
+  const gptr<const double> bg = glb(base);
+  const gptr<double> og = glb(out);
+  double ss = 0.0;
+  for (int64_t k = k0 + 2 * (int64_t)threadIdx.x; k < k1; k += 2 * kBT) {
+    const bool two = k + 1 < k1;
+    double a0, a1 = 0.0;
+    if (base != nullptr) {
+      a0 = beta * bg[k];
+      if (two) a1 = beta * bg[k + 1];
+    } else {
+      a0 = og[k];
+      if (two) a1 = og[k + 1];
+    }
+    int q = 0;
+    for (; q + 8 <= mq; q += 8) {
+      double2 v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t row = rows != nullptr ? rows[q + j] : q + j;
+        v[j] = gdev::load2(Ag + row * ld, k, k1, aligned != 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double c = coef[q + j];
+        a0 = fma(v[j].x, c, a0);
+        a1 = fma(v[j].y, c, a1);
+      }
+    }
+    for (; q < mq; ++q) {
+      const int64_t row = rows != nullptr ? rows[q] : q;
+      const double2 v = gdev::load2(Ag + row * ld, k, k1, aligned != 0);
+      a0 = fma(v.x, coef[q], a0);
+      a1 = fma(v.y, coef[q], a1);
+    }
+    og[k] = a0;
+    if (two) og[k + 1] = a1;
+    ss += a0 * a0 + a1 * a1;
+  }
+  return ss;
+}
+
+// Workgroup sum in a fixed order (valid in thread 0).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBT / 64; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// Wave-uniform copies of values that steer control flow around barriers.  The
+// values are equal in every thread already, but the compiler cannot prove it
+// for data read from memory; a loop whose exit it considers divergent gets
+// restructured so that the threads of a wave leave it in different
+// iterations, which breaks the workgroup barriers inside the loop.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <class T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  return reinterpret_cast<T*>((uintptr_t)uni64((int64_t)(uintptr_t)p));
+}
+
+// The Gram slabs and solves are separate (non-inlined) functions so that each
+// gets its own register allocation instead of one allocation over every
+// variant of the persistent loop.  They take the workgroup's dynamic LDS from
+// their own extern declaration, so their LDS accesses stay ds_* instructions.
+template <int NB>
+__device__ __noinline__ void gram_call(const double* A, int64_t ld, int64_t k0, int64_t k1,
+                                       const int32_t* idx, int m, const double* u, double* part,
+                                       int aligned) {
+  extern __shared__ __attribute__((aligned(16))) double dyn_sm[];
+  // Arguments of a non-inlined function are per-lane values to the compiler;
+  // the tile loop's barriers need its bounds to be visibly uniform.
+  gdev::gram_slab<NB, 2>(uni_ptr(A), uni64(ld), uni64(k0), uni64(k1), uni_ptr(idx), uni(m),
+                         uni_ptr(u), uni_ptr(part), uni(aligned), dyn_sm);
+}
+
+__device__ __forceinline__ void gram_any(int nb, const double* A, int64_t ld, int64_t k0,
+                                         int64_t k1, const int32_t* idx, int m, const double* u,
+                                         double* part, int aligned) {
+  switch (nb) {
+    case 1: gram_call<1>(A, ld, k0, k1, idx, m, u, part, aligned); break;
+    case 2: gram_call<2>(A, ld, k0, k1, idx, m, u, part, aligned); break;
+    case 4: gram_call<4>(A, ld, k0, k1, idx, m, u, part, aligned); break;
+    case 8: gram_call<8>(A, ld, k0, k1, idx, m, u, part, aligned); break;
+    default: gram_call<16>(A, ld, k0, k1, idx, m, u, part, aligned); break;
+  }
+}
+
+template <int BP, int PF>
+__device__ __noinline__ void solve_call(const SolveArgs& in) {
+  extern __shared__ __attribute__((aligned(16))) double dyn_sm[];
+  SolveArgs a;
+  a.G = uni_ptr(in.G);
+  a.Yu = uni_ptr(in.Yu);
+  a.idx = uni_ptr(in.idx);
+  a.y = uni_ptr(in.y);
+  a.x = uni_ptr(in.x);
+  a.delta = uni_ptr(in.delta);
+  a.status = uni_ptr(in.status);
+  a.m = uni(in.m);
+  a.b = uni(in.b);
+  a.s = uni(in.s);
+  a.mode = uni(in.mode);
+  a.lambda = __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, in.lambda)));
+  a.n = __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, in.n)));
+  sdev::solve_block<BP, PF, kBT>(a, dyn_sm);
+}
+
+__device__ __forceinline__ void solve_any(int bp, const SolveArgs& a) {
+  switch (bp) {
+    case 1: solve_call<1, 8>(a); break;
+    case 2: solve_call<2, 8>(a); break;
+    case 4: solve_call<4, 8>(a); break;
+    case 8: solve_call<8, 8>(a); break;
+    default: solve_call<16, 4>(a); break;
+  }
+}
+
+// Next work item of the launch's queue (the same value in every thread).  The
+// persistent loops are written as
+//   it = next_item(); while (it < nitems) { do { ... } while (false); it = next_item(); }
+// with every early exit a `break` out of the do-block, so that all threads run
+// the same barriers in the same order and the only loop exit is uniform.
+__device__ __forceinline__ int next_item(BQueue* Q, int* slot) {
+  __syncthreads();   // every thread is done with the previous item and the slot
+  if (threadIdx.x == 0) *slot = atomicAdd(&Q->ticket, 1);
+  __syncthreads();
+  return uni(*slot);
+}
+
+// Publish this workgroup's global writes and count its arrival at problem st;
+// true (in every thread) for the workgroup that completes the set of nslab.
+__device__ __forceinline__ bool arrive_last(BState* st, int nslab, int* slot) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) *slot = atomicAdd(&st->arrive, 1) == nslab - 1 ? 1 : 0;
+  __syncthreads();
+  const bool last = uni(*slot) != 0;
+  if (last) __threadfence();   // acquire the other workgroups' writes
+  return last;
+}
+
+// The last workgroup to leave resets the queue for the next launch.
+__device__ __forceinline__ void queue_exit(BQueue* Q) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&Q->exited, 1) == (int)gridDim.x - 1) {
+      atomicExch(&Q->ticket, 0);
+      atomicExch(&Q->exited, 0);
+    }
+  }
+}
+
+// ------------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict__ P,
+                                                         BState* __restrict__ S,
+                                                         const BItem* __restrict__ items,
+                                                         int nitems, BQueue* Q, int area) {
+  extern __shared__ __attribute__((aligned(16))) double sm[];
+  int32_t* icur = reinterpret_cast<int32_t*>(sm + area);
+  int32_t* iprev = icur + kBMaxRows;
+  double* dprev = reinterpret_cast<double*>(iprev + kBMaxRows);
+  int* ctl = reinterpret_cast<int*>(dprev + kBMaxRows);
+  const int tid = threadIdx.x;
+
+  for (int it = next_item(Q, ctl); it < nitems; it = next_item(Q, ctl)) do {
+    const BItem item = items[it];
+    const BProb& pr = P[item.prob];
+    BState* st = S + item.prob;
+    if (uni(st->active) == 0) break;
+    const int64_t h = uni64(st->h);
+    const int64_t hp = uni64(st->h_prev);
+    const int mp = uni(st->m_prev);
+    const int sk = (int)std::min((int64_t)pr.s, pr.H - h);
+    const int m = sk * pr.b;
+    const int64_t k0 = (int64_t)item.slab * pr.chunk;
+    const int64_t k1 = std::min(pr.n, k0 + pr.chunk);
+
+    if (tid < sk) smp::sample_block(pr.seed, h + tid, pr.b, pr.d, icur + tid * pr.b);
+    if (mp > 0) {
+      if (tid < mp / pr.b) smp::sample_block(pr.seed, hp + tid, pr.b, pr.d, iprev + tid * pr.b);
+      for (int q = tid; q < mp; q += kBT) dprev[q] = glb(pr.delta)[q];
+    }
+    __syncthreads();
+    if (mp > 0) {
+      // deferred companion update of the previous outer step, this slab's columns
+      slab_rows_dot(pr.A, pr.ld, k0, k1, iprev, dprev, mp, nullptr, 0.0, pr.r, pr.aligned);
+      __syncthreads();   // the Gram below reads these r values back
+    }
+    const int64_t pstride = (int64_t)(pr.nb * (pr.nb + 1) / 2) * 256 + 16 * pr.nb;
+    gram_any(pr.nb, pr.A, pr.ld, k0, k1, icur, m, pr.r, pr.partials + item.slab * pstride,
+             pr.aligned);
+    if (!arrive_last(st, pr.nslab, ctl + 1)) break;
+
+    // Last slab of this problem: Gov (overlap-augmented, Alg. 2 scale 1/n and
+    // shift lambda), then the fused solve and w[idx] += delta.
+    gdev::reduce_wg<kBT>(pr.partials, pr.nslab, pr.nb, icur, m, 1.0 / (double)pr.n, pr.lambda,
+                         pr.G, pr.Yu, 0, nullptr);
+    __syncthreads();
+    SolveArgs a;
+    a.G = pr.G;
+    a.Yu = pr.Yu;
+    a.idx = icur;
+    a.y = nullptr;
+    a.x = pr.w;
+    a.delta = pr.delta;
+    a.status = &st->status;
+    a.m = m;
+    a.b = pr.b;
+    a.s = sk;
+    a.mode = 0;
+    a.lambda = pr.lambda;
+    a.n = (double)pr.n;
+    solve_any(pr.bp, a);
+    __syncthreads();
+    if (tid == 0) {
+      st->arrive = 0;
+      st->h_prev = h;
+      st->m_prev = m;
+      st->h = h + sk;
+      st->steps += 1;
+      st->fresh = 0;
+      if (h + sk >= pr.H) st->active = 0;
+    }
+  } while (false);
+  queue_exit(Q);
+}
+
+// MODE 0: r = X^T w - y exactly and f(w) = ||r||^2/(2n) + lambda/2 ||w||^2;
+//         retire the problem when f(w) <= f_target.
+// MODE 1: apply the pending companion update only.
+template <int MODE>
+__global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict__ P,
+                                                        BState* __restrict__ S,
+                                                        const BItem* __restrict__ items,
+                                                        int nitems, BQueue* Q) {
+  __shared__ int32_t iprev[kBMaxRows];
+  __shared__ double dprev[kBMaxRows];
+  __shared__ double red[kBT / 64];
+  __shared__ int ctl[2];
+  const int tid = threadIdx.x;
+
+  for (int it = next_item(Q, ctl); it < nitems; it = next_item(Q, ctl)) do {
+    const BItem item = items[it];
+    const BProb& pr = P[item.prob];
+    BState* st = S + item.prob;
+    if (MODE == 0 ? uni(st->fresh) != 0 : uni(st->m_prev) == 0) break;
+    const int64_t k0 = (int64_t)item.slab * pr.chunk;
+    const int64_t k1 = std::min(pr.n, k0 + pr.chunk);
+    if (MODE == 0) {
+      double ss = slab_rows_dot(pr.A, pr.ld, k0, k1, nullptr, pr.w, (int)pr.d, pr.y, -1.0,
+                                pr.r, pr.aligned);
+      ss = block_sum(ss, red);
+      if (tid == 0) glb(pr.objp)[item.slab] = ss;
+    } else {
+      const int mp = uni(st->m_prev);
+      const int64_t hp = uni64(st->h_prev);
+      if (tid < mp / pr.b) smp::sample_block(pr.seed, hp + tid, pr.b, pr.d, iprev + tid * pr.b);
+      for (int q = tid; q < mp; q += kBT) dprev[q] = glb(pr.delta)[q];
+      __syncthreads();
+      slab_rows_dot(pr.A, pr.ld, k0, k1, iprev, dprev, mp, nullptr, 0.0, pr.r, pr.aligned);
+    }
+    if (!arrive_last(st, pr.nslab, ctl + 1)) break;
+    if (MODE == 0) {
+      double ww = 0.0;
+      const gptr<const double> wg = glb(pr.w);
+      for (int64_t i = tid; i < pr.d; i += kBT) ww = fma(wg[i], wg[i], ww);
+      ww = block_sum(ww, red);
+      if (tid == 0) {
+        double rr = 0.0;
+        for (int q = 0; q < pr.nslab; ++q) rr += glb(pr.objp)[q];
+        const double f = rr / (2.0 * (double)pr.n) + 0.5 * pr.lambda * ww;
+        st->obj = f;
+        if (!isfinite(f) && st->status == DEV_OK) st->status = DEV_NONFINITE;
+        st->fresh = 1;
+        st->m_prev = 0;
+        if ((pr.f_target > 0.0 && f <= pr.f_target) || !isfinite(f)) st->active = 0;
+        st->arrive = 0;
+      }
+    } else if (tid == 0) {
+      st->m_prev = 0;
+      st->arrive = 0;
+    }
+  } while (false);
+  queue_exit(Q);
+}
+
+// ------------------------------------------------------------------ planning
+
+int pow2_at_least(int b) {
+  int p = 1;
+  while (p < b) p *= 2;
+  return p;
+}
+
+int nb_of(int sb) {
+  int nb = 1;
+  while (16 * nb < sb) nb *= 2;
+  return nb;
+}
+
+int64_t pstride_of(int nb) { return (int64_t)(nb * (nb + 1) / 2) * 256 + 16 * nb; }
+
+// Cost model of one round (seconds), with rates measured on MI355X with the
+// one-problem kernels: the FP64 Gram at sb = 256 ran at 48 TFLOP/s over 256
+// CUs, the streaming passes at about 5 TB/s, one workgroup reads its partials
+// at about 60 GB/s, and the fused solve costs about 1.5 us per block.
+constexpr double kCuF64 = 48e12 / 256;
+constexpr double kCuBw = 5.0e12 / 256;
+constexpr double kWgBw = 60e9;
+constexpr double kSolveBlock = 1.5e-6;
+constexpr double kRoundFixed = 10e-6;
+
+// CU-seconds of one problem's slabs in one round (Gram of the padded rows and
+// the two passes over the gathered rows: Gram and deferred update).
+double slab_work(int sb, int64_t cols) {
+  const int sbp = 16 * nb_of(sb);
+  const double flops = (double)cols * sbp * (sbp + 1);
+  const double bytes = 16.0 * (double)cols * sb;
+  return std::max(flops / kCuF64, bytes / kCuBw);
+}
+
+int auto_b(int64_t d) {
+  if (d >= 64) return 16;
+  if (d >= 16) return 8;
+  if (d >= 8) return 4;
+  return (int)std::max<int64_t>(1, d);
+}
+
+struct Pick {
+  int b, s, nslab;
+  int64_t chunk;
+  double crit;
+};
+
+// (b, s) of every problem for a target of `rp` rounds per pass over the
+// coordinates, slabs sized so a round has about four items per CU, and the
+// predicted time of one pass (rounds per pass x round time).
+double plan_candidate(const std::vector<cabcd_problem>& pb, double rp, int cus,
+                      std::vector<Pick>& out) {
+  const size_t P = pb.size();
+  out.assign(P, Pick{});
+  double W = 0.0;
+  for (size_t p = 0; p < P; ++p) {
+    const int64_t d = pb[p].X.rows;
+    int b = pb[p].b, s = pb[p].s;
+    if (b == 0) b = s == 0 ? auto_b(d) : std::min(auto_b(d), kBMaxRows / s);
+    b = (int)std::min<int64_t>(b, d);
+    if (s == 0) {
+      const int smax = std::min(32, kBMaxRows / b);
+      s = (int)std::ceil((double)d / (b * rp));
+      s = std::max(1, std::min(s, smax));
+    }
+    out[p].b = b;
+    out[p].s = s;
+    W += slab_work(b * s, pb[p].X.cols);
+  }
+  const double target = std::max(W / (4.0 * cus), 20e-6);
+  double crit = 0.0, passes = 0.0;
+  for (size_t p = 0; p < P; ++p) {
+    const int sb = out[p].b * out[p].s;
+    const int nb = nb_of(sb);
+    const int kt = 256 / nb;
+    const int64_t n = pb[p].X.cols;
+    const double wp = slab_work(sb, n);
+    int64_t nslab = (int64_t)std::ceil(wp / target);
+    nslab = std::max<int64_t>(1, std::min<int64_t>(nslab, kBMaxSlabs));
+    nslab = std::min<int64_t>(nslab, (n + kt - 1) / kt);
+    int64_t chunk = (n + nslab - 1) / nslab;
+    chunk = (chunk + kt - 1) / kt * kt;
+    nslab = (n + chunk - 1) / chunk;
+    out[p].chunk = chunk;
+    out[p].nslab = (int)nslab;
+    out[p].crit = wp / nslab + nslab * pstride_of(nb) * 8.0 / kWgBw + out[p].s * kSolveBlock;
+    crit = std::max(crit, out[p].crit);
+    passes = std::max(passes, (double)pb[p].X.rows / sb);
+  }
+  const double T = std::max(W / cus, crit) + kRoundFixed;
+  return passes * T;
+}
+
+struct Workspace {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+}  // namespace cabcd
+
+// ---------------------------------------------------------------- the plan
+
+struct cabcd_batch_plan {
+  int device = 0;
+  int P = 0;
+  std::vector<cabcd::BProb> probs;
+  cabcd::BProb* dP = nullptr;
+  cabcd::BState* dS = nullptr;
+  cabcd::BItem* dI = nullptr;
+  cabcd::BQueue* dQ = nullptr;
+  void* mem = nullptr;
+  int nitems = 0;
+  int area = 0;            // doubles of the step kernel's shared Gram/solve area
+  size_t step_lds = 0;
+  int grid_step = 1, grid_aux = 1;
+  int monitor_every = 4;
+  uint32_t flags = 0;
+  int64_t rounds_done = 0;
+  bool pending = false;    // a step ran since the last recompute / flush
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_rounds = 0;
+};
+
+namespace cabcd {
+namespace {
+
+hipError_t launch_step(cabcd_batch_plan* B, hipStream_t st) {
+  hipLaunchKernelGGL(batch_step_kernel, dim3(B->grid_step), dim3(kBT), B->step_lds, st, B->dP,
+                     B->dS, B->dI, B->nitems, B->dQ, B->area);
+  return hipGetLastError();
+}
+
+hipError_t launch_aux(cabcd_batch_plan* B, int mode, hipStream_t st) {
+  if (mode == 0)
+    hipLaunchKernelGGL(batch_aux_kernel<0>, dim3(B->grid_aux), dim3(kBT), 0, st, B->dP, B->dS,
+                       B->dI, B->nitems, B->dQ);
+  else
+    hipLaunchKernelGGL(batch_aux_kernel<1>, dim3(B->grid_aux), dim3(kBT), 0, st, B->dP, B->dS,
+                       B->dI, B->nitems, B->dQ);
+  return hipGetLastError();
+}
+
+#define BATCH_HIP(call)                                                     \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      set_error("%s failed: %s", #call, hipGetErrorString(e_));             \
+      return CABCD_EHIP;                                                    \
+    }                                                                       \
+  } while (0)
+
+cabcd_status check_problem(const cabcd_problem& q, int p) {
+  const cabcd_matrix& X = q.X;
+  if (X.kind != CABCD_DENSE || X.dtype != CABCD_F64) {
+    set_error("problem %d: the batched path takes dense FP64 X", p);
+    return CABCD_EUNSUPPORTED;
+  }
+  if (X.data == nullptr || q.y == nullptr || q.w == nullptr || q.r == nullptr) {
+    set_error("problem %d: X, y, w and r must be non-NULL device pointers", p);
+    return CABCD_EINVAL;
+  }
+  const auto mis = [](const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 7) != 0; };
+  if (mis(X.data) || mis(q.y) || mis(q.w) || mis(q.r)) {
+    set_error("problem %d: X, y, w and r must be 8-byte aligned", p);
+    return CABCD_EINVAL;
+  }
+  if (X.rows < 1 || X.cols < 1 || X.rows > INT_MAX || X.cols > INT_MAX || X.ld < X.cols) {
+    set_error("problem %d: need 1 <= d, n < 2^31 and ld >= n (d=%lld n=%lld ld=%lld)", p,
+              (long long)X.rows, (long long)X.cols, (long long)X.ld);
+    return CABCD_EINVAL;
+  }
+  if (!(q.lambda > 0.0) || !std::isfinite(q.lambda)) {
+    set_error("problem %d: lambda must be finite and > 0", p);
+    return CABCD_EINVAL;
+  }
+  if (q.b < 0 || q.b > kBMaxB || q.b > X.rows) {
+    set_error("problem %d: b must be 0 (auto) or in [1, min(d, %d)] (b=%d)", p, kBMaxB, q.b);
+    return CABCD_EINVAL;
+  }
+  if (q.s < 0 || q.s > kBMaxRows || (q.b > 0 && q.s > 0 && q.b * q.s > kBMaxRows)) {
+    set_error("problem %d: s must be 0 (auto) or >= 1 with s*b <= %d (b=%d s=%d)", p,
+              kBMaxRows, q.b, q.s);
+    return CABCD_EINVAL;
+  }
+  return CABCD_OK;
+}
+
+cabcd_status sync_status(cabcd_batch_plan* B, hipStream_t st, int32_t* active) {
+  std::vector<BState> S(B->P);
+  BATCH_HIP(hipMemcpyAsync(S.data(), B->dS, sizeof(BState) * B->P, hipMemcpyDeviceToHost, st));
+  BATCH_HIP(hipStreamSynchronize(st));
+  int act = 0;
+  for (int p = 0; p < B->P; ++p) {
+    act += S[p].active != 0;
+    if (S[p].status == DEV_NOTSPD) {
+      set_error("problem %d: a diagonal block was not positive definite", p);
+      return CABCD_ENOTSPD;
+    }
+    if (S[p].status == DEV_NONFINITE) {
+      set_error("problem %d: non-finite values", p);
+      return CABCD_ENONFINITE;
+    }
+  }
+  if (active != nullptr) *active = act;
+  return CABCD_OK;
+}
+
+void release(cabcd_batch_plan* B) {
+  if (B == nullptr) return;
+  (void)hipSetDevice(B->device);
+  (void)hipDeviceSynchronize();
+  if (B->exec != nullptr) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph != nullptr) (void)hipGraphDestroy(B->graph);
+  if (B->cap != nullptr) (void)hipStreamDestroy(B->cap);
+  if (B->mem != nullptr) (void)hipFree(B->mem);
+  delete B;
+}
+
+cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* opts,
+                    hipStream_t st, cabcd_batch_plan* B) {
+  BATCH_HIP(hipGetDevice(&B->device));
+  int cus = 0;
+  BATCH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
+  cus = std::max(cus, 1);
+  B->P = P;
+  B->monitor_every = opts != nullptr ? opts->monitor_every : 4;
+  B->flags = opts != nullptr ? opts->flags : 0u;
+
+  // Autotune: the rounds-per-pass target with the cheapest predicted pass.
+  std::vector<cabcd_problem> probs(pb, pb + P);
+  std::vector<Pick> best, cand;
+  double best_cost = 1e300;
+  for (double rp : {1.0, 1.5, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0, 48.0, 64.0}) {
+    const double c = plan_candidate(probs, rp, cus, cand);
+    if (c < best_cost) {
+      best_cost = c;
+      best = cand;
+    }
+  }
+
+  // Work items: problems with the longest critical path first, slabs of one
+  // problem next to each other so they run concurrently.
+  std::vector<int> order(P);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return best[a].crit > best[b].crit; });
+  std::vector<BItem> items;
+  for (int p : order)
+    for (int q = 0; q < best[p].nslab; ++q) items.push_back(BItem{p, q});
+  B->nitems = (int)items.size();
+
+  // Workspace and device copies.
+  size_t bytes = 0;
+  auto add = [&](size_t n) { bytes = ((bytes + 255) & ~(size_t)255) + n; };
+  add(sizeof(BProb) * P);
+  add(sizeof(BState) * P);
+  add(sizeof(BItem) * items.size());
+  add(sizeof(BQueue));
+  int area = 0;
+  for (int p = 0; p < P; ++p) {
+    const int sb = best[p].b * best[p].s;
+    const int nb = nb_of(sb);
+    add(sizeof(double) * best[p].nslab * pstride_of(nb));
+    add(sizeof(double) * sb * sb);
+    add(sizeof(double) * sb);
+    add(sizeof(double) * sb);
+    add(sizeof(double) * best[p].nslab);
+    area = std::max<int>(area, (int)((solve_lds_bytes(sb, best[p].b) + 7) / 8));
+  }
+  area = std::max<int>(area, gdev::Cfg<16, 2>::LDS);
+  area = std::max<int>(area, gdev::Cfg<1, 2>::LDS);
+  B->area = (area + 1) & ~1;
+  B->step_lds = sizeof(double) * B->area + kBMaxRows * 2 * sizeof(int32_t) +
+                kBMaxRows * sizeof(double) + 4 * sizeof(int);
+  if (hipMalloc(&B->mem, bytes + 256) != hipSuccess) {
+    B->mem = nullptr;
+    set_error("hipMalloc of %zu bytes for the batch plan failed", bytes);
+    return CABCD_ENOMEM;
+  }
+  Workspace ws{static_cast<char*>(B->mem)};
+  B->dP = ws.take<BProb>(P);
+  B->dS = ws.take<BState>(P);
+  B->dI = ws.take<BItem>(items.size());
+  B->dQ = ws.take<BQueue>(1);
+  B->probs.resize(P);
+  std::vector<BState> S(P);
+  for (int p = 0; p < P; ++p) {
+    const cabcd_problem& q = pb[p];
+    BProb& o = B->probs[p];
+    const int sb = best[p].b * best[p].s;
+    o.A = static_cast<const double*>(q.X.data);
+    o.ld = q.X.ld;
+    o.d = q.X.rows;
+    o.n = q.X.cols;
+    o.y = q.y;
+    o.w = q.w;
+    o.r = q.r;
+    o.lambda = q.lambda;
+    o.f_target = q.f_target;
+    o.seed = q.seed;
+    o.H = q.H > 0 ? q.H : INT64_MAX;
+    o.chunk = best[p].chunk;
+    o.b = best[p].b;
+    o.s = best[p].s;
+    o.bp = pow2_at_least(o.b);
+    o.nb = nb_of(sb);
+    o.nslab = best[p].nslab;
+    o.aligned = ((reinterpret_cast<uintptr_t>(o.A) & 15) == 0 && (o.ld & 1) == 0) ? 1 : 0;
+    o.partials = ws.take<double>((size_t)o.nslab * pstride_of(o.nb));
+    o.G = ws.take<double>((size_t)sb * sb);
+    o.Yu = ws.take<double>(sb);
+    o.delta = ws.take<double>(sb);
+    o.objp = ws.take<double>(o.nslab);
+    BState& s = S[p];
+    std::memset(&s, 0, sizeof s);
+    s.obj = NAN;
+    s.active = 1;
+  }
+  BATCH_HIP(hipMemcpyAsync(B->dP, B->probs.data(), sizeof(BProb) * P, hipMemcpyHostToDevice, st));
+  BATCH_HIP(hipMemcpyAsync(B->dS, S.data(), sizeof(BState) * P, hipMemcpyHostToDevice, st));
+  BATCH_HIP(hipMemcpyAsync(B->dI, items.data(), sizeof(BItem) * items.size(),
+                           hipMemcpyHostToDevice, st));
+  BQueue q0{0, 0};
+  BATCH_HIP(hipMemcpyAsync(B->dQ, &q0, sizeof q0, hipMemcpyHostToDevice, st));
+
+  // Persistent grids: as many workgroups as fit on the device at once.
+  BATCH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(batch_step_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)B->step_lds));
+  int occ = 0;
+  BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_step_kernel, kBT,
+                                                         B->step_lds));
+  B->grid_step = std::max(1, std::min(B->nitems, std::max(occ, 1) * cus));
+  BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_aux_kernel<0>, kBT, 0));
+  B->grid_aux = std::max(1, std::min(B->nitems, std::max(occ, 1) * cus));
+
+  // r_0 = X^T w_0 - y and f(w_0).
+  BATCH_HIP(launch_aux(B, 0, st));
+  cabcd_status rc = sync_status(B, st, nullptr);
+  if (rc != CABCD_OK) return rc;
+
+  // Capture one monitor period (or one round without monitoring).
+  if ((B->flags & CABCD_BATCH_NO_GRAPH) == 0) {
+    BATCH_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    BATCH_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    const int R = B->monitor_every > 0 ? B->monitor_every : 1;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < R && e == hipSuccess; ++i) e = launch_step(B, B->cap);
+    if (e == hipSuccess && B->monitor_every > 0) e = launch_aux(B, 0, B->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+    B->graph = g;
+    if (e != hipSuccess || e2 != hipSuccess) {
+      set_error("hipGraph capture of the batched round failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+      return CABCD_EHIP;
+    }
+    BATCH_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    B->graph_rounds = R;
+  }
+  return CABCD_OK;
+}
+
+}  // namespace
+}  // namespace cabcd
+
+using namespace cabcd;
+
+extern "C" {
+
+cabcd_status cabcd_batch_create(const cabcd_problem* problems, int32_t P,
+                                const cabcd_batch_opts* opts, void* stream, cabcd_batch* out) {
+  clear_error();
+  if (out == nullptr) {
+    set_error("out must be non-NULL");
+    return CABCD_EINVAL;
+  }
+  *out = nullptr;
+  if (problems == nullptr || P < 1) {
+    set_error("need P >= 1 problems (P=%d)", P);
+    return CABCD_EINVAL;
+  }
+  if (opts != nullptr && opts->monitor_every < 0) {
+    set_error("monitor_every must be >= 0");
+    return CABCD_EINVAL;
+  }
+  for (int p = 0; p < P; ++p) {
+    const cabcd_status rc = check_problem(problems[p], p);
+    if (rc != CABCD_OK) return rc;
+  }
+  cabcd_batch_plan* B = new cabcd_batch_plan();
+  const cabcd_status rc = create(problems, P, opts, static_cast<hipStream_t>(stream), B);
+  if (rc != CABCD_OK) {
+    release(B);
+    return rc;
+  }
+  *out = B;
+  return CABCD_OK;
+}
+
+cabcd_status cabcd_batch_run(cabcd_batch B, int64_t rounds, void* stream, int32_t* active) {
+  clear_error();
+  if (B == nullptr || rounds < 0) {
+    set_error("need a plan and rounds >= 0");
+    return CABCD_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int M = B->monitor_every;
+  int64_t done = 0;
+  while (done < rounds) {
+    if (B->exec != nullptr && rounds - done >= B->graph_rounds &&
+        (M == 0 || B->rounds_done % M == 0)) {
+      BATCH_HIP(hipGraphLaunch(B->exec, st));
+      done += B->graph_rounds;
+      B->rounds_done += B->graph_rounds;
+      B->pending = M == 0;
+      continue;
+    }
+    BATCH_HIP(launch_step(B, st));
+    ++done;
+    ++B->rounds_done;
+    B->pending = true;
+    if (M > 0 && B->rounds_done % M == 0) {
+      BATCH_HIP(launch_aux(B, 0, st));
+      B->pending = false;
+    }
+  }
+  if (B->pending) {
+    BATCH_HIP(launch_aux(B, 1, st));
+    B->pending = false;
+  }
+  if (active != nullptr) return sync_status(B, st, active);
+  return CABCD_OK;
+}
+
+cabcd_status cabcd_batch_query(cabcd_batch B, int32_t p, cabcd_batch_info* info, void* stream) {
+  clear_error();
+  if (B == nullptr || info == nullptr || p < 0 || p >= B->P) {
+    set_error("need a plan, 0 <= p < P and an info struct");
+    return CABCD_EINVAL;
+  }
+  BState s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  BATCH_HIP(hipMemcpyAsync(&s, B->dS + p, sizeof s, hipMemcpyDeviceToHost, st));
+  BATCH_HIP(hipStreamSynchronize(st));
+  const BProb& o = B->probs[p];
+  info->b = o.b;
+  info->s = o.s;
+  info->nslab = o.nslab;
+  info->active = s.active;
+  info->chunk = o.chunk;
+  info->h = s.h;
+  info->steps = s.steps;
+  info->objective = s.obj;
+  info->status = s.status == DEV_NOTSPD      ? CABCD_ENOTSPD
+                 : s.status == DEV_NONFINITE ? CABCD_ENONFINITE
+                                             : CABCD_OK;
+  info->reserved = 0;
+  return CABCD_OK;
+}
+
+cabcd_status cabcd_batch_destroy(cabcd_batch B) {
+  release(B);
+  return CABCD_OK;
+}
+
+cabcd_status cabcd_primal_bcd_batched(const cabcd_problem* problems, int32_t P,
+                                      int64_t max_rounds, const cabcd_batch_opts* opts,
+                                      void* stream) {
+  cabcd_batch B = nullptr;
+  cabcd_status rc = cabcd_batch_create(problems, P, opts, stream, &B);
+  if (rc != CABCD_OK) return rc;
+  const int64_t period = B->graph_rounds > 0 ? B->graph_rounds : 4;
+  int64_t done = 0;
+  int32_t active = 1;
+  while (rc == CABCD_OK && active > 0 && done < max_rounds) {
+    const int64_t r = std::min(period, max_rounds - done);
+    rc = cabcd_batch_run(B, r, stream, &active);
+    done += r;
+  }
+  const std::string msg = cabcd_last_error();
+  release(B);
+  if (rc != CABCD_OK) set_error("%s", msg.c_str());
+  return rc;
+}
+
+}  // extern "C"

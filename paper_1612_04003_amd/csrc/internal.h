@@ -20,6 +20,18 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Global-memory view of a device pointer.  A pointer that reaches device code
+// through memory or through a non-inlined call is generic to the compiler, and
+// generic (flat) accesses also count against the LDS wait counter, so an LDS
+// barrier would wait for global prefetches still in flight.  Accesses through
+// the cast compile to global_* instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
 // Exact decoding of the low-precision storage formats to FP64.
 __device__ __forceinline__ double decode_bf16(uint32_t b) {
   return (double)__uint_as_float((b & 0xFFFFu) << 16);
@@ -38,6 +50,55 @@ void clear_error();
 enum DeviceStatus : int { DEV_OK = 0, DEV_NOTSPD = 1, DEV_NONFINITE = 2 };
 
 // ------------------------------------------------------------------ sampler
+// Counter-based block sampler (the sampling step of Alg. 1-4): b distinct
+// coordinates per inner iteration, uniform without replacement, keyed by
+// (seed, h) only, so every consumer of the same seed draws the same blocks.
+//   SplitMix64 output t of a stream seeded with x: mix64(x + GAMMA*(t+1))
+//     (Steele, Lea & Flood, OOPSLA 2014; finaliser constants of that paper)
+//   key(h) = output h of the stream seeded with `seed`
+//   word t = upper 32 bits of output t of the stream seeded with key(h)
+//   bounded(range): Lemire's multiply-shift with rejection (TOMACS 2019)
+//   block: Floyd's algorithm (Bentley & Floyd, CACM 1987), insertion order.
+namespace smp {
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t stream_out(uint64_t seed, uint64_t t) {
+  return mix64(seed + kGamma * (t + 1));
+}
+
+// The b indices of inner iteration h into out[0..b) (out may be in LDS).
+__device__ __forceinline__ void sample_block(uint64_t seed, int64_t h, int b, int64_t range,
+                                             int32_t* out) {
+  const uint64_t key = stream_out(seed, (uint64_t)h);
+  uint64_t t = 0;
+  int filled = 0;
+  for (int64_t j = range - b; j < range; ++j) {
+    const uint64_t m = (uint64_t)(j + 1);          // draw uniformly from [0, j]
+    uint64_t x = stream_out(key, t++) >> 32;
+    uint64_t prod = x * m;
+    uint32_t low = (uint32_t)prod;
+    if (low < m) {
+      const uint32_t thr = (uint32_t)((0x100000000ull - m) % m);
+      while (low < thr) {
+        x = stream_out(key, t++) >> 32;
+        prod = x * m;
+        low = (uint32_t)prod;
+      }
+    }
+    const int32_t v = (int32_t)(prod >> 32);
+    bool seen = false;
+    for (int q = 0; q < filled; ++q) seen |= (out[q] == v);
+    out[filled++] = seen ? (int32_t)j : v;
+  }
+}
+}  // namespace smp
+
 hipError_t launch_sample(uint64_t seed, int64_t h0, int64_t count, int b, int64_t range,
                          int32_t* idx, hipStream_t st);
 

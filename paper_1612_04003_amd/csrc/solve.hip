@@ -1,241 +1,16 @@
-// The s inner b x b solves of one outer step, fused into one workgroup.
-//
-// Primal (Alg. 2, eq. recur): with G the s-step Gram and S_jt = I_j^T I_t,
-//   dw_j = Gamma_j^{-1} ( c_j - sum_{t<j} (G_jt + lambda S_jt) dw_t ),
-//   c = -lambda w_I - (1/n) Y (z - y),   Gamma_j = G_jj.
-// Dual (Alg. 4): writing Theta_j = G'_jj and using (1/(lambda n)) Y_j^T Y_t =
-// n G'_jt, the printed recurrence becomes
-//   da_j = Theta_j^{-1} ( c_j - sum_{t<j} (G'_jt + (1/n) S_jt) da_t ),
-//   c = (1/n) (Y^T w - a_I - y_I).
-// Both are one block forward substitution with the lower block triangle of the
-// overlap-augmented Gram Gov = scale Y Y^T + shift [idx_p == idx_q], which the
-// Gram reduction writes (its diagonal blocks are exactly Gamma_j / Theta_j
-// because indices within a block are distinct).
-//
-// Phases (one workgroup; thread p owns row p of the outer step):
-//  1. c, and the diagonal blocks of Gov gathered into registers;
-//  2. every diagonal block inverted by one wave with in-place Gauss-Jordan
-//     elimination, the block's entries spread over the lanes and exchanged by
-//     shuffles (no LDS round trips, no barriers).  Blocks are padded to
-//     BP = 2^k >= b with the identity, whose inverse keeps the padding.  On an
-//     SPD matrix the Gauss-Jordan pivots are the LDL^T pivots, so a pivot <= 0
-//     or NaN is reported as "not positive definite";
-//  3. the dependent chain over j: delta_j = Gamma_j^{-1} rhs_j, then every later
-//     row subtracts its Gov row segment times delta_j.  Row segments of the
-//     next PF blocks are prefetched into registers; the barriers order LDS
-//     only, so the prefetches stay in flight; vectors in LDS are zero-padded to
-//     BP so every read is unconditional;
-//  4. delta written out, and x[idx] += delta: an LDS hash of the indices gives
-//     each coordinate's first occurrence and count; the first occurrence adds
-//     the duplicates in block order (single writer).
-#include "internal.h"
-
-#include <algorithm>
-#include <climits>
+// The fused solve kernel (one workgroup per outer step) and its launcher; the
+// device code and its design notes are in solve_dev.h.
+#include "solve_dev.h"
 
 namespace cabcd {
 namespace {
 
-constexpr int pow2_at_least(int b) {
-  int p = 1;
-  while (p < b) p *= 2;
-  return p;
-}
-
-template <int BP>
-struct SolveCfg {
-  static constexpr int EPL = BP * BP > 64 ? BP * BP / 64 : 1;   // block entries per lane
-  static constexpr int SPW = BP * BP < 64 ? 64 / (BP * BP) : 1; // blocks per wave
-};
-
-// In-place Gauss-Jordan inversion of the SPW blocks held by one wave.
-// EPL == 1: lane l holds entry (u, v) = ((l % BP^2) / BP, l % BP) of block
-// l / BP^2.  EPL > 1: entry l + 64 t of the single block sits in slot t.
-template <int BP>
-__device__ __forceinline__ void gj_invert(double (&e)[SolveCfg<BP>::EPL], int lane, bool& bad) {
-  using C = SolveCfg<BP>;
-  if constexpr (C::EPL == 1) {
-    const int base = (lane / (BP * BP)) * (BP * BP);
-    const int idx = lane - base;
-    const int u = idx / BP, v = idx % BP;
-#pragma unroll
-    for (int k = 0; k < BP; ++k) {
-      const double piv = __shfl(e[0], base + k * BP + k, 64);
-      const double akv_old = __shfl(e[0], base + k * BP + v, 64);
-      const double f = __shfl(e[0], base + u * BP + k, 64);
-      bad |= !(piv > 0.0);
-      const double rp = 1.0 / piv;
-      const double akv = (v == k ? 1.0 : akv_old) * rp;   // row k after a[k][k] = 1, / piv
-      e[0] = u == k ? akv : (v == k ? 0.0 : e[0]) - f * akv;
-    }
-  } else {
-    const int v = lane % BP;   // the same column in every slot: 64 is a multiple of BP
-#pragma unroll
-    for (int k = 0; k < BP; ++k) {
-      const int pe = k * BP + k;
-      const double piv = __shfl(e[pe / 64], pe % 64, 64);
-      bad |= !(piv > 0.0);
-      const double rp = 1.0 / piv;
-      const double akv_old = __shfl(e[(k * BP) / 64], (k * BP + v) % 64, 64);
-      const double akv = (v == k ? 1.0 : akv_old) * rp;
-      double f[C::EPL];
-#pragma unroll
-      for (int t = 0; t < C::EPL; ++t) {
-        const int u = (lane + 64 * t) / BP;
-        f[t] = __shfl(e[t], (u * BP + k) % 64, 64);
-      }
-#pragma unroll
-      for (int t = 0; t < C::EPL; ++t) {
-        const int u = (lane + 64 * t) / BP;
-        e[t] = u == k ? akv : (v == k ? 0.0 : e[t]) - f[t] * akv;
-      }
-    }
-  }
-}
-
-constexpr int kHashMin = 2048;   // LDS hash slots for the scatter (>= 2 m)
-
-__device__ __forceinline__ unsigned hash_idx(int i, int slots) {
-  return ((unsigned)i * 2654435761u) & (unsigned)(slots - 1);
-}
+using namespace sdev;
 
 template <int BP, int PF, int THREADS>
 __global__ __launch_bounds__(THREADS) void solve_kernel(SolveArgs a) {
-  using C = SolveCfg<BP>;
   extern __shared__ __attribute__((aligned(16))) double sm[];
-  const int m = a.m, b = a.b, s = a.s;
-  // LDS: Ginv [s][BP][BP] (reused as the hash table in phase 4), R [BP],
-  // Dl [s][BP] (zero-padded delta), Ix [m]
-  const int slots = std::max(kHashMin, pow2_at_least(2 * m));
-  const size_t gi_doubles =
-      std::max((size_t)s * BP * BP, ((size_t)slots * 3 * sizeof(int) + 7) / sizeof(double));
-  double* Gi = sm;
-  double* R = Gi + gi_doubles;
-  double* Dl = R + BP;
-  int* Ix = reinterpret_cast<int*>(Dl + (size_t)s * BP);
-
-  const int p = threadIdx.x;
-  const int lane = p & 63;
-  const int wave = p >> 6;
-  const bool active = p < m;
-  const int j_of = active ? p / b : -1;   // block of this row (-1: no row)
-  const int u = active ? p - j_of * b : 0;
-
-  // ---- phase 1
-  double rhs = 0.0;
-  int ip = 0;
-  if (active) {
-    ip = a.idx[p];
-    Ix[p] = ip;
-    const double yu = a.Yu[p];
-    const double xi = a.x[ip];
-    rhs = a.mode == 0 ? (-a.lambda * xi - yu / a.n) : ((yu - xi - a.y[ip]) / a.n);
-  }
-  for (int q = p; q < s * BP; q += THREADS) Dl[q] = 0.0;
-  if (p < BP) R[p] = 0.0;
-
-  // Prefetch ring of Gov row segments Gov[p][jb*b + v].  Gov is symmetric, so
-  // they are read as Gov[jb*b + v][p]: consecutive threads then read
-  // consecutive addresses (one cache line per 16 lanes instead of one per
-  // lane).  Unconditional loads with the block and column clamped into range
-  // keep the number of loads uniform, so the compiler waits for exactly the
-  // one it needs.
-  const double* gcol = a.G + (active ? p : m - 1);
-  double ring[PF][BP];
-  auto ring_load = [&](int q, int jb) {
-    const double* g = gcol + (int64_t)(jb < j_of ? jb : 0) * b * m;
-#pragma unroll
-    for (int v = 0; v < BP; ++v) ring[q][v] = g[(int64_t)(v < b ? v : b - 1) * m];
-  };
-#pragma unroll
-  for (int q = 0; q < PF; ++q) ring_load(q, q);
-
-  // ---- phase 2: invert the diagonal blocks, SPW blocks per wave at a time
-  constexpr int WAVES = THREADS / 64;
-  bool bad = false;
-  for (int j0 = wave * C::SPW; j0 < s; j0 += WAVES * C::SPW) {
-    // entry t of this lane: block blk(t), row uu(t), column vv(t)
-    auto blk = [&](int t) { return C::EPL == 1 ? j0 + lane / (BP * BP) : j0; };
-    auto eix = [&](int t) { return C::EPL == 1 ? lane % (BP * BP) : lane + 64 * t; };
-    double e[C::EPL];
-#pragma unroll
-    for (int t = 0; t < C::EPL; ++t) {
-      const int bj = blk(t), uu = eix(t) / BP, vv = eix(t) % BP;
-      e[t] = (bj < s && uu < b && vv < b) ? a.G[(int64_t)(bj * b + uu) * m + bj * b + vv]
-                                          : (uu == vv ? 1.0 : 0.0);   // identity padding
-    }
-    gj_invert<BP>(e, lane, bad);
-#pragma unroll
-    for (int t = 0; t < C::EPL; ++t)
-      if (blk(t) < s) Gi[((size_t)blk(t) * BP + eix(t) / BP) * BP + eix(t) % BP] = e[t];
-  }
-  if (bad) *a.status = DEV_NOTSPD;
-  lds_barrier();
-
-  // ---- phase 3: the dependent chain over the s blocks.  Every thread runs all
-  // rounds (the work of steps j >= s is switched off, the barriers and loads
-  // are not), so the control flow is uniform.
-  for (int j0 = 0; j0 < s; j0 += PF) {
-#pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int j = j0 + q;
-      if (j_of == j) R[u] = rhs;
-      lds_barrier();
-      if (p < b && j < s) {
-        const double* g = Gi + ((size_t)j * BP + p) * BP;
-        double t = 0.0;
-#pragma unroll
-        for (int v = 0; v < BP; ++v) t += g[v] * R[v];
-        Dl[j * BP + p] = t;
-      }
-      lds_barrier();
-      if (j_of > j) {
-        const double* dj = Dl + j * BP;
-        double acc = 0.0;
-#pragma unroll
-        for (int v = 0; v < BP; ++v) acc += ring[q][v] * dj[v];
-        rhs -= acc;
-      }
-      ring_load(q, j + PF);
-    }
-  }
-
-  // ---- phase 4: outputs.  Gi is free now and holds the hash table.
-  int* hkey = reinterpret_cast<int*>(Gi);
-  int* hmin = hkey + slots;
-  int* hcnt = hmin + slots;
-  for (int q = p; q < slots; q += THREADS) {
-    hkey[q] = -1;
-    hmin[q] = INT_MAX;
-    hcnt[q] = 0;
-  }
-  lds_barrier();
-  unsigned h = 0;
-  double dp = 0.0;
-  if (active) {
-    dp = Dl[j_of * BP + u];
-    a.delta[p] = dp;
-    if (!isfinite(dp)) *a.status = DEV_NONFINITE;
-    h = hash_idx(ip, slots);
-    for (;;) {
-      const int old = atomicCAS(&hkey[h], -1, ip);
-      if (old == -1 || old == ip) break;
-      h = (h + 1) & (unsigned)(slots - 1);
-    }
-    atomicMin(&hmin[h], p);
-    atomicAdd(&hcnt[h], 1);
-  }
-  lds_barrier();
-  if (active && hmin[h] == p) {
-    if (hcnt[h] == 1) {
-      a.x[ip] += dp;
-    } else {
-      double acc = a.x[ip];
-      for (int q = p; q < m; ++q)
-        if (Ix[q] == ip) acc += Dl[(q / b) * BP + q % b];
-      a.x[ip] = acc;
-    }
-  }
+  solve_block<BP, PF, THREADS>(a, sm);
 }
 
 template <int BP, int PF, int THREADS>

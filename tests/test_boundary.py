@@ -88,3 +88,60 @@ def test_workspace_bytes_grows_with_problem():
     b = lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(2048, 262144)), 8, 32)
     assert 0 < a < b
     assert lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(64, 1024)), 16, 17) == 0
+
+
+def test_batch_struct_layout_matches_header():
+    assert ctypes.sizeof(cabcd.Problem) == ctypes.sizeof(cabcd.Matrix) + 8 * 8
+    assert ctypes.sizeof(cabcd.BatchOpts) == 4 + 4
+    assert ctypes.sizeof(cabcd.BatchInfo) == 4 * 4 + 8 * 3 + 8 + 4 + 4
+
+
+def _fake_problem(**kw):
+    q = cabcd.Problem()
+    q.X = _fake_matrix(kw.pop("d", 64), kw.pop("n", 1024))
+    q.y, q.w, q.r = 0x2000, 0x3000, 0x4000
+    q.lam, q.b, q.s, q.seed, q.H = 1e-3, 4, 8, 1, 10
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(lam=0.0), cabcd.EINVAL),
+    (dict(lam=float("inf")), cabcd.EINVAL),
+    (dict(b=-1), cabcd.EINVAL),
+    (dict(b=17), cabcd.EINVAL),           # above the batched block limit
+    (dict(b=65, d=64), cabcd.EINVAL),     # b > d
+    (dict(b=16, s=17), cabcd.EINVAL),     # s*b > 256
+    (dict(s=-2), cabcd.EINVAL),
+    (dict(y=0), cabcd.EINVAL),
+    (dict(w=0), cabcd.EINVAL),
+    (dict(n=0), cabcd.EINVAL),
+])
+def test_batch_argument_errors(kw, status):
+    lib = cabcd.load()
+    probs = (cabcd.Problem * 3)(_fake_problem(), _fake_problem(**kw), _fake_problem())
+    h = ctypes.c_void_p(0x1)
+    st = lib.cabcd_batch_create(probs, 3, None, None, ctypes.byref(h))
+    assert st == status
+    assert h.value is None
+    msg = lib.cabcd_last_error().decode()
+    assert "problem 1" in msg
+    assert lib.cabcd_primal_bcd_batched(probs, 3, 10, None, None) == status
+
+
+def test_batch_plan_errors():
+    lib = cabcd.load()
+    h = ctypes.c_void_p()
+    assert lib.cabcd_batch_create(None, 1, None, None, ctypes.byref(h)) == cabcd.EINVAL
+    probs = (cabcd.Problem * 1)(_fake_problem())
+    assert lib.cabcd_batch_create(probs, 0, None, None, ctypes.byref(h)) == cabcd.EINVAL
+    o = cabcd.BatchOpts()
+    o.monitor_every = -1
+    assert lib.cabcd_batch_create(probs, 1, ctypes.byref(o), None,
+                                  ctypes.byref(h)) == cabcd.EINVAL
+    assert lib.cabcd_batch_run(None, 1, None, None) == cabcd.EINVAL
+    assert lib.cabcd_batch_query(None, 0, None, None) == cabcd.EINVAL
+    assert lib.cabcd_batch_destroy(None) == cabcd.OK
+    probs[0].X.dtype = cabcd.BF16
+    assert lib.cabcd_batch_create(probs, 1, None, None, ctypes.byref(h)) == cabcd.EUNSUPPORTED

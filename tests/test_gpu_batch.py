@@ -1,0 +1,152 @@
+"""Batched primal CA-BCD (one persistent launch per round for many problems)
+against the CPU oracle, problem by problem.
+
+* With (b, s, seed, H) fixed per problem, each problem's w must equal the
+  oracle's Alg. 2 run on that problem alone (same blocks) to 1e-10 relative,
+  and r must equal X^T w - y.
+* The hipGraph replay and direct launches give bitwise identical results, and
+  so does a run split into several calls (the arithmetic is deterministic).
+* Autotuned (b, s): every problem reaches a relative objective error of 1e-6
+  against its closed-form optimum and is retired by its f_target.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bcd
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# (d, n, b, s, H, lambda, seed): ragged last steps, b = d, s*b = 256, odd n
+# (rows not 16-byte aligned), many slabs, b = 1, b not a power of two.
+CASES = [
+    (37, 1001, 4, 3, 50, 1e-2, 11),
+    (64, 4096, 8, 8, 200, 1e-3, 12),
+    (300, 5000, 16, 16, 96, 1e-3, 13),
+    (20, 777, 5, 2, 23, 5e-2, 14),
+    (128, 20000, 16, 4, 64, 1e-4, 15),
+    (9, 300, 9, 1, 3, 1e-1, 16),
+    (50, 4096, 1, 32, 100, 1e-3, 17),
+    (200, 3001, 12, 10, 77, 1e-3, 18),
+    (33, 65, 16, 16, 40, 1e-2, 19),
+    (1, 100, 1, 4, 9, 1e-1, 20),
+]
+
+
+def _problems(cases):
+    probs = []
+    for i, (d, n, b, s, H, lam, seed) in enumerate(cases):
+        X, y, _ = synth.gaussian_ridge(d, n, 500 + i)
+        probs.append(dict(X=X.to(DEV), y=y.to(DEV), lam=lam, b=b, s=s, seed=seed, H=H,
+                          Xc=X.numpy(), yc=y.numpy()))
+    return probs
+
+
+def _run(gpu_lib, probs, chunks, monitor_every=2, graph=True):
+    with gpu_lib.Batch(probs, monitor_every=monitor_every, graph=graph) as B:
+        act = None
+        for c in chunks:
+            act = B.run(c)
+        infos = [B.info(p) for p in range(len(probs))]
+    torch.cuda.synchronize()
+    return act, infos
+
+
+def test_batch_matches_oracle_per_problem(gpu_lib):
+    _say("batch vs oracle,", len(CASES), "problems")
+    probs = _problems(CASES)
+    act, infos = _run(gpu_lib, probs, [100])
+    assert act == 0
+    for q, (d, n, b, s, H, lam, seed), inf in zip(probs, CASES, infos):
+        assert inf["b"] == b and inf["s"] == s
+        assert inf["h"] == H and inf["steps"] == -(-H // s) and not inf["active"]
+        assert inf["status"] == gpu_lib.OK and np.isfinite(inf["objective"])
+        wo, _ = bcd.primal_bcd(q["Xc"], q["yc"], lam, b, s, H, seed)
+        w = q["w"].cpu().numpy()
+        err = np.linalg.norm(w - wo) / max(np.linalg.norm(wo), 1e-300)
+        _say(f"  d={d} n={n} b={b} s={s} H={H}: rel err {err:.2e}")
+        assert err <= 1e-10
+        r = q["r"].cpu().numpy()
+        assert np.linalg.norm(r - (q["Xc"].T @ w - q["yc"])) <= 1e-10 * np.linalg.norm(q["yc"])
+
+
+def test_batch_graph_direct_and_split_runs_are_identical(gpu_lib):
+    _say("batch graph / direct / split runs")
+    cases = CASES[:6]
+    runs = []
+    for graph, chunks in ((True, [6]), (False, [6]), (True, [2, 1, 3])):
+        probs = _problems(cases)
+        _run(gpu_lib, probs, chunks, graph=graph)
+        runs.append([(q["w"].cpu().numpy(), q["r"].cpu().numpy()) for q in probs])
+    for other in runs[1:]:
+        for (w0, r0), (w1, r1) in zip(runs[0], other):
+            assert np.array_equal(w0, w1)
+            assert np.array_equal(r0, r1)
+
+
+def test_batch_without_monitoring(gpu_lib):
+    _say("batch, monitor_every = 0")
+    cases = CASES[:4]
+    probs = _problems(cases)
+    act, infos = _run(gpu_lib, probs, [30, 30, 50], monitor_every=0)
+    assert act == 0
+    for q, (d, n, b, s, H, lam, seed) in zip(probs, cases):
+        wo, _ = bcd.primal_bcd(q["Xc"], q["yc"], lam, b, s, H, seed)
+        w = q["w"].cpu().numpy()
+        assert np.linalg.norm(w - wo) <= 1e-10 * np.linalg.norm(wo)
+        r = q["r"].cpu().numpy()   # maintained by the recurrence only
+        assert np.linalg.norm(r - (q["Xc"].T @ w - q["yc"])) <= 1e-9 * np.linalg.norm(q["yc"])
+
+
+def test_batch_autotuned_reaches_1e6(gpu_lib):
+    P = 24
+    ds, ns, lams = synth.ridge_batch(P, 77, d_range=(32, 512), n_range=(2048, 32768))
+    _say("batch autotuned, P =", P)
+    probs, fstars = [], []
+    for p in range(P):
+        X, y, _ = synth.gaussian_ridge(ds[p], ns[p], 900 + p)
+        Xc, yc = X.numpy(), y.numpy()
+        wst = bcd.ridge_closed_form(Xc, yc, lams[p])
+        fst = bcd.primal_objective(Xc, yc, lams[p], wst)
+        fstars.append(fst)
+        probs.append(dict(X=X.to(DEV), y=y.to(DEV), lam=lams[p], seed=3000 + p,
+                          f_target=fst * (1 + 1e-6), Xc=Xc, yc=yc))
+    with gpu_lib.Batch(probs, monitor_every=4) as B:
+        rounds, act = 0, P
+        while act > 0 and rounds < 4000:
+            act = B.run(4)
+            rounds += 4
+        infos = [B.info(p) for p in range(P)]
+    _say(f"  all retired after {rounds} rounds")
+    assert act == 0
+    for q, fst, inf, d in zip(probs, fstars, infos, ds):
+        assert 1 <= inf["b"] <= 16 and inf["b"] <= d and inf["b"] * inf["s"] <= 256
+        w = q["w"].cpu().numpy()
+        rel = (bcd.primal_objective(q["Xc"], q["yc"], q["lam"], w) - fst) / fst
+        assert rel <= 1e-6 * (1 + 1e-6)
+        assert abs(inf["objective"] - bcd.primal_objective(q["Xc"], q["yc"], q["lam"], w)) \
+            <= 1e-12 * fst
+    _say("  (b, s) chosen:", sorted({(i["b"], i["s"]) for i in infos}))
+
+
+def test_batch_one_shot_and_nonfinite(gpu_lib):
+    _say("batch one-shot; non-finite data is reported")
+    probs = _problems(CASES[:3])
+    gpu_lib.primal_bcd_batched(probs, 1000, monitor_every=3)
+    for q, (d, n, b, s, H, lam, seed) in zip(probs, CASES[:3]):
+        wo, _ = bcd.primal_bcd(q["Xc"], q["yc"], lam, b, s, H, seed)
+        assert np.linalg.norm(q["w"].cpu().numpy() - wo) <= 1e-10 * np.linalg.norm(wo)
+    probs = _problems(CASES[:3])
+    probs[1]["X"][3, 5] = float("nan")
+    with pytest.raises(gpu_lib.CabcdError) as e:
+        gpu_lib.primal_bcd_batched(probs, 1000, monitor_every=3)
+    assert e.value.status in (gpu_lib.ENOTSPD, gpu_lib.ENONFINITE)
+    assert "problem 1" in str(e.value)
