@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tol", action="store_true", help="skip the time-to-1e-6 runs")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra records")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched time-to-1e-6 runs")
+    ap.add_argument("--only-batch", action="store_true", help="run only the batched record")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per Gram launch measured by rocprofv3 counters")
     return ap.parse_args()
@@ -265,6 +267,104 @@ def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, la
     return res
 
 
+def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, max_rounds=20000):
+    """256 independent dense ridge problems (d, n, lambda log-uniform), time to a
+    relative objective error of 1e-6 on every problem: the batched persistent
+    path (one launch per round, hipGraph) against the one-problem path run
+    problem after problem with the same (b, s), both on this GPU; FP64 and BF16
+    storage (the BF16 runs solve the stored problem X^)."""
+    ds, ns, lams = synth.ridge_batch(P, seed)
+    log(f"batched: generating {P} problems (sum d*n = {sum(d * n for d, n in zip(ds, ns)):.3g})")
+    data = [synth.gaussian_ridge(ds[p], ns[p], seed + 1 + p, device="cuda")[:2] for p in range(P)]
+    torch.cuda.synchronize()
+
+    def fstar(X, y, lam):
+        n = X.shape[1]
+        M = X @ X.t()
+        M /= n
+        M.diagonal().add_(lam)
+        L = torch.linalg.cholesky(M)
+        w = torch.cholesky_solve(((X @ y) / n)[:, None], L)[:, 0]
+        f, _ = cabcd.primal_objective(X, y, lam, w)
+        return f.item()
+
+    res = {"workload": f"{P} Gaussian ridge problems, d log-uniform [32, 1024], n log-uniform "
+                       f"[4096, 131072], lambda log-uniform [1e-6, 1e-1]; exact residual + "
+                       f"objective every {monitor} rounds; stop at relative objective error "
+                       f"{tol:g} on every problem",
+           "problems": P, "sum_dn": int(sum(d * n for d, n in zip(ds, ns)))}
+    for name in ("f64", "bf16"):
+        if name == "f64":
+            mats = [X for X, _ in data]
+            fst = [fstar(X, y, lams[p]) for p, (X, y) in enumerate(data)]
+        else:
+            mats, fst = [], []
+            for p, (X, y) in enumerate(data):
+                Q = cabcd.quantize(X, cabcd.BF16)
+                Xh = Q.dequantize()
+                fst.append(fstar(Xh, y, lams[p]))
+                del Xh
+                mats.append(Q)
+            torch.cuda.empty_cache()
+        probs = [dict(X=mats[p], y=data[p][1], lam=lams[p], seed=2_000_000 + p,
+                      f_target=fst[p] * (1 + tol)) for p in range(P)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B = cabcd.Batch(probs, monitor_every=monitor)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rounds, act = 0, P
+        while act > 0 and rounds < max_rounds:
+            act = B.run(monitor)
+            rounds += monitor
+        t2 = time.perf_counter()
+        infos = [B.info(p) for p in range(P)]
+        B.close()
+        errs = [(i["objective"] - f) / f for i, f in zip(infos, fst)]
+        rec = {"plan_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4), "rounds": rounds,
+               "unconverged": act, "max_rel_err": max(errs),
+               "ms_per_round": round((t2 - t1) / max(rounds, 1) * 1e3, 4)}
+        pairs = {}
+        for i in infos:
+            k = f"b{i['b']}s{i['s']}"
+            pairs[k] = pairs.get(k, 0) + 1
+        rec["bs_choices"] = pairs
+        log(f"batched {name}: {rec}")
+        if name == "f64":
+            # one problem at a time, same (b, s), same stopping rule
+            tot, steps_tot, worst = 0.0, 0, 0.0
+            for p in range(P):
+                X, y = data[p]
+                b, s = infos[p]["b"], infos[p]["s"]
+                w = torch.zeros(ds[p], dtype=torch.float64, device="cuda")
+                r = torch.empty(ns[p], dtype=torch.float64, device="cuda")
+                tr = torch.zeros(1, dtype=torch.float64, device="cuda")
+                cabcd.primal_bcd(X, y, lams[p], b, s, 0, 7, w=w, r=r)
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                steps, err = 0, float("inf")
+                while steps < max_rounds:
+                    cabcd.primal_bcd(X, y, lams[p], b, s, monitor * s, 2_000_000 + p, w=w, r=r,
+                                     h0=steps * s, flags=cabcd.FLAG_STATE_VALID,
+                                     resid_every=monitor, monitor_every=monitor, trace=tr)
+                    steps += monitor
+                    err = (tr.item() - fst[p]) / fst[p]
+                    if err <= tol:
+                        break
+                tot += time.perf_counter() - ta
+                steps_tot += steps
+                worst = max(worst, err)
+            rec["one_at_a_time_s"] = round(tot, 4)
+            rec["one_at_a_time_outer_steps"] = steps_tot
+            rec["one_at_a_time_max_rel_err"] = worst
+            rec["speedup"] = round(tot / (t2 - t1), 3)
+            log(f"one-at-a-time f64: {tot:.3f} s, speedup {rec['speedup']}")
+        res[name] = rec
+        del probs, mats
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -281,6 +381,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     cabcd.load()
+    if args.only_batch:
+        print(json.dumps({"batched_tol": batched_tol(cabcd, torch, synth)}), flush=True)
+        return
     out, X, y = headline(args, cabcd, torch, synth)
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
@@ -293,6 +396,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_tol:
         out["time_to_tol"] = time_to_tol(cabcd, torch, synth)
+    if not args.no_batch:
+        out["batched_tol"] = batched_tol(cabcd, torch, synth)
     print(json.dumps(out), flush=True)
 
 

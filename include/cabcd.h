@@ -249,7 +249,10 @@ cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha,
  * lambda, b, s, seed and H (the same blocks), up to rounding order.
  */
 typedef struct cabcd_problem {
-  cabcd_matrix X;            /* dense F64, rows d = features, cols n = samples     */
+  cabcd_matrix X;            /* dense, rows d = features, cols n = samples: F64, or
+                                BF16 / FP8 storage (Gram on the codes with FP32
+                                accumulation, all else FP64 on X^); one storage
+                                type per batch                                     */
   const double* y;           /* n labels                                           */
   double lambda;             /* > 0                                                */
   int32_t b;                 /* block size, 1..16; 0: chosen by the autotuner      */

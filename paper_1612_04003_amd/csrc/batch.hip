@@ -19,6 +19,7 @@
 // periodic full residual of the paper's stopping discussion) or flushes the
 // pending update.  The plan captures both into a hipGraph.
 #include "gram_dev.h"
+#include "lowp_dev.h"
 #include "solve_dev.h"
 
 #include <algorithm>
@@ -37,7 +38,8 @@ constexpr int kBMaxB = 16;
 constexpr int kBMaxSlabs = 64;
 
 struct BProb {                     // constant per problem (device copy)
-  const double* A;
+  const void* A;                   // FP64 values or BF16 / FP8 codes (row-major)
+  const float* rs;                 // FP8 row scales (NULL: 1)
   int64_t ld, d, n;
   const double* y;
   double* w;
@@ -129,6 +131,77 @@ __device__ __forceinline__ double slab_rows_dot(const double* __restrict__ A, in
   return ss;
 }
 
+// The same pass over stored BF16 / FP8 codes: rows decoded exactly to FP64 and
+// multiplied by coef[q] * rs[row(q)] (rs NULL: 1).  k0 is a multiple of the
+// 16-byte chunk.
+template <int FMT>
+__device__ __forceinline__ double slab_rows_dot_lp(const uint8_t* __restrict__ A, int64_t ld,
+                                                   int64_t k0, int64_t k1, const int32_t* rows,
+                                                   const double* coef, const float* rs, int mq,
+                                                   const double* __restrict__ base, double beta,
+                                                   double* __restrict__ out, int aligned) {
+  constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;
+  constexpr int EPC = 16 / ES;
+  const gptr<const uint8_t> Ag = glb(A);
+  const gptr<const double> bg = glb(base);
+  const gptr<double> og = glb(out);
+  const gptr<const float> rg = glb(rs);
+  double ss = 0.0;
+  for (int64_t k = k0 + EPC * (int64_t)threadIdx.x; k < k1; k += (int64_t)EPC * kBT) {
+    double acc[EPC];
+#pragma unroll
+    for (int e = 0; e < EPC; ++e)
+      acc[e] = k + e < k1 ? (base != nullptr ? beta * bg[k + e] : og[k + e]) : 0.0;
+    int q = 0;
+    for (; q + 4 <= mq; q += 4) {
+      uint4 x[4];
+      double c[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t row = rows != nullptr ? rows[q + j] : q + j;
+        c[j] = coef[q + j] * (rs != nullptr ? (double)rg[row] : 1.0);
+        x[j] = ldev::lp_load<FMT>(Ag + row * ld * ES, k, k1, aligned != 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double dv[EPC];
+        ldev::lp_decode_all<FMT>(x[j], dv);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) acc[e] = fma(dv[e], c[j], acc[e]);
+      }
+    }
+    for (; q < mq; ++q) {
+      const int64_t row = rows != nullptr ? rows[q] : q;
+      const double c = coef[q] * (rs != nullptr ? (double)rg[row] : 1.0);
+      double dv[EPC];
+      ldev::lp_decode_all<FMT>(ldev::lp_load<FMT>(Ag + row * ld * ES, k, k1, aligned != 0), dv);
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) acc[e] = fma(dv[e], c, acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+      if (k + e < k1) {
+        og[k + e] = acc[e];
+        ss += acc[e] * acc[e];
+      }
+    }
+  }
+  return ss;
+}
+
+// Either pass, by storage format.
+template <int FMT>
+__device__ __forceinline__ double rows_dot(const BProb& pr, int64_t k0, int64_t k1,
+                                           const int32_t* rows, const double* coef, int mq,
+                                           const double* base, double beta) {
+  if constexpr (FMT == CABCD_F64)
+    return slab_rows_dot(static_cast<const double*>(pr.A), pr.ld, k0, k1, rows, coef, mq, base,
+                         beta, pr.r, pr.aligned);
+  else
+    return slab_rows_dot_lp<FMT>(static_cast<const uint8_t*>(pr.A), pr.ld, k0, k1, rows, coef,
+                                 pr.rs, mq, base, beta, pr.r, pr.aligned);
+}
+
 // Workgroup sum in a fixed order (valid in thread 0).
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -175,15 +248,38 @@ __device__ __noinline__ void gram_call(const double* A, int64_t ld, int64_t k0, 
                          uni_ptr(u), uni_ptr(part), uni(aligned), dyn_sm);
 }
 
-__device__ __forceinline__ void gram_any(int nb, const double* A, int64_t ld, int64_t k0,
+template <int NB, int FMT>
+__device__ __noinline__ void gram_lp_call(const uint8_t* A, int64_t ld, int64_t k0, int64_t k1,
+                                          const int32_t* idx, int m, const double* u,
+                                          double* part, int aligned) {
+  extern __shared__ __attribute__((aligned(16))) double dyn_sm[];
+  ldev::gram_lp_slab<NB, FMT>(uni_ptr(A), uni64(ld), uni64(k0), uni64(k1), uni_ptr(idx), uni(m),
+                              uni_ptr(u), uni_ptr(part), uni(aligned),
+                              reinterpret_cast<uint8_t*>(dyn_sm));
+}
+
+template <int FMT>
+__device__ __forceinline__ void gram_any(int nb, const void* A, int64_t ld, int64_t k0,
                                          int64_t k1, const int32_t* idx, int m, const double* u,
                                          double* part, int aligned) {
-  switch (nb) {
-    case 1: gram_call<1>(A, ld, k0, k1, idx, m, u, part, aligned); break;
-    case 2: gram_call<2>(A, ld, k0, k1, idx, m, u, part, aligned); break;
-    case 4: gram_call<4>(A, ld, k0, k1, idx, m, u, part, aligned); break;
-    case 8: gram_call<8>(A, ld, k0, k1, idx, m, u, part, aligned); break;
-    default: gram_call<16>(A, ld, k0, k1, idx, m, u, part, aligned); break;
+  if constexpr (FMT == CABCD_F64) {
+    const double* a = static_cast<const double*>(A);
+    switch (nb) {
+      case 1: gram_call<1>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      case 2: gram_call<2>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      case 4: gram_call<4>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      case 8: gram_call<8>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      default: gram_call<16>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+    }
+  } else {
+    const uint8_t* a = static_cast<const uint8_t*>(A);
+    switch (nb) {
+      case 1: gram_lp_call<1, FMT>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      case 2: gram_lp_call<2, FMT>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      case 4: gram_lp_call<4, FMT>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      case 8: gram_lp_call<8, FMT>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      default: gram_lp_call<16, FMT>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+    }
   }
 }
 
@@ -254,6 +350,7 @@ __device__ __forceinline__ void queue_exit(BQueue* Q) {
 
 // ------------------------------------------------------------------- kernels
 
+template <int FMT>
 __global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict__ P,
                                                          BState* __restrict__ S,
                                                          const BItem* __restrict__ items,
@@ -286,18 +383,18 @@ __global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict
     __syncthreads();
     if (mp > 0) {
       // deferred companion update of the previous outer step, this slab's columns
-      slab_rows_dot(pr.A, pr.ld, k0, k1, iprev, dprev, mp, nullptr, 0.0, pr.r, pr.aligned);
+      rows_dot<FMT>(pr, k0, k1, iprev, dprev, mp, nullptr, 0.0);
       __syncthreads();   // the Gram below reads these r values back
     }
     const int64_t pstride = (int64_t)(pr.nb * (pr.nb + 1) / 2) * 256 + 16 * pr.nb;
-    gram_any(pr.nb, pr.A, pr.ld, k0, k1, icur, m, pr.r, pr.partials + item.slab * pstride,
-             pr.aligned);
+    gram_any<FMT>(pr.nb, pr.A, pr.ld, k0, k1, icur, m, pr.r, pr.partials + item.slab * pstride,
+                  pr.aligned);
     if (!arrive_last(st, pr.nslab, ctl + 1)) break;
 
     // Last slab of this problem: Gov (overlap-augmented, Alg. 2 scale 1/n and
     // shift lambda), then the fused solve and w[idx] += delta.
     gdev::reduce_wg<kBT>(pr.partials, pr.nslab, pr.nb, icur, m, 1.0 / (double)pr.n, pr.lambda,
-                         pr.G, pr.Yu, 0, nullptr);
+                         pr.G, pr.Yu, FMT == CABCD_F64 ? 0 : 1, pr.rs);
     __syncthreads();
     SolveArgs a;
     a.G = pr.G;
@@ -331,7 +428,7 @@ __global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict
 // MODE 0: r = X^T w - y exactly and f(w) = ||r||^2/(2n) + lambda/2 ||w||^2;
 //         retire the problem when f(w) <= f_target.
 // MODE 1: apply the pending companion update only.
-template <int MODE>
+template <int MODE, int FMT>
 __global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict__ P,
                                                         BState* __restrict__ S,
                                                         const BItem* __restrict__ items,
@@ -350,8 +447,7 @@ __global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict_
     const int64_t k0 = (int64_t)item.slab * pr.chunk;
     const int64_t k1 = std::min(pr.n, k0 + pr.chunk);
     if (MODE == 0) {
-      double ss = slab_rows_dot(pr.A, pr.ld, k0, k1, nullptr, pr.w, (int)pr.d, pr.y, -1.0,
-                                pr.r, pr.aligned);
+      double ss = rows_dot<FMT>(pr, k0, k1, nullptr, pr.w, (int)pr.d, pr.y, -1.0);
       ss = block_sum(ss, red);
       if (tid == 0) glb(pr.objp)[item.slab] = ss;
     } else {
@@ -360,7 +456,7 @@ __global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict_
       if (tid < mp / pr.b) smp::sample_block(pr.seed, hp + tid, pr.b, pr.d, iprev + tid * pr.b);
       for (int q = tid; q < mp; q += kBT) dprev[q] = glb(pr.delta)[q];
       __syncthreads();
-      slab_rows_dot(pr.A, pr.ld, k0, k1, iprev, dprev, mp, nullptr, 0.0, pr.r, pr.aligned);
+      rows_dot<FMT>(pr, k0, k1, iprev, dprev, mp, nullptr, 0.0);
     }
     if (!arrive_last(st, pr.nslab, ctl + 1)) break;
     if (MODE == 0) {
@@ -408,18 +504,26 @@ int64_t pstride_of(int nb) { return (int64_t)(nb * (nb + 1) / 2) * 256 + 16 * nb
 // CUs, the streaming passes at about 5 TB/s, one workgroup reads its partials
 // at about 60 GB/s, and the fused solve costs about 1.5 us per block.
 constexpr double kCuF64 = 48e12 / 256;
+constexpr double kCuLp = 500e12 / 256;   // FP32-accumulating BF16/FP8 Gram, well below peak
 constexpr double kCuBw = 5.0e12 / 256;
 constexpr double kWgBw = 60e9;
 constexpr double kSolveBlock = 1.5e-6;
 constexpr double kRoundFixed = 10e-6;
 
+int elem_bytes(int dtype) { return dtype == CABCD_F64 ? 8 : dtype == CABCD_BF16 ? 2 : 1; }
+
+// Columns per LDS tile of the Gram slab (slab widths are multiples of it).
+int tile_cols(int nb, int dtype) {
+  return dtype == CABCD_F64 ? 256 / nb : (2048 / nb) / elem_bytes(dtype);
+}
+
 // CU-seconds of one problem's slabs in one round (Gram of the padded rows and
 // the two passes over the gathered rows: Gram and deferred update).
-double slab_work(int sb, int64_t cols) {
+double slab_work(int sb, int64_t cols, int dtype) {
   const int sbp = 16 * nb_of(sb);
   const double flops = (double)cols * sbp * (sbp + 1);
-  const double bytes = 16.0 * (double)cols * sb;
-  return std::max(flops / kCuF64, bytes / kCuBw);
+  const double bytes = 2.0 * elem_bytes(dtype) * (double)cols * sb;
+  return std::max(flops / (dtype == CABCD_F64 ? kCuF64 : kCuLp), bytes / kCuBw);
 }
 
 int auto_b(int64_t d) {
@@ -455,16 +559,16 @@ double plan_candidate(const std::vector<cabcd_problem>& pb, double rp, int cus,
     }
     out[p].b = b;
     out[p].s = s;
-    W += slab_work(b * s, pb[p].X.cols);
+    W += slab_work(b * s, pb[p].X.cols, pb[p].X.dtype);
   }
   const double target = std::max(W / (4.0 * cus), 20e-6);
   double crit = 0.0, passes = 0.0;
   for (size_t p = 0; p < P; ++p) {
     const int sb = out[p].b * out[p].s;
     const int nb = nb_of(sb);
-    const int kt = 256 / nb;
+    const int kt = tile_cols(nb, pb[p].X.dtype);
     const int64_t n = pb[p].X.cols;
-    const double wp = slab_work(sb, n);
+    const double wp = slab_work(sb, n, pb[p].X.dtype);
     int64_t nslab = (int64_t)std::ceil(wp / target);
     nslab = std::max<int64_t>(1, std::min<int64_t>(nslab, kBMaxSlabs));
     nslab = std::min<int64_t>(nslab, (n + kt - 1) / kt);
@@ -519,25 +623,51 @@ struct cabcd_batch_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_rounds = 0;
+  int dtype = CABCD_F64;   // storage type shared by every problem of the plan
 };
 
 namespace cabcd {
 namespace {
 
-hipError_t launch_step(cabcd_batch_plan* B, hipStream_t st) {
-  hipLaunchKernelGGL(batch_step_kernel, dim3(B->grid_step), dim3(kBT), B->step_lds, st, B->dP,
-                     B->dS, B->dI, B->nitems, B->dQ, B->area);
+template <int FMT>
+hipError_t launch_step_t(cabcd_batch_plan* B, hipStream_t st) {
+  hipLaunchKernelGGL(batch_step_kernel<FMT>, dim3(B->grid_step), dim3(kBT), B->step_lds, st,
+                     B->dP, B->dS, B->dI, B->nitems, B->dQ, B->area);
   return hipGetLastError();
 }
 
-hipError_t launch_aux(cabcd_batch_plan* B, int mode, hipStream_t st) {
-  if (mode == 0)
-    hipLaunchKernelGGL(batch_aux_kernel<0>, dim3(B->grid_aux), dim3(kBT), 0, st, B->dP, B->dS,
-                       B->dI, B->nitems, B->dQ);
-  else
-    hipLaunchKernelGGL(batch_aux_kernel<1>, dim3(B->grid_aux), dim3(kBT), 0, st, B->dP, B->dS,
-                       B->dI, B->nitems, B->dQ);
+template <int MODE, int FMT>
+hipError_t launch_aux_t(cabcd_batch_plan* B, hipStream_t st) {
+  hipLaunchKernelGGL((batch_aux_kernel<MODE, FMT>), dim3(B->grid_aux), dim3(kBT), 0, st, B->dP,
+                     B->dS, B->dI, B->nitems, B->dQ);
   return hipGetLastError();
+}
+
+hipError_t launch_step(cabcd_batch_plan* B, hipStream_t st) {
+  switch (B->dtype) {
+    case CABCD_F64: return launch_step_t<CABCD_F64>(B, st);
+    case CABCD_BF16: return launch_step_t<CABCD_BF16>(B, st);
+    default: return launch_step_t<CABCD_FP8_E4M3>(B, st);
+  }
+}
+
+hipError_t launch_aux(cabcd_batch_plan* B, int mode, hipStream_t st) {
+  switch (B->dtype * 2 + mode) {
+    case CABCD_F64 * 2: return launch_aux_t<0, CABCD_F64>(B, st);
+    case CABCD_F64 * 2 + 1: return launch_aux_t<1, CABCD_F64>(B, st);
+    case CABCD_BF16 * 2: return launch_aux_t<0, CABCD_BF16>(B, st);
+    case CABCD_BF16 * 2 + 1: return launch_aux_t<1, CABCD_BF16>(B, st);
+    case CABCD_FP8_E4M3 * 2: return launch_aux_t<0, CABCD_FP8_E4M3>(B, st);
+    default: return launch_aux_t<1, CABCD_FP8_E4M3>(B, st);
+  }
+}
+
+const void* step_kernel_ptr(int dtype) {
+  switch (dtype) {
+    case CABCD_F64: return reinterpret_cast<const void*>(batch_step_kernel<CABCD_F64>);
+    case CABCD_BF16: return reinterpret_cast<const void*>(batch_step_kernel<CABCD_BF16>);
+    default: return reinterpret_cast<const void*>(batch_step_kernel<CABCD_FP8_E4M3>);
+  }
 }
 
 #define BATCH_HIP(call)                                                     \
@@ -551,17 +681,27 @@ hipError_t launch_aux(cabcd_batch_plan* B, int mode, hipStream_t st) {
 
 cabcd_status check_problem(const cabcd_problem& q, int p) {
   const cabcd_matrix& X = q.X;
-  if (X.kind != CABCD_DENSE || X.dtype != CABCD_F64) {
-    set_error("problem %d: the batched path takes dense FP64 X", p);
+  if (X.kind != CABCD_DENSE) {
+    set_error("problem %d: the batched path takes dense X (FP64, BF16 or FP8-E4M3)", p);
     return CABCD_EUNSUPPORTED;
+  }
+  if (X.dtype != CABCD_F64 && X.dtype != CABCD_BF16 && X.dtype != CABCD_FP8_E4M3) {
+    set_error("problem %d: unknown dtype %d", p, X.dtype);
+    return CABCD_EINVAL;
+  }
+  if (X.dtype == CABCD_FP8_E4M3 && X.row_scale == nullptr) {
+    set_error("problem %d: FP8 storage needs its row scales", p);
+    return CABCD_EINVAL;
   }
   if (X.data == nullptr || q.y == nullptr || q.w == nullptr || q.r == nullptr) {
     set_error("problem %d: X, y, w and r must be non-NULL device pointers", p);
     return CABCD_EINVAL;
   }
   const auto mis = [](const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 7) != 0; };
-  if (mis(X.data) || mis(q.y) || mis(q.w) || mis(q.r)) {
-    set_error("problem %d: X, y, w and r must be 8-byte aligned", p);
+  if (mis(q.y) || mis(q.w) || mis(q.r) ||
+      (reinterpret_cast<uintptr_t>(X.data) % elem_bytes(X.dtype)) != 0 ||
+      (reinterpret_cast<uintptr_t>(X.row_scale) & 3) != 0) {
+    set_error("problem %d: X, y, w, r and row_scale must be aligned to their element size", p);
     return CABCD_EINVAL;
   }
   if (X.rows < 1 || X.cols < 1 || X.rows > INT_MAX || X.cols > INT_MAX || X.ld < X.cols) {
@@ -623,6 +763,7 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   BATCH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
   cus = std::max(cus, 1);
   B->P = P;
+  B->dtype = pb[0].X.dtype;
   B->monitor_every = opts != nullptr ? opts->monitor_every : 4;
   B->flags = opts != nullptr ? opts->flags : 0u;
 
@@ -667,8 +808,16 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
     add(sizeof(double) * best[p].nslab);
     area = std::max<int>(area, (int)((solve_lds_bytes(sb, best[p].b) + 7) / 8));
   }
-  area = std::max<int>(area, gdev::Cfg<16, 2>::LDS);
-  area = std::max<int>(area, gdev::Cfg<1, 2>::LDS);
+  if (B->dtype == CABCD_F64) {
+    area = std::max<int>(area, gdev::Cfg<16, 2>::LDS);
+    area = std::max<int>(area, gdev::Cfg<1, 2>::LDS);
+  } else {
+    const int lp = B->dtype == CABCD_BF16
+                       ? std::max(ldev::LpCfg<16, CABCD_BF16>::LDS, ldev::LpCfg<1, CABCD_BF16>::LDS)
+                       : std::max(ldev::LpCfg<16, CABCD_FP8_E4M3>::LDS,
+                                  ldev::LpCfg<1, CABCD_FP8_E4M3>::LDS);
+    area = std::max<int>(area, (lp + 7) / 8);
+  }
   B->area = (area + 1) & ~1;
   B->step_lds = sizeof(double) * B->area + kBMaxRows * 2 * sizeof(int32_t) +
                 kBMaxRows * sizeof(double) + 4 * sizeof(int);
@@ -688,7 +837,8 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
     const cabcd_problem& q = pb[p];
     BProb& o = B->probs[p];
     const int sb = best[p].b * best[p].s;
-    o.A = static_cast<const double*>(q.X.data);
+    o.A = q.X.data;
+    o.rs = q.X.dtype == CABCD_F64 ? nullptr : q.X.row_scale;
     o.ld = q.X.ld;
     o.d = q.X.rows;
     o.n = q.X.cols;
@@ -705,7 +855,10 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
     o.bp = pow2_at_least(o.b);
     o.nb = nb_of(sb);
     o.nslab = best[p].nslab;
-    o.aligned = ((reinterpret_cast<uintptr_t>(o.A) & 15) == 0 && (o.ld & 1) == 0) ? 1 : 0;
+    o.aligned = ((reinterpret_cast<uintptr_t>(o.A) & 15) == 0 &&
+                 ((o.ld * elem_bytes(B->dtype)) & 15) == 0)
+                    ? 1
+                    : 0;
     o.partials = ws.take<double>((size_t)o.nslab * pstride_of(o.nb));
     o.G = ws.take<double>((size_t)sb * sb);
     o.Yu = ws.take<double>(sb);
@@ -724,13 +877,14 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   BATCH_HIP(hipMemcpyAsync(B->dQ, &q0, sizeof q0, hipMemcpyHostToDevice, st));
 
   // Persistent grids: as many workgroups as fit on the device at once.
-  BATCH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(batch_step_kernel),
+  BATCH_HIP(hipFuncSetAttribute(step_kernel_ptr(B->dtype),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)B->step_lds));
   int occ = 0;
-  BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_step_kernel, kBT,
+  BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_kernel_ptr(B->dtype), kBT,
                                                          B->step_lds));
   B->grid_step = std::max(1, std::min(B->nitems, std::max(occ, 1) * cus));
-  BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_aux_kernel<0>, kBT, 0));
+  BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &occ, reinterpret_cast<const void*>(batch_aux_kernel<0, CABCD_F64>), kBT, 0));
   B->grid_aux = std::max(1, std::min(B->nitems, std::max(occ, 1) * cus));
 
   // r_0 = X^T w_0 - y and f(w_0).
@@ -786,6 +940,10 @@ cabcd_status cabcd_batch_create(const cabcd_problem* problems, int32_t P,
   for (int p = 0; p < P; ++p) {
     const cabcd_status rc = check_problem(problems[p], p);
     if (rc != CABCD_OK) return rc;
+    if (problems[p].X.dtype != problems[0].X.dtype) {
+      set_error("problem %d: every problem of a batch must use the same storage type", p);
+      return CABCD_EINVAL;
+    }
   }
   cabcd_batch_plan* B = new cabcd_batch_plan();
   const cabcd_status rc = create(problems, P, opts, static_cast<hipStream_t>(stream), B);

@@ -10,13 +10,15 @@
 // The method then runs on X^ (exact in FP64): the Gram uses the stored codes on
 // the matrix cores with FP32 accumulation and applies s_p s_q in FP64, while
 // Y u, the companion updates and the exact recomputation decode to FP64.
-#include "internal.h"
+#include "lowp_dev.h"
 
 #include <algorithm>
 #include <cmath>
 
 namespace cabcd {
 namespace {
+
+using namespace ldev;
 
 constexpr int kQThreads = 256;
 
@@ -81,121 +83,6 @@ __global__ __launch_bounds__(kQThreads) void quantize_kernel(const double* __res
   if (threadIdx.x == 0) row_scale[r] = s;
 }
 
-// ---------------------------------------------------------------- Gram
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int kLpThreads = 512;   // 8 waves, two block rows each
-
-// FMT: CABCD_BF16 (2-byte elements, one MFMA per 16-byte fragment) or
-// CABCD_FP8_E4M3 (1-byte elements, two MFMAs per 16-byte fragment).
-template <int NB, int FMT>
-struct LpCfg {
-  static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;      // element bytes
-  static constexpr int SBP = 16 * NB;
-  static constexpr int NBLK = NB * (NB + 1) / 2;
-  static constexpr int RB = 2048 / NB;                      // tile row bytes: tile = 32 KiB
-  static constexpr int RSB = RB + 16;                       // LDS row stride in bytes
-  static constexpr int KT = RB / ES;                        // tile width in elements
-  static constexpr int EPC = 16 / ES;                       // elements per 16-byte chunk
-  static constexpr int CH = RB / 16;                        // chunks per row
-  static constexpr int NCH = SBP * CH / kLpThreads;         // chunks per thread (= 4)
-  static constexpr int WIN = RB / 64;                       // 64-byte windows per tile row
-  static constexpr int BW = NB >= 2 ? NB / 2 : 1;
-  static constexpr int KG = 8 / BW;
-  static constexpr int NACC = NB >= 2 ? NB + 1 : 1;
-  static constexpr int TILE = SBP * RSB;                    // bytes
-  static constexpr int RED = (KG - 1) * NBLK * 256 * 4;     // bytes (FP32 partial blocks)
-  static constexpr int YUS = SBP * CH * 8;                  // bytes
-  static constexpr int LDS = std::max(std::max(2 * TILE, RED), YUS);
-  static_assert(NCH * kLpThreads == SBP * CH, "tile must split evenly");
-  static_assert(WIN % KG == 0, "windows must split evenly");
-};
-
-__device__ __forceinline__ int lp_blk_index(int r, int c) { return r * (r + 1) / 2 + c; }
-
-template <int NB>
-__device__ __forceinline__ int lp_acc_block(int bw, int a) {
-  if (NB == 1) return 0;
-  const int r1 = bw, r2 = NB - 1 - bw;
-  return a <= r1 ? lp_blk_index(r1, a) : lp_blk_index(r2, a - r1 - 1);
-}
-
-template <int FMT>
-__device__ __forceinline__ f4 lp_mma(const uint4& a, const uint4& b, f4 c) {
-  if constexpr (FMT == CABCD_BF16) {
-    bf16x8 x, y;
-    __builtin_memcpy(&x, &a, 16);
-    __builtin_memcpy(&y, &b, 16);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
-  } else {
-    const long a0 = (long)(((uint64_t)a.y << 32) | a.x), b0 = (long)(((uint64_t)b.y << 32) | b.x);
-    const long a1 = (long)(((uint64_t)a.w << 32) | a.z), b1 = (long)(((uint64_t)b.w << 32) | b.z);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
-  }
-}
-
-template <int NB, int FMT, int W>
-__device__ __forceinline__ void lp_tile(const uint8_t* __restrict__ tile, int lane, int kg,
-                                        f4 (&acc)[LpCfg<NB, FMT>::NACC]) {
-  using C = LpCfg<NB, FMT>;
-  constexpr int R1 = NB >= 2 ? W : 0;
-  constexpr int R2 = NB >= 2 ? NB - 1 - W : 0;
-  const uint8_t* base = tile + (lane & 15) * C::RSB + 16 * (lane >> 4);
-#pragma unroll
-  for (int p = 0; p < C::WIN / C::KG; ++p) {
-    const int off = 64 * (kg + p * C::KG);
-    auto frag = [&](int r) {
-      return *reinterpret_cast<const uint4*>(base + r * 16 * C::RSB + off);
-    };
-    const uint4 f1 = frag(R1);
-    const uint4 f2 = NB >= 2 ? frag(R2) : f1;
-#pragma unroll
-    for (int c = 0; c <= R2; ++c) {
-      const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-      if (c <= R1) acc[c] = lp_mma<FMT>(f1, fc, acc[c]);
-      if constexpr (NB >= 2) acc[R1 + 1 + c] = lp_mma<FMT>(f2, fc, acc[R1 + 1 + c]);
-    }
-  }
-}
-
-template <int NB, int FMT, int W = 0>
-__device__ __forceinline__ void lp_dispatch(int bw, const uint8_t* tile, int lane, int kg,
-                                            f4 (&acc)[LpCfg<NB, FMT>::NACC]) {
-  if constexpr (W < LpCfg<NB, FMT>::BW) {
-    if (bw == W)
-      lp_tile<NB, FMT, W>(tile, lane, kg, acc);
-    else
-      lp_dispatch<NB, FMT, W + 1>(bw, tile, lane, kg, acc);
-  }
-}
-
-template <int FMT>
-__device__ __forceinline__ double lp_decode(const uint4& v, int e) {
-  const uint32_t words[4] = {v.x, v.y, v.z, v.w};
-  if constexpr (FMT == CABCD_BF16) {
-    return decode_bf16((uint16_t)(words[e >> 1] >> (16 * (e & 1))));
-  } else {
-    return decode_e4m3((words[e >> 2] >> (8 * (e & 3))) & 0xFF);
-  }
-}
-
-// 16-byte chunk of row `row` starting at element k (zeros past k_end).
-template <int FMT>
-__device__ __forceinline__ uint4 lp_load(const uint8_t* __restrict__ row, int64_t k,
-                                         int64_t k_end, bool aligned) {
-  constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;
-  constexpr int EPC = 16 / ES;
-  if (k + EPC <= k_end && aligned) return *reinterpret_cast<const uint4*>(row + k * ES);
-  uint8_t b[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) b[e] = (k + e / ES < k_end) ? row[k * ES + e] : 0;
-  uint4 v;
-  __builtin_memcpy(&v, b, 16);
-  return v;
-}
-
 template <int NB, int FMT>
 __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
     const uint8_t* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
@@ -203,115 +90,10 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
     int aligned) {
   using C = LpCfg<NB, FMT>;
   __shared__ __attribute__((aligned(16))) uint8_t lds[C::LDS];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int bw = wave % C::BW;
-  const int kg = wave / C::BW;
-  const int c = tid % C::CH;
   const int64_t k_begin = (int64_t)blockIdx.x * chunk;
   const int64_t k_end = std::min(cols, k_begin + chunk);
-  const int ntiles = (int)((k_end - k_begin + C::KT - 1) / C::KT);
-
-  int rho[C::NCH];
-  const uint8_t* rowp[C::NCH];
-#pragma unroll
-  for (int i = 0; i < C::NCH; ++i) {
-    rho[i] = tid / C::CH + (kLpThreads / C::CH) * i;
-    rowp[i] = rho[i] < m ? A + (int64_t)idx[rho[i]] * ld * C::ES : nullptr;
-  }
-  const bool want_u = u != nullptr;
-  double yu[C::NCH];
-  uint4 buf[C::NCH];
-  double ub[C::EPC];
-#pragma unroll
-  for (int i = 0; i < C::NCH; ++i) yu[i] = 0.0;
-
-  auto load_tile = [&](int t) {
-    const int64_t k = k_begin + (int64_t)t * C::KT + (int64_t)C::EPC * c;
-    if (want_u) {
-#pragma unroll
-      for (int e = 0; e < C::EPC; ++e) ub[e] = (k + e < k_end) ? u[k + e] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < C::NCH; ++i)
-      buf[i] = rowp[i] ? lp_load<FMT>(rowp[i], k, k_end, aligned != 0) : make_uint4(0, 0, 0, 0);
-  };
-  auto store_tile = [&](int slot) {
-    uint8_t* T = lds + slot * C::TILE;
-#pragma unroll
-    for (int i = 0; i < C::NCH; ++i) {
-      *reinterpret_cast<uint4*>(T + rho[i] * C::RSB + 16 * c) = buf[i];
-      if (want_u) {
-#pragma unroll
-        for (int e = 0; e < C::EPC; ++e) yu[i] = fma(lp_decode<FMT>(buf[i], e), ub[e], yu[i]);
-      }
-    }
-  };
-
-  f4 acc[C::NACC];
-#pragma unroll
-  for (int a = 0; a < C::NACC; ++a) acc[a] = f4{0.f, 0.f, 0.f, 0.f};
-  load_tile(0);
-  store_tile(0);
-  __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
-    const bool more = t + 1 < ntiles;
-    if (more) load_tile(t + 1);
-    lp_dispatch<NB, FMT>(bw, lds + (t & 1) * C::TILE, lane, kg, acc);
-    if (more) store_tile((t + 1) & 1);
-    __syncthreads();
-  }
-
-  double* part = partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP);
-  float* red = reinterpret_cast<float*>(lds);
-  if constexpr (C::KG > 1) {
-    if (kg > 0) {
-#pragma unroll
-      for (int a = 0; a < C::NACC; ++a) {
-        float* dst = red + ((kg - 1) * C::NBLK + lp_acc_block<NB>(bw, a)) * 256 + lane;
-        dst[0] = acc[a][0];
-        dst[64] = acc[a][1];
-        dst[128] = acc[a][2];
-        dst[192] = acc[a][3];
-      }
-    }
-    __syncthreads();
-    if (kg == 0) {
-      for (int g = 1; g < C::KG; ++g) {
-#pragma unroll
-        for (int a = 0; a < C::NACC; ++a) {
-          const float* src = red + ((g - 1) * C::NBLK + lp_acc_block<NB>(bw, a)) * 256 + lane;
-          acc[a][0] += src[0];
-          acc[a][1] += src[64];
-          acc[a][2] += src[128];
-          acc[a][3] += src[192];
-        }
-      }
-    }
-  }
-  if (kg == 0) {
-#pragma unroll
-    for (int a = 0; a < C::NACC; ++a) {
-      double* dst = part + lp_acc_block<NB>(bw, a) * 256 + lane;
-      dst[0] = acc[a][0];
-      dst[64] = acc[a][1];
-      dst[128] = acc[a][2];
-      dst[192] = acc[a][3];
-    }
-  }
-  if (want_u) {
-    __syncthreads();
-    double* ys = reinterpret_cast<double*>(lds);
-#pragma unroll
-    for (int i = 0; i < C::NCH; ++i) ys[rho[i] * C::CH + c] = yu[i];
-    __syncthreads();
-    if (tid < C::SBP) {
-      double s = 0.0;
-      for (int q = 0; q < C::CH; ++q) s += ys[tid * C::CH + q];
-      part[C::NBLK * 256 + tid] = s;
-    }
-  }
+  gram_lp_slab<NB, FMT>(A, ld, k_begin, k_end, idx, m, u,
+                        partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP), aligned, lds);
 }
 
 template <int NB, int FMT>
@@ -369,16 +151,21 @@ __global__ __launch_bounds__(kLvThreads) void gemv_t_lp_kernel(
       x[q] = lp_load<FMT>(A + row * ld * ES, k, cols, aligned != 0);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
+      double dv[EPC];
+      lp_decode_all<FMT>(x[q], dv);
 #pragma unroll
-      for (int e = 0; e < EPC; ++e) acc[e] = fma(lp_decode<FMT>(x[q], e), c[q], acc[e]);
+      for (int e = 0; e < EPC; ++e) acc[e] = fma(dv[e], c[q], acc[e]);
+    }
   }
   for (; p < m; ++p) {
     const int64_t row = idx ? (int64_t)idx[p] : p;
     const double cq = v[p] * (rs ? (double)rs[row] : 1.0);
     const uint4 x = lp_load<FMT>(A + row * ld * ES, k, cols, aligned != 0);
+    double dv[EPC];
+    lp_decode_all<FMT>(x, dv);
 #pragma unroll
-    for (int e = 0; e < EPC; ++e) acc[e] = fma(lp_decode<FMT>(x, e), cq, acc[e]);
+    for (int e = 0; e < EPC; ++e) acc[e] = fma(dv[e], cq, acc[e]);
   }
 #pragma unroll
   for (int e = 0; e < EPC; ++e) {

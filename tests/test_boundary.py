@@ -143,5 +143,14 @@ def test_batch_plan_errors():
     assert lib.cabcd_batch_run(None, 1, None, None) == cabcd.EINVAL
     assert lib.cabcd_batch_query(None, 0, None, None) == cabcd.EINVAL
     assert lib.cabcd_batch_destroy(None) == cabcd.OK
-    probs[0].X.dtype = cabcd.BF16
+    probs[0].X.kind = cabcd.CSR_KIND
     assert lib.cabcd_batch_create(probs, 1, None, None, ctypes.byref(h)) == cabcd.EUNSUPPORTED
+    probs[0].X.kind, probs[0].X.dtype = cabcd.DENSE, cabcd.FP8_E4M3
+    assert lib.cabcd_batch_create(probs, 1, None, None, ctypes.byref(h)) == cabcd.EINVAL
+    assert "row scales" in lib.cabcd_last_error().decode()
+    probs[0].X.dtype = 9
+    assert lib.cabcd_batch_create(probs, 1, None, None, ctypes.byref(h)) == cabcd.EINVAL
+    two = (cabcd.Problem * 2)(_fake_problem(), _fake_problem())
+    two[1].X.dtype = cabcd.BF16
+    assert lib.cabcd_batch_create(two, 2, None, None, ctypes.byref(h)) == cabcd.EINVAL
+    assert "same storage type" in lib.cabcd_last_error().decode()

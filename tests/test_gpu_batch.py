@@ -150,3 +150,54 @@ def test_batch_one_shot_and_nonfinite(gpu_lib):
         gpu_lib.primal_bcd_batched(probs, 1000, monitor_every=3)
     assert e.value.status in (gpu_lib.ENOTSPD, gpu_lib.ENONFINITE)
     assert "problem 1" in str(e.value)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_batch_lowp_reaches_1e6_on_dequantised(gpu_lib, dtype):
+    """BF16 / FP8 storage: each problem is (X^, y, lambda) with X^ the stored
+    matrix; it must reach 1e-6 relative objective error against the closed form
+    on X^ and be retired by its target; r at the last monitor point equals
+    X^ T w - y.  The distance to the FP64 oracle's iterates on X^ with the same
+    blocks is reported, not pinned (the Gram is accumulated in FP32)."""
+    P = 12
+    ds, ns, lams = synth.ridge_batch(P, 78, d_range=(32, 300), n_range=(2048, 20000),
+                                     lam_range=(1e-4, 1e-1))
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    _say("batch", dtype, "P =", P)
+    probs = []
+    for p in range(P):
+        X, y, _ = synth.gaussian_ridge(ds[p], ns[p], 1200 + p)
+        Q = gpu_lib.quantize(X.to(DEV), code)
+        Xh = Q.dequantize().cpu().numpy()
+        yc = y.numpy()
+        fst = bcd.primal_objective(Xh, yc, lams[p], bcd.ridge_closed_form(Xh, yc, lams[p]))
+        probs.append(dict(X=Q, y=y.to(DEV), lam=lams[p], seed=4000 + p,
+                          f_target=fst * (1 + 1e-6), Xh=Xh, yc=yc, fst=fst))
+    with gpu_lib.Batch(probs, monitor_every=4) as B:
+        rounds, act = 0, P
+        while act > 0 and rounds < 4000:
+            act = B.run(4)
+            rounds += 4
+        infos = [B.info(p) for p in range(P)]
+    _say(f"  all retired after {rounds} rounds")
+    assert act == 0
+    for q, inf in zip(probs, infos):
+        w = q["w"].cpu().numpy()
+        rel = (bcd.primal_objective(q["Xh"], q["yc"], q["lam"], w) - q["fst"]) / q["fst"]
+        assert rel <= 1e-6 * (1 + 1e-6)
+        r = q["r"].cpu().numpy()
+        assert np.linalg.norm(r - (q["Xh"].T @ w - q["yc"])) <= 1e-12 * np.linalg.norm(q["yc"])
+    q, inf = probs[0], infos[0]
+    wo, _ = bcd.primal_bcd(q["Xh"], q["yc"], q["lam"], inf["b"], inf["s"], inf["h"], q["seed"])
+    _say(f"  problem 0: ||w - w_fp64 oracle|| / ||w_fp64|| = "
+         f"{np.linalg.norm(q['w'].cpu().numpy() - wo) / np.linalg.norm(wo):.2e} (reported)")
+
+
+def test_batch_mixed_storage_types_rejected(gpu_lib):
+    X, y, _ = synth.gaussian_ridge(16, 256, 1)
+    Xd = X.to(DEV)
+    probs = [dict(X=Xd, y=y.to(DEV), lam=0.1, b=4, s=2, H=8),
+             dict(X=gpu_lib.quantize(Xd, gpu_lib.BF16), y=y.to(DEV), lam=0.1, b=4, s=2, H=8)]
+    with pytest.raises(gpu_lib.CabcdError) as e:
+        gpu_lib.Batch(probs)
+    assert e.value.status == gpu_lib.EINVAL

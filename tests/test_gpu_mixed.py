@@ -115,3 +115,43 @@ def test_mixed_dual_is_unsupported(gpu_lib):
     with pytest.raises(gpu_lib.CabcdError) as e:
         gpu_lib.dual_bcd(Q, y.to(DEV), 0.1, 4, 2, 4, 0)
     assert e.value.status == gpu_lib.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_every_code_decodes_exactly(gpu_lib, dtype):
+    """Every finite storage code, through the Gram's FP64 Y u and through the
+    FP64 streaming pass of the exact residual, against the oracle's decoder."""
+    _say("decode all codes", dtype)
+    if dtype == "fp8":
+        codes = np.array([c for c in range(256) if c & 0x7F != 0x7F], dtype=np.uint8)
+        want = quant.e4m3_decode(codes)
+        ct = torch.tensor(codes, dtype=torch.uint8)
+        code, scales = gpu_lib.FP8_E4M3, torch.ones(len(codes), dtype=torch.float32, device=DEV)
+    else:
+        bits = np.arange(65536, dtype=np.uint32)
+        finite = ((bits >> 7) & 0xFF) != 0xFF
+        codes = bits[finite].astype(np.uint16)
+        want = quant.bf16_decode(codes)
+        ct = torch.tensor(codes.view(np.int16), dtype=torch.int16)
+        code, scales = gpu_lib.BF16, None
+    m, cols = len(codes), 40
+    Qc = torch.zeros((m, cols), dtype=ct.dtype)
+    Qc[:, 0] = ct
+    Q = gpu_lib.Quantized(Qc.to(DEV), scales, code)
+    u = torch.zeros(cols, dtype=torch.float64, device=DEV)
+    u[0] = 1.0
+    for r0 in range(0, m, 256):
+        r1 = min(m, r0 + 256)
+        idx = torch.arange(r0, r1, dtype=torch.int32, device=DEV)
+        _, Yu = gpu_lib.gram(Q, idx, 1.0, 0.0, u)
+        assert np.array_equal(Yu.cpu().numpy(), want[r0:r1])
+    # streaming pass: r = X^T w - y with w picking one code per column sum
+    rng = np.random.default_rng(5)
+    w = rng.integers(-4, 5, size=m).astype(np.float64)
+    w[(np.abs(want) > 1e20) | ((np.abs(want) < 1e-20) & (want != 0))] = 0.0   # keep the sum finite
+    y = torch.zeros(cols, dtype=torch.float64, device=DEV)
+    _, r = gpu_lib.primal_objective(Q, y, 1.0, torch.tensor(w, device=DEV))
+    ref = float(np.sum(w * want))
+    got = r.cpu().numpy()
+    assert abs(got[0] - ref) <= 1e-13 * np.sum(np.abs(w * want))
+    assert np.all(got[1:] == 0.0)
