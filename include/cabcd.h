@@ -94,6 +94,9 @@ typedef struct cabcd_matrix {
 #define CABCD_FLAG_STATE_VALID 1u  /* primal: r already holds X^T w - y on entry;
                                       dual: w already holds -X a/(lambda n)       */
 #define CABCD_FLAG_ASYNC 2u        /* do not synchronise; device status is lost   */
+#define CABCD_FLAG_MONITOR_MAINTAINED 4u  /* primal: monitor points evaluate f(w)
+                                             from the maintained residual r instead
+                                             of recomputing X^T w - y              */
 
 typedef struct cabcd_opts {
   int64_t h0;                /* global index of the first inner iteration (resume) */
@@ -241,9 +244,10 @@ cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha,
  * queue; the last slab of a problem to finish sums its partials, runs the
  * fused solve and records the step).  The companion update r += Y^T delta of a
  * step is applied by the next round's slabs on their own columns.  Every
- * monitor_every rounds a second persistent launch recomputes r = X^T w - y
- * exactly and the objective f(w), and retires problems that reached f_target.
- * Both launches are captured once into a hipGraph and replayed.
+ * monitor_every rounds a second persistent launch evaluates the objective f(w)
+ * (recomputing r = X^T w - y exactly, or from the maintained residual, see
+ * cheap_monitors) and retires problems that reached f_target.  The launches
+ * are captured once into hipGraphs and replayed.
  *
  * Per problem, the iterates are those of cabcd_primal_bcd with the same X, y,
  * lambda, b, s, seed and H (the same blocks), up to rounding order.
@@ -269,9 +273,15 @@ typedef struct cabcd_problem {
 #define CABCD_BATCH_NO_GRAPH 1u    /* launch every kernel directly (no hipGraph)   */
 
 typedef struct cabcd_batch_opts {
-  int32_t monitor_every;     /* rounds between exact recomputations (default 4;
-                                0: never, then only the budgets H end problems)    */
+  int32_t monitor_every;     /* rounds between monitor points (default 4; 0: never,
+                                then only the budgets H end problems)              */
   uint32_t flags;            /* CABCD_BATCH_*                                      */
+  int32_t cheap_monitors;    /* monitor points between two exact ones at which the
+                                pending update is applied and f(w) is evaluated
+                                from the maintained residual instead of
+                                recomputing r = X^T w - y from X (0: every monitor
+                                point is exact)                                    */
+  int32_t reserved;
 } cabcd_batch_opts;
 
 /* What the plan chose for one problem and where it stands. */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcabcd.so")
 OK, EINVAL, ENOTSPD, EHIP, ENOMEM, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 DENSE, CSR_KIND = 0, 1
 F64, BF16, FP8_E4M3 = 0, 1, 2
-FLAG_STATE_VALID, FLAG_ASYNC = 1, 2
+FLAG_STATE_VALID, FLAG_ASYNC, FLAG_MONITOR_MAINTAINED = 1, 2, 4
 
 _STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOTSPD: "ENOTSPD", EHIP: "EHIP",
                  ENOMEM: "ENOMEM", EUNSUPPORTED: "EUNSUPPORTED", ENONFINITE: "ENONFINITE"}
@@ -57,7 +57,8 @@ class Problem(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("monitor_every", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+    _fields_ = [("monitor_every", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("cheap_monitors", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -420,11 +421,12 @@ class Batch:
     `problems` is a list of dicts (see _problems); w and r are created when
     absent and written in place (q["w"], q["r"])."""
 
-    def __init__(self, problems, monitor_every=4, graph=True):
+    def __init__(self, problems, monitor_every=4, graph=True, cheap_monitors=0):
         self.problems = problems
         arr, self._keep = _problems(problems)
         o = BatchOpts()
         o.monitor_every, o.flags = monitor_every, 0 if graph else BATCH_NO_GRAPH
+        o.cheap_monitors = cheap_monitors
         h = ctypes.c_void_p()
         _check(load().cabcd_batch_create(arr, len(problems), ctypes.byref(o), _stream(),
                                          ctypes.byref(h)))
@@ -462,12 +464,13 @@ class Batch:
             pass
 
 
-def primal_bcd_batched(problems, max_rounds, monitor_every=4, graph=True):
+def primal_bcd_batched(problems, max_rounds, monitor_every=4, graph=True, cheap_monitors=0):
     """One-shot batched solve (plan, run until no problem is active or
     max_rounds, release).  Results are written to each problem's w and r."""
     arr, keep = _problems(problems)
     o = BatchOpts()
     o.monitor_every, o.flags = monitor_every, 0 if graph else BATCH_NO_GRAPH
+    o.cheap_monitors = cheap_monitors
     _check(load().cabcd_primal_bcd_batched(arr, len(problems), max_rounds, ctypes.byref(o),
                                            _stream()))
     del keep

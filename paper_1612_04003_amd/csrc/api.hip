@@ -473,10 +473,11 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     return mat_scatter(M, nullptr, rows, coord, 1.0, y, -1.0, false, comp, B.scratch, st);
   };
   // f(w) at a monitor point.  fresh: the primal residual comp was recomputed
-  // exactly in this outer step, so it is used instead of another full pass.
+  // exactly in this outer step, so it is used instead of another full pass;
+  // CABCD_FLAG_MONITOR_MAINTAINED asks for the maintained residual always.
   auto monitor = [&](int64_t slot, bool fresh) -> hipError_t {
     hipError_t he;
-    if (!dual && fresh)
+    if (!dual && (fresh || (o.flags & CABCD_FLAG_MONITOR_MAINTAINED)))
       return launch_objective(comp, cols, 0.5 / n, coord, rows, 0.5 * lambda, o.trace + slot,
                               B.obj, B.status, st);
     if (dual) {   // f(w) with r = X^T w - y computed from the X^T layout

@@ -15,9 +15,12 @@
 //      slabs sums the partials in slab order (deterministic), runs the fused
 //      solve of the s blocks (Cholesky/recurrence, w[idx] += delta) and records
 //      the step.  No workgroup ever waits for another.
-// A second persistent kernel recomputes r = X^T w - y exactly and f(w) (the
-// periodic full residual of the paper's stopping discussion) or flushes the
-// pending update.  The plan captures both into a hipGraph.
+// A second persistent kernel evaluates f(w) every few rounds, either
+// recomputing r = X^T w - y exactly from X (the periodic full residual of the
+// paper's stopping discussion) or from the maintained residual after applying
+// the pending update, and retires problems that reached their target; it also
+// flushes the pending update at the end of a run.  The plan captures one
+// monitor period into hipGraphs.
 #include "gram_dev.h"
 #include "lowp_dev.h"
 #include "solve_dev.h"
@@ -67,7 +70,7 @@ struct BState {                    // mutable per problem
   int active;                      // still iterating
   int arrive;                      // slab arrivals in the current launch
   int status;                      // DeviceStatus (sticky)
-  int fresh;                       // r exact and obj current
+  int fresh;                       // 0: stale, 1: obj from the maintained r, 2: r exact
   int pad[3];
 };
 
@@ -425,9 +428,13 @@ __global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict
   queue_exit(Q);
 }
 
-// MODE 0: r = X^T w - y exactly and f(w) = ||r||^2/(2n) + lambda/2 ||w||^2;
-//         retire the problem when f(w) <= f_target.
-// MODE 1: apply the pending companion update only.
+// MODE 0 (exact): r = X^T w - y recomputed from X, f(w) = ||r||^2/(2n) +
+//         lambda/2 ||w||^2, retire the problem when f(w) <= f_target;
+// MODE 1 (flush): apply the pending companion update only;
+// MODE 2 (monitor): apply the pending update and evaluate f(w) from the
+//         maintained r (a pass over the pending rows and r only), retire as 0.
+constexpr int kAuxExact = 0, kAuxFlush = 1, kAuxMonitor = 2;
+
 template <int MODE, int FMT>
 __global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict__ P,
                                                         BState* __restrict__ S,
@@ -443,23 +450,30 @@ __global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict_
     const BItem item = items[it];
     const BProb& pr = P[item.prob];
     BState* st = S + item.prob;
-    if (MODE == 0 ? uni(st->fresh) != 0 : uni(st->m_prev) == 0) break;
+    const int fresh = uni(st->fresh);
+    const int mp = uni(st->m_prev);
+    if (MODE == kAuxExact ? fresh == 2 : MODE == kAuxFlush ? mp == 0 : fresh != 0) break;
     const int64_t k0 = (int64_t)item.slab * pr.chunk;
     const int64_t k1 = std::min(pr.n, k0 + pr.chunk);
-    if (MODE == 0) {
-      double ss = rows_dot<FMT>(pr, k0, k1, nullptr, pr.w, (int)pr.d, pr.y, -1.0);
-      ss = block_sum(ss, red);
-      if (tid == 0) glb(pr.objp)[item.slab] = ss;
-    } else {
-      const int mp = uni(st->m_prev);
+    double ss = 0.0;
+    if (MODE == kAuxExact) {
+      ss = rows_dot<FMT>(pr, k0, k1, nullptr, pr.w, (int)pr.d, pr.y, -1.0);
+    } else if (mp > 0) {
       const int64_t hp = uni64(st->h_prev);
       if (tid < mp / pr.b) smp::sample_block(pr.seed, hp + tid, pr.b, pr.d, iprev + tid * pr.b);
       for (int q = tid; q < mp; q += kBT) dprev[q] = glb(pr.delta)[q];
       __syncthreads();
-      rows_dot<FMT>(pr, k0, k1, iprev, dprev, mp, nullptr, 0.0);
+      ss = rows_dot<FMT>(pr, k0, k1, iprev, dprev, mp, nullptr, 0.0);
+    } else {
+      const gptr<const double> rg = glb(pr.r);
+      for (int64_t k = k0 + tid; k < k1; k += kBT) ss = fma(rg[k], rg[k], ss);
+    }
+    if (MODE != kAuxFlush) {
+      ss = block_sum(ss, red);
+      if (tid == 0) glb(pr.objp)[item.slab] = ss;
     }
     if (!arrive_last(st, pr.nslab, ctl + 1)) break;
-    if (MODE == 0) {
+    if (MODE != kAuxFlush) {
       double ww = 0.0;
       const gptr<const double> wg = glb(pr.w);
       for (int64_t i = tid; i < pr.d; i += kBT) ww = fma(wg[i], wg[i], ww);
@@ -470,7 +484,7 @@ __global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict_
         const double f = rr / (2.0 * (double)pr.n) + 0.5 * pr.lambda * ww;
         st->obj = f;
         if (!isfinite(f) && st->status == DEV_OK) st->status = DEV_NONFINITE;
-        st->fresh = 1;
+        st->fresh = MODE == kAuxExact ? 2 : 1;
         st->m_prev = 0;
         if ((pr.f_target > 0.0 && f <= pr.f_target) || !isfinite(f)) st->active = 0;
         st->arrive = 0;
@@ -616,12 +630,14 @@ struct cabcd_batch_plan {
   size_t step_lds = 0;
   int grid_step = 1, grid_aux = 1;
   int monitor_every = 4;
+  int cheap_monitors = 0;  // maintained-residual monitor points between exact ones
   uint32_t flags = 0;
   int64_t rounds_done = 0;
+  int64_t monitors_done = 0;
   bool pending = false;    // a step ran since the last recompute / flush
   hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};      // [0]: ends in a cheap monitor, [1]: exact
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   int graph_rounds = 0;
   int dtype = CABCD_F64;   // storage type shared by every problem of the plan
 };
@@ -651,14 +667,20 @@ hipError_t launch_step(cabcd_batch_plan* B, hipStream_t st) {
   }
 }
 
+template <int FMT>
+hipError_t launch_aux_f(cabcd_batch_plan* B, int mode, hipStream_t st) {
+  switch (mode) {
+    case kAuxExact: return launch_aux_t<kAuxExact, FMT>(B, st);
+    case kAuxFlush: return launch_aux_t<kAuxFlush, FMT>(B, st);
+    default: return launch_aux_t<kAuxMonitor, FMT>(B, st);
+  }
+}
+
 hipError_t launch_aux(cabcd_batch_plan* B, int mode, hipStream_t st) {
-  switch (B->dtype * 2 + mode) {
-    case CABCD_F64 * 2: return launch_aux_t<0, CABCD_F64>(B, st);
-    case CABCD_F64 * 2 + 1: return launch_aux_t<1, CABCD_F64>(B, st);
-    case CABCD_BF16 * 2: return launch_aux_t<0, CABCD_BF16>(B, st);
-    case CABCD_BF16 * 2 + 1: return launch_aux_t<1, CABCD_BF16>(B, st);
-    case CABCD_FP8_E4M3 * 2: return launch_aux_t<0, CABCD_FP8_E4M3>(B, st);
-    default: return launch_aux_t<1, CABCD_FP8_E4M3>(B, st);
+  switch (B->dtype) {
+    case CABCD_F64: return launch_aux_f<CABCD_F64>(B, mode, st);
+    case CABCD_BF16: return launch_aux_f<CABCD_BF16>(B, mode, st);
+    default: return launch_aux_f<CABCD_FP8_E4M3>(B, mode, st);
   }
 }
 
@@ -749,8 +771,10 @@ void release(cabcd_batch_plan* B) {
   if (B == nullptr) return;
   (void)hipSetDevice(B->device);
   (void)hipDeviceSynchronize();
-  if (B->exec != nullptr) (void)hipGraphExecDestroy(B->exec);
-  if (B->graph != nullptr) (void)hipGraphDestroy(B->graph);
+  for (int g = 0; g < 2; ++g) {
+    if (B->exec[g] != nullptr) (void)hipGraphExecDestroy(B->exec[g]);
+    if (B->graph[g] != nullptr) (void)hipGraphDestroy(B->graph[g]);
+  }
   if (B->cap != nullptr) (void)hipStreamDestroy(B->cap);
   if (B->mem != nullptr) (void)hipFree(B->mem);
   delete B;
@@ -765,6 +789,7 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   B->P = P;
   B->dtype = pb[0].X.dtype;
   B->monitor_every = opts != nullptr ? opts->monitor_every : 4;
+  B->cheap_monitors = opts != nullptr ? opts->cheap_monitors : 0;
   B->flags = opts != nullptr ? opts->flags : 0u;
 
   // Autotune: the rounds-per-pass target with the cheapest predicted pass.
@@ -888,27 +913,31 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   B->grid_aux = std::max(1, std::min(B->nitems, std::max(occ, 1) * cus));
 
   // r_0 = X^T w_0 - y and f(w_0).
-  BATCH_HIP(launch_aux(B, 0, st));
+  BATCH_HIP(launch_aux(B, kAuxExact, st));
   cabcd_status rc = sync_status(B, st, nullptr);
   if (rc != CABCD_OK) return rc;
 
-  // Capture one monitor period (or one round without monitoring).
+  // Capture one monitor period (or one round without monitoring): one graph
+  // ending in a maintained-residual monitor, one ending in an exact one.
   if ((B->flags & CABCD_BATCH_NO_GRAPH) == 0) {
     BATCH_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
-    BATCH_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
     const int R = B->monitor_every > 0 ? B->monitor_every : 1;
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < R && e == hipSuccess; ++i) e = launch_step(B, B->cap);
-    if (e == hipSuccess && B->monitor_every > 0) e = launch_aux(B, 0, B->cap);
-    hipGraph_t g = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
-    B->graph = g;
-    if (e != hipSuccess || e2 != hipSuccess) {
-      set_error("hipGraph capture of the batched round failed: %s",
-                hipGetErrorString(e != hipSuccess ? e : e2));
-      return CABCD_EHIP;
+    for (int g = 0; g < (B->monitor_every > 0 ? 2 : 1); ++g) {
+      BATCH_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < R && e == hipSuccess; ++i) e = launch_step(B, B->cap);
+      if (e == hipSuccess && B->monitor_every > 0)
+        e = launch_aux(B, g == 1 ? kAuxExact : kAuxMonitor, B->cap);
+      hipGraph_t graph = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(B->cap, &graph);
+      B->graph[g] = graph;
+      if (e != hipSuccess || e2 != hipSuccess) {
+        set_error("hipGraph capture of the batched round failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+        return CABCD_EHIP;
+      }
+      BATCH_HIP(hipGraphInstantiate(&B->exec[g], B->graph[g], nullptr, nullptr, 0));
     }
-    BATCH_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     B->graph_rounds = R;
   }
   return CABCD_OK;
@@ -933,8 +962,8 @@ cabcd_status cabcd_batch_create(const cabcd_problem* problems, int32_t P,
     set_error("need P >= 1 problems (P=%d)", P);
     return CABCD_EINVAL;
   }
-  if (opts != nullptr && opts->monitor_every < 0) {
-    set_error("monitor_every must be >= 0");
+  if (opts != nullptr && (opts->monitor_every < 0 || opts->cheap_monitors < 0)) {
+    set_error("monitor_every and cheap_monitors must be >= 0");
     return CABCD_EINVAL;
   }
   for (int p = 0; p < P; ++p) {
@@ -963,13 +992,19 @@ cabcd_status cabcd_batch_run(cabcd_batch B, int64_t rounds, void* stream, int32_
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int M = B->monitor_every;
+  // Every (cheap_monitors + 1)-th monitor point recomputes r exactly.
+  const auto next_exact = [&]() {
+    return (B->monitors_done + 1) % ((int64_t)B->cheap_monitors + 1) == 0;
+  };
   int64_t done = 0;
   while (done < rounds) {
-    if (B->exec != nullptr && rounds - done >= B->graph_rounds &&
+    if (B->exec[0] != nullptr && rounds - done >= B->graph_rounds &&
         (M == 0 || B->rounds_done % M == 0)) {
-      BATCH_HIP(hipGraphLaunch(B->exec, st));
+      const int g = M > 0 && next_exact() ? 1 : 0;
+      BATCH_HIP(hipGraphLaunch(B->exec[g], st));
       done += B->graph_rounds;
       B->rounds_done += B->graph_rounds;
+      if (M > 0) ++B->monitors_done;
       B->pending = M == 0;
       continue;
     }
@@ -978,12 +1013,13 @@ cabcd_status cabcd_batch_run(cabcd_batch B, int64_t rounds, void* stream, int32_
     ++B->rounds_done;
     B->pending = true;
     if (M > 0 && B->rounds_done % M == 0) {
-      BATCH_HIP(launch_aux(B, 0, st));
+      BATCH_HIP(launch_aux(B, next_exact() ? kAuxExact : kAuxMonitor, st));
+      ++B->monitors_done;
       B->pending = false;
     }
   }
   if (B->pending) {
-    BATCH_HIP(launch_aux(B, 1, st));
+    BATCH_HIP(launch_aux(B, kAuxFlush, st));
     B->pending = false;
   }
   if (active != nullptr) return sync_status(B, st, active);

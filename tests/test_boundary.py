@@ -92,7 +92,7 @@ def test_workspace_bytes_grows_with_problem():
 
 def test_batch_struct_layout_matches_header():
     assert ctypes.sizeof(cabcd.Problem) == ctypes.sizeof(cabcd.Matrix) + 8 * 8
-    assert ctypes.sizeof(cabcd.BatchOpts) == 4 + 4
+    assert ctypes.sizeof(cabcd.BatchOpts) == 4 * 4
     assert ctypes.sizeof(cabcd.BatchInfo) == 4 * 4 + 8 * 3 + 8 + 4 + 4
 
 

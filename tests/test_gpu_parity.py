@@ -166,6 +166,19 @@ def test_primal_monitor_and_recompute(gpu_lib):
     assert _rel(r.cpu(), r_exact) <= 1e-12
 
 
+def test_primal_monitor_from_maintained_residual(gpu_lib):
+    _say("primal monitor, maintained residual")
+    X, y, _ = synth.gaussian_ridge(30, 400, 6)
+    lam = 1e-2
+    trace = torch.zeros(10, dtype=torch.float64, device=DEV)
+    gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), lam, 3, 4, 40, 8, monitor_every=1, trace=trace,
+                       flags=gpu_lib.FLAG_MONITOR_MAINTAINED)
+    fs = []
+    bcd.primal_bcd(X.numpy(), y.numpy(), lam, 3, 4, 40, 8,
+                   monitor=lambda h, w_, z_: fs.append(bcd.primal_objective(X.numpy(), y.numpy(), lam, w_)))
+    assert np.allclose(trace.cpu().numpy(), np.array(fs), rtol=1e-12, atol=0)
+
+
 def test_primal_nan_is_reported(gpu_lib):
     _say("primal nan")
     X, y, _ = synth.gaussian_ridge(10, 64, 7)
