@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the extra records")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched time-to-1e-6 runs")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched record")
+    ap.add_argument("--batch-no-baseline", action="store_true",
+                    help="batched record without the one-problem-at-a-time baseline")
+    ap.add_argument("--only-tol", action="store_true", help="run only the mixed time-to-1e-6")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per Gram launch measured by rocprofv3 counters")
     return ap.parse_args()
@@ -107,6 +110,24 @@ def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False)
     return time.perf_counter() - t0, cabcd.timing_dict(tm)
 
 
+def measured_traffic(path, key):
+    """HBM bytes per launch from the committed PMC summary, or None when there is
+    none for this workload or the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        with open(path) as fh:
+            ent = json.load(fh).get(key)
+        if ent is None:
+            return None
+        h = hashlib.sha256()
+        for f in ent["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        return ent["bytes"] if h.hexdigest()[:16] == ent["sources_sha256_16"] else None
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def headline(args, cabcd, torch, synth):
     dev = "cuda:0"
     d, n, b, s, lam = args.d, args.n, args.b, args.s, args.lam
@@ -122,12 +143,7 @@ def headline(args, cabcd, torch, synth):
     gram_ms = g["ms"] / max(g["launches"], 1)
     ybytes = sb * n * 8
     mfma_bound = (sb + 1) / 8.0 > PEAK_FP64_MATRIX_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
-    traffic = None
-    try:
-        with open(args.traffic_json) as fh:
-            traffic = json.load(fh).get(f"gram_f64_d{d}_n{n}_sb{sb}")
-    except (OSError, ValueError):
-        pass
+    traffic = measured_traffic(args.traffic_json, f"gram_f64_d{d}_n{n}_sb{sb}")
     if mfma_bound:
         achieved = gram_flops / (gram_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_MATRIX_TFLOPS,
@@ -268,7 +284,7 @@ def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, la
 
 
 def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, cheap=7,
-                max_rounds=20000):
+                max_rounds=20000, baseline=True):
     """256 independent dense ridge problems (d, n, lambda log-uniform), time to a
     relative objective error of 1e-6 on every problem: the batched persistent
     path (one launch per round, hipGraph) against the one-problem path run
@@ -335,7 +351,7 @@ def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, chea
             pairs[k] = pairs.get(k, 0) + 1
         rec["bs_choices"] = pairs
         log(f"batched {name}: {rec}")
-        if name == "f64":
+        if name == "f64" and baseline:
             # one problem at a time, same (b, s), same stopping rule
             tot, steps_tot, worst = 0.0, 0, 0.0
             for p in range(P):
@@ -393,7 +409,12 @@ def main():
         sys.exit(1)
     cabcd.load()
     if args.only_batch:
-        print(json.dumps({"batched_tol": batched_tol(cabcd, torch, synth)}), flush=True)
+        print(json.dumps({"batched_tol": batched_tol(cabcd, torch, synth,
+                                                     baseline=not args.batch_no_baseline)}),
+              flush=True)
+        return
+    if args.only_tol:
+        print(json.dumps({"time_to_tol": time_to_tol(cabcd, torch, synth)}), flush=True)
         return
     out, X, y = headline(args, cabcd, torch, synth)
     if not args.no_cpu_baseline:
