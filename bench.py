@@ -153,7 +153,8 @@ def headline(args, cabcd, torch, synth):
         achieved = ybytes / (gram_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
-    roof["kernel"] = "gram_f64_kernel<16,2>" if sb > 128 else "gram_f64_kernel"
+    roof["kernel"] = ("gram_f64_dma16_kernel" if sb > 128 and n % 2 == 0 else
+                      "gram_f64_kernel<16,2>" if sb > 128 else "gram_f64_kernel")
     roof["per_launch"] = {"flops": gram_flops, "bytes": ybytes, "ms": round(gram_ms, 4)}
     out = {
         "metric": "CA-BCD Gram TFLOP/s (% peak) + time-to-1e-6 rel obj error, FP64 vs mixed",

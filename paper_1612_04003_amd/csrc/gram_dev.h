@@ -301,6 +301,175 @@ __device__ __forceinline__ void gram_slab(const double* __restrict__ A, int64_t 
 }
 
 
+// ---------------------------------------------------------------------------
+// NB = 16 fed by LDS-DMA loads (gfx950 global_load_lds_dwordx4): the tile goes
+// from global memory straight into LDS, so there are no staging registers and
+// no ds_write instructions.  A DMA instruction writes 64 consecutive 16-byte
+// LDS slots (lane l at base + 16 l); the slots hold unpadded 128-byte rows
+// whose eight 16-byte chunks are XOR-swizzled, chunk c of row r at position
+// c ^ ((r >> 1) & 7), so the sixteen rows of a fragment read fall in distinct
+// banks.  Y u is accumulated from the waves' own-row fragments (each block row
+// is owned by exactly one wave) and summed over the four lane groups at the
+// end.  Needs A 16-byte aligned with an even ld; chunks that cross the end of
+// the slab are written with ordinary LDS stores (zero-filled).
+struct D16 {
+  static constexpr int NB = 16, SBP = 256, NBLK = 136, KT = 16, CH = 8;
+  static constexpr int THREADS = 512;
+  static constexpr int TILE = SBP * KT + KT;         // doubles per buffer: rows, then u
+  static constexpr int DMA_PER_WAVE = SBP * CH / THREADS;   // 4 instructions
+  static constexpr int LDS = 2 * TILE;
+};
+
+__device__ __forceinline__ int d16_swz(int r) { return (r >> 1) & 7; }
+
+// The whole slab for wave W (block rows W and 15 - W); gram_slab_dma16 picks
+// the instantiation once, so each wave's tile loop is one straight-line path
+// for the register allocator.
+template <int W>
+__device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t ld,
+                                         int64_t k_begin, int64_t k_end, const int32_t* idx,
+                                         int m, const double* __restrict__ u,
+                                         double* __restrict__ part, double* lds) {
+  using C = D16;
+  typedef __attribute__((address_space(3))) void* lds_vptr;
+  typedef __attribute__((address_space(1))) const void* glb_vptr;
+  constexpr int R0 = W, R1 = 15 - W;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int ntiles = (int)((k_end - k_begin + C::KT - 1) / C::KT);
+
+  // DMA instruction i of this wave fills slots (4 W + i) * 64 + lane.
+  gptr<const double> src[C::DMA_PER_WAVE];
+  int cofs[C::DMA_PER_WAVE];
+  const gptr<const double> Ag = glb(A);
+#pragma unroll
+  for (int i = 0; i < C::DMA_PER_WAVE; ++i) {
+    const int q = (C::DMA_PER_WAVE * W + i) * 64 + lane;
+    const int r = q >> 3;
+    cofs[i] = 2 * ((q & 7) ^ d16_swz(r));
+    src[i] = Ag + (int64_t)idx[r < m ? r : 0] * ld;   // rows past m: any valid row
+  }
+  const bool want_u = u != nullptr;
+  const gptr<const double> ug = glb(u);
+  const bool u_dma = want_u && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  auto issue = [&](int t, int slot) {
+    const int64_t k0 = k_begin + (int64_t)t * C::KT;
+    double* T = lds + slot * C::TILE;
+#pragma unroll
+    for (int i = 0; i < C::DMA_PER_WAVE; ++i) {
+      double* dst = T + (C::DMA_PER_WAVE * W + i) * 128;   // 64 slots of 2 doubles
+      const int64_t k = k0 + cofs[i];
+      if (k + 1 < k_end) {
+        __builtin_amdgcn_global_load_lds((glb_vptr)(src[i] + k), (lds_vptr)dst, 16, 0, 0);
+      } else {
+        double2 v;
+        v.x = k < k_end ? src[i][k] : 0.0;
+        v.y = 0.0;
+        *reinterpret_cast<double2*>(dst + 2 * lane) = v;
+      }
+    }
+    // the tile's 16 entries of u (zeros without u): lanes 0..7 of wave 7
+    if (W == 7 && lane < C::CH) {
+      double* dst = T + C::SBP * C::KT;
+      const int64_t k = k0 + 2 * lane;
+      if (u_dma && k + 1 < k_end) {
+        __builtin_amdgcn_global_load_lds((glb_vptr)(ug + k), (lds_vptr)dst, 16, 0, 0);
+      } else {
+        double2 v;
+        v.x = want_u && k < k_end ? ug[k] : 0.0;
+        v.y = want_u && k + 1 < k_end ? ug[k + 1] : 0.0;
+        *reinterpret_cast<double2*>(dst + 2 * lane) = v;
+      }
+    }
+  };
+
+  // This lane's fragment offsets (doubles) for the two k-pairs of a tile: row
+  // lane & 15 of every block row, chunk 4 pp + lane / 16, swizzled.
+  const int g = lane >> 4;
+  const int rl = lane & 15;
+  const int lane_off[2] = {rl * C::KT + 2 * ((0 + g) ^ d16_swz(rl)),
+                           rl * C::KT + 2 * ((4 + g) ^ d16_swz(rl))};
+
+  d4 acc[17];
+#pragma unroll
+  for (int a = 0; a < 17; ++a) acc[a] = d4{0.0, 0.0, 0.0, 0.0};
+  double yua[2] = {0.0, 0.0};
+
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);   // the LDS-DMA writes count on the vector memory counter
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) issue(t + 1, (t + 1) & 1);
+    const double* tile = lds + (t & 1) * C::TILE;
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      const double* base = tile + lane_off[pp];
+      auto frag = [&](int r) {   // rows 16 r .. 16 r + 15, this lane's chunk of pair pp
+        return *reinterpret_cast<const double2*>(base + r * 16 * C::KT);
+      };
+      const double2 f0 = frag(R0);
+      const double2 f1 = frag(R1);
+      const double2 ut =   // u at the same two columns (unswizzled, after the rows)
+          *reinterpret_cast<const double2*>(tile + C::SBP * C::KT + 8 * pp + 2 * g);
+      yua[0] = fma(f0.x, ut.x, yua[0]);
+      yua[0] = fma(f0.y, ut.y, yua[0]);
+      yua[1] = fma(f1.x, ut.x, yua[1]);
+      yua[1] = fma(f1.y, ut.y, yua[1]);
+#pragma unroll
+      for (int c = 0; c <= R1; ++c) {
+        const double2 fc = c == R0 ? f0 : (c == R1 ? f1 : frag(c));
+        if (c <= R0) {
+          acc[c] = mfma(f0.x, fc.x, acc[c]);
+          acc[c] = mfma(f0.y, fc.y, acc[c]);
+        }
+        acc[R0 + 1 + c] = mfma(f1.x, fc.x, acc[R0 + 1 + c]);
+        acc[R0 + 1 + c] = mfma(f1.y, fc.y, acc[R0 + 1 + c]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // tile t + 1 is in LDS
+    __syncthreads();
+  }
+
+  gptr<double> pg = glb(part);
+#pragma unroll
+  for (int a = 0; a < 17; ++a) {
+    const int blk = a <= R0 ? blk_index(R0, a) : blk_index(R1, a - R0 - 1);
+    gptr<double> dst = pg + blk * 256 + lane;
+    dst[0] = acc[a][0];
+    dst[64] = acc[a][1];
+    dst[128] = acc[a][2];
+    dst[192] = acc[a][3];
+  }
+  if (want_u) {   // Y u of the two owned block rows: sum the four lane groups
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      double v = yua[i];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (lane < 16) pg[C::NBLK * 256 + 16 * (i == 0 ? R0 : R1) + lane] = v;
+    }
+  }
+}
+
+// The NB = 16 slab of gram_slab<16, 2> on the DMA path; same arguments and
+// partial layout (A must be 16-byte aligned with an even ld).
+__device__ __forceinline__ void gram_slab_dma16(const double* __restrict__ A, int64_t ld,
+                                                int64_t k_begin, int64_t k_end,
+                                                const int32_t* idx, int m,
+                                                const double* __restrict__ u,
+                                                double* __restrict__ part, double* lds) {
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: d16_slab<0>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    case 1: d16_slab<1>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    case 2: d16_slab<2>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    case 3: d16_slab<3>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    case 4: d16_slab<4>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    case 5: d16_slab<5>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    case 6: d16_slab<6>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    default: d16_slab<7>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+  }
+}
+
 // Element e of a partial block (lane-major: e = item*64 + lane) sits at
 // column lane%16 of its 16x16 block and row 4*item + lane/16 (layout 0: the
 // output order of v_mfma_f64_16x16x4_f64 on gfx950) or 4*(lane/16) + item

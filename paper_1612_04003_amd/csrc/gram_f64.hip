@@ -25,6 +25,16 @@ __global__ __launch_bounds__((Cfg<NB, RPW>::THREADS)) void gram_f64_kernel(
                      partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP), aligned, lds);
 }
 
+__global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
+    const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
+    int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) double lds[D16::LDS];
+  const int64_t k_begin = (int64_t)blockIdx.x * chunk;
+  const int64_t k_end = std::min(cols, k_begin + chunk);
+  gram_slab_dma16(A, ld, k_begin, k_end, idx, m, u,
+                  partials + (int64_t)blockIdx.x * (D16::NBLK * 256 + D16::SBP), lds);
+}
+
 constexpr int kRedElems = 64;    // partial entries per reduction workgroup
 constexpr int kRedGroups = 4;    // split groups per entry (one wave each)
 
@@ -70,6 +80,13 @@ hipError_t launch_nb(const GramPlan& p, const double* A, int64_t ld, int64_t col
                      const int32_t* idx, int m, const double* u, double* partials,
                      hipStream_t st) {
   const int aligned = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (ld & 1) == 0) ? 1 : 0;
+  if constexpr (NB == 16) {
+    if (p.rpw == 1 && aligned) {
+      hipLaunchKernelGGL(gram_f64_dma16_kernel, dim3(p.nsplit), dim3(D16::THREADS), 0, st, A, ld,
+                         cols, idx, m, u, p.chunk, partials);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((gram_f64_kernel<NB, RPW>), dim3(p.nsplit), dim3(Cfg<NB, RPW>::THREADS), 0,
                      st, A, ld, cols, idx, m, u, p.chunk, partials, aligned);
   return hipGetLastError();
@@ -127,6 +144,11 @@ GramPlan plan_gram_f64(int m, int64_t cols) {
   // wave per SIMD, accumulators in AGPRs) measured slower at nb = 8 (30.9 vs
   // 38.3 TFLOP/s) and does not fit the registers at nb = 16.
   p.rpw = 2;
+  if (nb == 16) {
+    // rpw = 1: the LDS-DMA variant of the same decomposition (aligned A only).
+    const char* env = std::getenv("CABCD_GRAM_DMA");
+    p.rpw = (env != nullptr && std::atoi(env) == 0) ? 2 : 1;
+  }
   return p;
 }
 
