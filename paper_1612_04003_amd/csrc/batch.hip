@@ -240,6 +240,15 @@ __device__ __forceinline__ T* uni_ptr(T* p) {
 // gets its own register allocation instead of one allocation over every
 // variant of the persistent loop.  They take the workgroup's dynamic LDS from
 // their own extern declaration, so their LDS accesses stay ds_* instructions.
+// Rows fed to LDS by DMA, one owned row per lane (16-byte aligned A, even ld).
+__device__ __noinline__ void gram_call_dma16(const double* A, int64_t ld, int64_t k0,
+                                             int64_t k1, const int32_t* idx, int m,
+                                             const double* u, double* part) {
+  extern __shared__ __attribute__((aligned(16))) double dyn_sm[];
+  gdev::gram_slab_dma16(uni_ptr(A), uni64(ld), uni64(k0), uni64(k1), uni_ptr(idx), uni(m),
+                        uni_ptr(u), uni_ptr(part), dyn_sm);
+}
+
 template <int NB>
 __device__ __noinline__ void gram_call(const double* A, int64_t ld, int64_t k0, int64_t k1,
                                        const int32_t* idx, int m, const double* u, double* part,
@@ -272,7 +281,10 @@ __device__ __forceinline__ void gram_any(int nb, const void* A, int64_t ld, int6
       case 2: gram_call<2>(a, ld, k0, k1, idx, m, u, part, aligned); break;
       case 4: gram_call<4>(a, ld, k0, k1, idx, m, u, part, aligned); break;
       case 8: gram_call<8>(a, ld, k0, k1, idx, m, u, part, aligned); break;
-      default: gram_call<16>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      default:
+        if (uni(aligned)) gram_call_dma16(a, ld, k0, k1, idx, m, u, part);
+        else gram_call<16>(a, ld, k0, k1, idx, m, u, part, aligned);
+        break;
     }
   } else {
     const uint8_t* a = static_cast<const uint8_t*>(A);
@@ -303,7 +315,7 @@ __device__ __noinline__ void solve_call(const SolveArgs& in) {
   a.mode = uni(in.mode);
   a.lambda = __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, in.lambda)));
   a.n = __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, in.n)));
-  sdev::solve_block<BP, PF, kBT>(a, dyn_sm);
+  sdev::solve_block<BP, PF, kBT, 1>(a, dyn_sm);   // s BP <= 2 s b <= 512 lanes
 }
 
 __device__ __forceinline__ void solve_any(int bp, const SolveArgs& a) {
@@ -836,6 +848,7 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   if (B->dtype == CABCD_F64) {
     area = std::max<int>(area, gdev::Cfg<16, 2>::LDS);
     area = std::max<int>(area, gdev::Cfg<1, 2>::LDS);
+    area = std::max<int>(area, gdev::D16::LDS);
   } else {
     const int lp = B->dtype == CABCD_BF16
                        ? std::max(ldev::LpCfg<16, CABCD_BF16>::LDS, ldev::LpCfg<1, CABCD_BF16>::LDS)

@@ -7,32 +7,43 @@ namespace {
 
 using namespace sdev;
 
-template <int BP, int PF, int THREADS>
+template <int BP, int PF, int THREADS, int MAP>
 __global__ __launch_bounds__(THREADS) void solve_kernel(SolveArgs a) {
   extern __shared__ __attribute__((aligned(16))) double sm[];
-  solve_block<BP, PF, THREADS>(a, sm);
+  solve_block<BP, PF, THREADS, MAP>(a, sm);
 }
 
-template <int BP, int PF, int THREADS>
+template <int BP, int PF, int THREADS, int MAP>
 hipError_t launch_b(const SolveArgs& a, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(solve_kernel<BP, PF, THREADS>),
+        reinterpret_cast<const void*>(solve_kernel<BP, PF, THREADS, MAP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSolveMaxLds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((solve_kernel<BP, PF, THREADS>), dim3(1), dim3(THREADS),
+  hipLaunchKernelGGL((solve_kernel<BP, PF, THREADS, MAP>), dim3(1), dim3(THREADS),
                      solve_lds_bytes(a.m, a.b), st, a);
   return hipGetLastError();
 }
 
+// The one-barrier block mapping (MAP 1) whenever s BP lanes fit the workgroup.
 template <int BP, int PF>
 hipError_t launch_t(const SolveArgs& a, hipStream_t st) {
-  if (a.m <= 512) return launch_b<BP, PF, 512>(a, st);
-  if constexpr (BP <= 8) return launch_b<BP, 2, 1024>(a, st);
-  if constexpr (BP == 16) return launch_b<BP, 1, 1024>(a, st);
+  const int lanes = a.s * BP;
+  if constexpr (BP <= 16) {
+    if (lanes <= 512) return launch_b<BP, PF, 512, 1>(a, st);
+  }
+  if (a.m <= 512) return launch_b<BP, PF, 512, 0>(a, st);
+  if constexpr (BP <= 8) {
+    if (lanes <= 1024) return launch_b<BP, 2, 1024, 1>(a, st);
+    return launch_b<BP, 2, 1024, 0>(a, st);
+  }
+  if constexpr (BP == 16) {
+    if (lanes <= 1024) return launch_b<BP, 1, 1024, 1>(a, st);
+    return launch_b<BP, 1, 1024, 0>(a, st);
+  }
   return hipErrorInvalidValue;   // b in (16, 32] never reaches m > 512 within the LDS bound
 }
 

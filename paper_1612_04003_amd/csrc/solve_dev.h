@@ -103,9 +103,15 @@ __device__ __forceinline__ unsigned hash_idx(int i, int slots) {
   return ((unsigned)i * 2654435761u) & (unsigned)(slots - 1);
 }
 
-// One outer step's fused solve by one workgroup of THREADS threads (THREADS >=
-// m); sm holds solve_lds_bytes(m, b) bytes of LDS.
-template <int BP, int PF, int THREADS>
+// One outer step's fused solve by one workgroup of THREADS threads; sm holds
+// solve_lds_bytes(m, b) bytes of LDS.
+//   MAP 0: thread p owns row p (THREADS >= m); per block two barriers: the
+//          block's rhs goes through LDS to b threads that apply Gamma_j^-1.
+//   MAP 1: thread j BP + u owns row j b + u (THREADS >= s BP), so a block's
+//          rows are BP consecutive lanes of one wave: they apply Gamma_j^-1
+//          (rows kept in registers) to their rhs with in-wave shuffles, and
+//          one barrier per block publishes delta_j.
+template <int BP, int PF, int THREADS, int MAP = 0>
 __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   using C = SolveCfg<BP>;
   const int m = a.m, b = a.b, s = a.s;
@@ -119,12 +125,14 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   double* Dl = R + BP;
   int* Ix = reinterpret_cast<int*>(Dl + (size_t)s * BP);
 
-  const int p = threadIdx.x;
-  const int lane = p & 63;
-  const int wave = p >> 6;
-  const bool active = p < m;
-  const int j_of = active ? p / b : -1;   // block of this row (-1: no row)
-  const int u = active ? p - j_of * b : 0;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const bool active = MAP == 0 ? tid < m : (tid / BP < s && tid % BP < b);
+  // block of this row (-1: no row; MAP 1 keeps padding lanes on their block)
+  const int j_of = MAP == 0 ? (active ? tid / b : -1) : (tid / BP < s ? tid / BP : -1);
+  const int u = MAP == 0 ? (active ? tid - j_of * b : 0) : tid % BP;
+  const int p = MAP == 0 ? tid : (active ? j_of * b + u : m);   // row of the outer step
 
   // ---- phase 1
   double rhs = 0.0;
@@ -136,8 +144,8 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
     const double xi = glb(a.x)[ip];
     rhs = a.mode == 0 ? (-a.lambda * xi - yu / a.n) : ((yu - xi - glb(a.y)[ip]) / a.n);
   }
-  for (int q = p; q < s * BP; q += THREADS) Dl[q] = 0.0;
-  if (p < BP) R[p] = 0.0;
+  for (int q = tid; q < s * BP; q += THREADS) Dl[q] = 0.0;
+  if (tid < BP) R[tid] = 0.0;
 
   // Prefetch ring of Gov row segments Gov[p][jb*b + v].  Gov is symmetric, so
   // they are read as Gov[jb*b + v][p]: consecutive threads then read
@@ -180,6 +188,33 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   // ---- phase 3: the dependent chain over the s blocks.  Every thread runs all
   // rounds (the work of steps j >= s is switched off, the barriers and loads
   // are not), so the control flow is uniform.
+  if constexpr (MAP == 1) {
+    double gi[BP];   // row u of Gamma_{j_of}^-1 (identity rows for padding)
+#pragma unroll
+    for (int v = 0; v < BP; ++v) gi[v] = j_of >= 0 ? Gi[((size_t)j_of * BP + u) * BP + v] : 0.0;
+    const int l0 = lane - u;   // first lane of this thread's block
+    for (int j0 = 0; j0 < s; j0 += PF) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int j = j0 + q;
+        if (j_of == j) {
+          double d = 0.0;
+#pragma unroll
+          for (int v = 0; v < BP; ++v) d += gi[v] * __shfl(rhs, l0 + v, 64);
+          Dl[j * BP + u] = u < b ? d : 0.0;
+        }
+        lds_barrier();
+        if (active && j_of > j) {
+          const double* dj = Dl + j * BP;
+          double acc = 0.0;
+#pragma unroll
+          for (int v = 0; v < BP; ++v) acc += ring[q][v] * dj[v];
+          rhs -= acc;
+        }
+        ring_load(q, j + PF);
+      }
+    }
+  } else
   for (int j0 = 0; j0 < s; j0 += PF) {
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
@@ -209,7 +244,7 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   int* hkey = reinterpret_cast<int*>(Gi);
   int* hmin = hkey + slots;
   int* hcnt = hmin + slots;
-  for (int q = p; q < slots; q += THREADS) {
+  for (int q = tid; q < slots; q += THREADS) {
     hkey[q] = -1;
     hmin[q] = INT_MAX;
     hcnt[q] = 0;

@@ -40,40 +40,50 @@ struct GemvT {
   int aligned;
 };
 
+// VEC: 16-byte loads of column pairs (A 16-byte aligned, even ld).  Eight rows
+// are loaded before their products are added, so each thread keeps eight
+// loads in flight.
+template <bool VEC>
 __global__ __launch_bounds__(kVecThreads) void gemv_t_kernel(GemvT g) {
+  constexpr int U = 8;
   const int64_t k = ((int64_t)blockIdx.x * kVecThreads + threadIdx.x) * 2;
   const int64_t p0 = (int64_t)blockIdx.y * g.rows_per_group;
   const int64_t p1 = std::min(g.m, p0 + g.rows_per_group);
   if (k >= g.cols) return;
   const bool two = k + 1 < g.cols;
-  const bool vec = two && g.aligned;
+  const bool vec = VEC && two;
+  const gptr<const double> A = glb(g.A);
+  const gptr<const double> v = glb(g.v);
   double s0 = 0.0, s1 = 0.0;
   int64_t p = p0;
-  for (; p + 4 <= p1; p += 4) {
-    double2 x[4];
-    double c[4];
+  for (; p + U <= p1; p += U) {
+    double2 x[U];
+    double c[U];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < U; ++q) {
       const int64_t row = g.idx ? (int64_t)g.idx[p + q] : p + q;
-      const double* a = g.A + row * g.ld + k;
-      c[q] = g.v[p + q];
+      const gptr<const double> a = A + row * g.ld + k;
+      c[q] = v[p + q];
       if (vec) {
-        x[q] = *reinterpret_cast<const double2*>(a);
+        typedef double dv2 __attribute__((ext_vector_type(2)));
+        const dv2 t = *reinterpret_cast<gptr<const dv2>>(a);
+        x[q].x = t.x;
+        x[q].y = t.y;
       } else {
         x[q].x = a[0];
         x[q].y = two ? a[1] : 0.0;
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < U; ++q) {
       s0 = fma(x[q].x, c[q], s0);
       s1 = fma(x[q].y, c[q], s1);
     }
   }
   for (; p < p1; ++p) {
     const int64_t row = g.idx ? (int64_t)g.idx[p] : p;
-    const double* a = g.A + row * g.ld + k;
-    const double c = g.v[p];
+    const gptr<const double> a = A + row * g.ld + k;
+    const double c = v[p];
     s0 = fma(a[0], c, s0);
     if (two) s1 = fma(a[1], c, s1);
   }
@@ -102,8 +112,11 @@ __global__ __launch_bounds__(kVecThreads) void gemv_t_combine_kernel(GemvT g, in
 }
 
 int gemv_t_groups(int64_t m, int64_t cols) {
+  // Split the rows (partials + a combine pass) only when there are too few
+  // column tiles to give every CU work; a split pass measured slower than one
+  // pass at 256+ tiles.
   const int64_t tiles = (cols + kColsPerWG - 1) / kColsPerWG;
-  int64_t rg = (1024 + tiles - 1) / tiles;
+  int64_t rg = (256 + tiles - 1) / tiles;
   rg = std::min<int64_t>(rg, std::max<int64_t>(1, m / 16));
   rg = std::min<int64_t>(rg, 4096);
   return (int)std::max<int64_t>(rg, 1);
@@ -207,8 +220,12 @@ hipError_t launch_gemv_t(const double* A, int64_t ld, int64_t cols, const int32_
   g.scratch = rg > 1 ? scratch : nullptr;
   if (rg > 1 && scratch == nullptr) return hipErrorInvalidValue;
   const int64_t tiles = (cols + kColsPerWG - 1) / kColsPerWG;
-  hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)tiles, (unsigned)rg), dim3(kVecThreads), 0,
-                     st, g);
+  if (g.aligned)
+    hipLaunchKernelGGL(gemv_t_kernel<true>, dim3((unsigned)tiles, (unsigned)rg),
+                       dim3(kVecThreads), 0, st, g);
+  else
+    hipLaunchKernelGGL(gemv_t_kernel<false>, dim3((unsigned)tiles, (unsigned)rg),
+                       dim3(kVecThreads), 0, st, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || rg == 1) return e;
   hipLaunchKernelGGL(gemv_t_combine_kernel,
