@@ -123,14 +123,8 @@ def gram(A, idx, scale, shift, u=None):
 # primal: Alg. 1 (s = 1) and Alg. 2 (CA-BCD)
 # ----------------------------------------------------------------------------
 
-def primal_bcd(X, y, lam, b, s, H, seed, w0=None, explicit_idx=None, h0=0,
-               monitor=None):
-    """CA-BCD (Alg. 2); with s = 1 it is BCD (Alg. 1).
-
-    Returns (w_H, z_H) with z_H = X^T w_H maintained by the recurrence.
-    `explicit_idx`, if given, is indexable by global iteration and replaces the
-    sampler.  `monitor(h, w, z)` is called after every outer step.
-    """
+def _primal_steps(X, y, lam, b, s, H, seed, w0, explicit_idx, h0):
+    """The outer steps of Alg. 2; yields (h, w, z) after each one."""
     d, n = X.shape
     if not (lam > 0 and 1 <= b <= d and s >= 1 and H >= 0):
         raise ValueError("invalid arguments")
@@ -164,21 +158,63 @@ def primal_bcd(X, y, lam, b, s, H, seed, w0=None, explicit_idx=None, h0=0,
         w = w + v
         z = z + X.T @ v
         h += sk
-        if monitor is not None:
+        yield h, w, z
+    if H == 0:
+        yield 0, w, z
+
+
+def primal_bcd(X, y, lam, b, s, H, seed, w0=None, explicit_idx=None, h0=0,
+               monitor=None):
+    """CA-BCD (Alg. 2); with s = 1 it is BCD (Alg. 1).
+
+    Returns (w_H, z_H) with z_H = X^T w_H maintained by the recurrence.
+    `explicit_idx`, if given, is indexable by global iteration and replaces the
+    sampler.  `monitor(h, w, z)` is called after every outer step.
+    """
+    for h, w, z in _primal_steps(X, y, lam, b, s, H, seed, w0, explicit_idx, h0):
+        if monitor is not None and h > 0:
             monitor(h, w, z)
     return w, z
+
+
+def primal_residual(X, y, lam, w, z):
+    """The full primal residual of Section 5.1.5 (stopping criterion),
+    -lam w - 1/n X z + 1/n X y, with z = X^T w as maintained by the iteration
+    (the b-row subsample of this vector is the right-hand side of every block
+    solve).  With the exact z it is -grad f(w)."""
+    n = X.shape[1]
+    return -lam * np.asarray(w, dtype=np.float64) - np.asarray(X @ (z - y)).ravel() / n
+
+
+def primal_bcd_tol(X, y, lam, b, s, H, seed, tol, check_every=1, w0=None,
+                   explicit_idx=None, h0=0):
+    """Alg. 2 stopped by the residual test of Section 5.1.5: after every
+    `check_every`-th outer step the full primal residual (with the maintained
+    z) is formed, and the run stops at the first check where its 2-norm is
+    <= tol, else after H inner iterations.
+
+    Returns (w, z, h, norm): the iterate, its maintained z, the inner
+    iterations performed and the norm at the last check (nan if none)."""
+    if not (check_every >= 1 and tol >= 0):
+        raise ValueError("invalid arguments")
+    k, norm = 0, float("nan")
+    for h, w, z in _primal_steps(X, y, lam, b, s, H, seed, w0, explicit_idx, h0):
+        if h == 0:
+            break
+        k += 1
+        if k % check_every == 0:
+            norm = float(np.linalg.norm(primal_residual(X, y, lam, w, z)))
+            if norm <= tol:
+                break
+    return w, z, h, norm
 
 
 # ----------------------------------------------------------------------------
 # dual: Alg. 3 (s = 1) and Alg. 4 (CA-BDCD)
 # ----------------------------------------------------------------------------
 
-def dual_bcd(X, y, lam, b, s, H, seed, alpha0=None, explicit_idx=None, h0=0,
-             monitor=None):
-    """CA-BDCD (Alg. 4); with s = 1 it is BDCD (Alg. 3).
-
-    Returns (alpha_H, w_H), w_H maintained by the recurrence.
-    """
+def _dual_steps(X, y, lam, b, s, H, seed, alpha0, explicit_idx, h0):
+    """The outer steps of Alg. 4; yields (h, alpha, w) after each one."""
     d, n = X.shape
     if not (lam > 0 and 1 <= b <= n and s >= 1 and H >= 0):
         raise ValueError("invalid arguments")
@@ -214,6 +250,46 @@ def dual_bcd(X, y, lam, b, s, H, seed, alpha0=None, explicit_idx=None, h0=0,
         alpha = alpha + v
         w = w - np.asarray(X @ v).ravel() / (lam * n)
         h += sk
-        if monitor is not None:
+        yield h, alpha, w
+    if H == 0:
+        yield 0, alpha, w
+
+
+def dual_bcd(X, y, lam, b, s, H, seed, alpha0=None, explicit_idx=None, h0=0,
+             monitor=None):
+    """CA-BDCD (Alg. 4); with s = 1 it is BDCD (Alg. 3).
+
+    Returns (alpha_H, w_H), w_H maintained by the recurrence.
+    """
+    for h, alpha, w in _dual_steps(X, y, lam, b, s, H, seed, alpha0, explicit_idx, h0):
+        if monitor is not None and h > 0:
             monitor(h, alpha, w)
     return alpha, w
+
+
+def dual_residual(X, y, alpha, w):
+    """The full dual residual of Section 5.1.5, -X^T w + alpha + y, with w as
+    maintained by the iteration (its b-entry subsample is the vector each
+    block solve of Alg. 3/4 is applied to).  With w = -X alpha/(lam n) it is
+    n grad D(alpha)."""
+    return (-np.asarray(X.T @ w).ravel() + np.asarray(alpha, dtype=np.float64)
+            + np.asarray(y, dtype=np.float64))
+
+
+def dual_bcd_tol(X, y, lam, b, s, H, seed, tol, check_every=1, alpha0=None,
+                 explicit_idx=None, h0=0):
+    """Alg. 4 stopped by the dual residual test of Section 5.1.5 (2-norm of
+    the full dual residual <= tol at every `check_every`-th outer step).
+    Returns (alpha, w, h, norm) as primal_bcd_tol."""
+    if not (check_every >= 1 and tol >= 0):
+        raise ValueError("invalid arguments")
+    k, norm = 0, float("nan")
+    for h, alpha, w in _dual_steps(X, y, lam, b, s, H, seed, alpha0, explicit_idx, h0):
+        if h == 0:
+            break
+        k += 1
+        if k % check_every == 0:
+            norm = float(np.linalg.norm(dual_residual(X, y, alpha, w)))
+            if norm <= tol:
+                break
+    return alpha, w, h, norm
