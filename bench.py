@@ -224,6 +224,66 @@ def extra_records(args, cabcd, torch, synth, X, y):
             "gram_gflops": round(np.mean(fl) / (g * 1e-3) / 1e9, 2),
             "gram_gbs": round(np.mean(by) / (g * 1e-3) / 1e9, 2)}
         log(f"sparse dual s={s}: {rec[f'sparse_dual_s{s}']}")
+    rec.update(resid_tol_records(cabcd, torch, X, y, lam, args.b, args.s, A, yd))
+    return rec
+
+
+def resid_tol_records(cabcd, torch, X, y, lam, b, s, A, yd, every=8):
+    """Runs stopped by the residual test of Section 5.1.5 (tolerances of the
+    paper's performance runs: 1e-1 primal, 1e-2 dual, relative to the
+    residual at the start): wall time, inner iterations, and the cost of one
+    check (a full pass over A) from a second, event-timed run."""
+    rec = {}
+    dev = X.device
+    d, n = X.shape
+
+    def run(fn, mat, yy, coord_len, comp_len, tol, H, seed, timing=None):
+        st = {}
+        coord = torch.zeros(coord_len, dtype=torch.float64, device=dev)
+        comp = torch.empty(comp_len, dtype=torch.float64, device=dev)
+        kw = dict(timing=timing) if timing is not None else {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if fn == "primal":
+            cabcd.primal_bcd(mat, yy, lam_of[fn], b_of[fn], s_of[fn], H, seed, w=coord, r=comp,
+                             tol=tol, check_every=every, stats=st, **kw)
+        else:
+            cabcd.dual_bcd(mat, yy, lam_of[fn], b_of[fn], s_of[fn], H, seed, alpha=coord, w=comp,
+                           tol=tol, check_every=every, stats=st, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
+    lam_of = {"primal": lam, "dual": 1e-5}
+    b_of = {"primal": b, "dual": 16}
+    s_of = {"primal": s, "dual": 8}
+    zero = torch.zeros(d, dtype=torch.float64, device=dev)
+    nrm0, _ = cabcd.primal_residual(X, lam, zero, -y)      # w = 0: r = -y
+    tol = 0.1 * nrm0.item()
+    H = 200000
+    run("primal", X, y, d, n, tol, H, 2003)                  # warm-up
+    el, st = run("primal", X, y, d, n, tol, H, 2003)
+    tm = cabcd.new_timing()
+    run("primal", X, y, d, n, tol, H, 2003, timing=tm)
+    ph = cabcd.timing_dict(tm)["check"]
+    rec["primal_resid_tol"] = {
+        "tol_rel": 0.1, "check_every": every, "s": s, "b": b, "reached": st["h"] < H,
+        "h": st["h"], "s_total": round(el, 4), "resid_rel": st["resid_norm"] / nrm0.item(),
+        "check_ms": round(ph["ms"] / max(ph["launches"], 1), 4)}
+    log(f"primal residual stop: {rec['primal_resid_tol']}")
+    nA = A.shape[0]
+    ynorm = float(torch.linalg.norm(yd))
+    tol = 1e-2 * ynorm
+    H = 80000
+    run("dual", A, yd, nA, A.shape[1], tol, H, 2004)
+    el, st = run("dual", A, yd, nA, A.shape[1], tol, H, 2004)
+    tm = cabcd.new_timing()
+    run("dual", A, yd, nA, A.shape[1], tol, H, 2004, timing=tm)
+    ph = cabcd.timing_dict(tm)["check"]
+    rec["sparse_dual_resid_tol"] = {
+        "tol_rel": 1e-2, "check_every": every, "s": 8, "b": 16, "reached": st["h"] < H,
+        "h": st["h"], "s_total": round(el, 4), "resid_rel": st["resid_norm"] / ynorm,
+        "check_ms": round(ph["ms"] / max(ph["launches"], 1), 4)}
+    log(f"sparse dual residual stop: {rec['sparse_dual_resid_tol']}")
     return rec
 
 

@@ -117,6 +117,19 @@ typedef struct cabcd_opts {
                                 `stream`; timing[p] accumulates its milliseconds and
                                 timing[CABCD_NPHASES+p] its launch count.  Needs a
                                 synchronising call (no CABCD_FLAG_ASYNC).           */
+  /* Residual stopping test (Section 5.1.5).  Every check_every-th outer step
+     the full residual is formed from the maintained vectors (primal:
+     -lambda w - 1/n X r, i.e. -grad f(w) up to the drift of r; dual:
+     -X^T w + alpha + y) and the run stops after that step when its 2-norm is
+     <= tol.  tol = 0 with check_every > 0 only reports the norm.  Needs a
+     synchronising call (the norm is read on the host at every check).       */
+  double tol;                /* >= 0, absolute bound on the residual 2-norm        */
+  int32_t check_every;       /* outer steps between checks (0 = no checks)         */
+  int32_t reserved1;
+  int64_t* iters_done;       /* optional HOST out: inner iterations performed (H
+                                unless the test stopped the run)                   */
+  double* resid_norm;        /* optional HOST out: norm at the last check (NaN if
+                                there was none)                                    */
 } cabcd_opts;
 
 /* Phases reported through cabcd_opts.timing (the breakdown of one outer step). */
@@ -127,9 +140,11 @@ typedef struct cabcd_opts {
 #define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta                 */
 #define CABCD_PHASE_RECOMPUTE 5 /* exact companion recomputation                   */
 #define CABCD_PHASE_MONITOR 6   /* objective evaluation                            */
-#define CABCD_NPHASES 7
+#define CABCD_PHASE_CHECK 7     /* full residual of the stopping test              */
+#define CABCD_NPHASES 8
 
-/* Fill *o with defaults: h0 0, no flags, no recompute, no monitor, sampler on. */
+/* Fill *o with defaults: h0 0, no flags, no recompute, no monitor, sampler on,
+   no residual checks. */
 void cabcd_opts_init(cabcd_opts* o);
 
 /*
@@ -229,6 +244,28 @@ cabcd_status cabcd_primal_objective(const cabcd_matrix* X, const double* y,
 cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y,
                                       double lambda, const double* w, double* r,
                                       double* f, void* stream);
+
+/*
+ * Full primal residual of the stopping test (Section 5.1.5) with A = X (d x n,
+ * dense F64 / BF16 / FP8 or CSR):
+ *   rho = -lambda w - (1/n) X r   (d),   *norm = ||rho||_2 (device scalar)
+ * for the given r = z - y (the maintained one, or X^T w - y from
+ * cabcd_primal_objective, which makes rho = -grad f(w)).  Either output may be
+ * NULL, not both.  Synchronises the stream.
+ */
+cabcd_status cabcd_primal_residual(const cabcd_matrix* X, double lambda, const double* w,
+                                   const double* r, double* rho, double* norm, void* stream);
+
+/*
+ * Full dual residual of the stopping test (Section 5.1.5) with A = X^T (n x d,
+ * dense F64 or CSR):
+ *   rho = -X^T w + alpha + y   (n),   *norm = ||rho||_2 (device scalar)
+ * for the given w (the maintained one, or -X alpha/(lambda n), which makes
+ * rho = n grad D(alpha)).  Either output may be NULL, not both.
+ * Synchronises the stream.
+ */
+cabcd_status cabcd_dual_residual(const cabcd_matrix* XT, const double* y, const double* alpha,
+                                 const double* w, double* rho, double* norm, void* stream);
 
 /*
  * Primal-dual map (eq. 3) with A = X^T (n x d): w = -X a / (lambda n) (d).

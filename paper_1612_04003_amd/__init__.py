@@ -46,7 +46,11 @@ class Opts(ctypes.Structure):
                 ("explicit_idx", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("trace_len", ctypes.c_int64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("timing", ctypes.POINTER(ctypes.c_double))]
+                ("timing", ctypes.POINTER(ctypes.c_double)),
+                ("tol", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32),
+                ("iters_done", ctypes.POINTER(ctypes.c_int64)),
+                ("resid_norm", ctypes.POINTER(ctypes.c_double))]
 
 
 class Problem(ctypes.Structure):
@@ -70,8 +74,8 @@ class BatchInfo(ctypes.Structure):
 
 BATCH_NO_GRAPH = 1
 
-NPHASES = 7
-PHASES = ["sample", "gram", "reduce", "solve", "update", "recompute", "monitor"]
+NPHASES = 8
+PHASES = ["sample", "gram", "reduce", "solve", "update", "recompute", "monitor", "check"]
 
 
 _lib = None
@@ -98,6 +102,8 @@ def load():
         "cabcd_primal_objective": (I32, [MP, P, D, P, P, P, P]),
         "cabcd_primal_objective_t": (I32, [MP, P, D, P, P, P, P]),
         "cabcd_dual_to_primal": (I32, [MP, P, D, P, P]),
+        "cabcd_primal_residual": (I32, [MP, D, P, P, P, P, P]),
+        "cabcd_dual_residual": (I32, [MP, P, P, P, P, P, P]),
         "cabcd_workspace_bytes": (ctypes.c_size_t, [MP, I32, I32]),
         "cabcd_quantize": (I32, [P, I64, I64, I64, I32, P, I64, P, P]),
         "cabcd_batch_create": (I32, [ctypes.POINTER(Problem), I32, ctypes.POINTER(BatchOpts), P,
@@ -122,7 +128,8 @@ def exported_symbols():
     """Names of the C entry points this binding expects the library to export."""
     return ["cabcd_opts_init", "cabcd_sample", "cabcd_gram", "cabcd_primal_bcd",
             "cabcd_dual_bcd", "cabcd_primal_objective", "cabcd_primal_objective_t",
-            "cabcd_dual_to_primal", "cabcd_workspace_bytes", "cabcd_last_error",
+            "cabcd_dual_to_primal", "cabcd_primal_residual", "cabcd_dual_residual",
+            "cabcd_workspace_bytes", "cabcd_last_error",
             "cabcd_version", "cabcd_quantize", "cabcd_batch_create", "cabcd_batch_run",
             "cabcd_batch_query", "cabcd_batch_destroy", "cabcd_primal_bcd_batched"]
 
@@ -261,11 +268,18 @@ def describe(A):
 
 
 def _opts(h0=0, flags=0, resid_every=0, monitor_every=0, explicit_idx=None, trace=None,
-          workspace=None, timing=None):
+          workspace=None, timing=None, tol=0.0, check_every=0, stats=None):
+    """cabcd_opts from keywords.  `stats`, a dict, receives "h" (inner
+    iterations performed) and "resid_norm" (norm at the last residual check)
+    after the call."""
     o = Opts()
     load().cabcd_opts_init(ctypes.byref(o))
     o.h0, o.flags = h0, flags
     o.resid_every, o.monitor_every = resid_every, monitor_every
+    o.tol, o.check_every = float(tol), int(check_every)
+    o._h, o._norm, o._stats = ctypes.c_int64(0), ctypes.c_double(0.0), stats
+    o.iters_done = ctypes.pointer(o._h)
+    o.resid_norm = ctypes.pointer(o._norm)
     if explicit_idx is not None:
         _need(explicit_idx, torch.int32, "explicit_idx")
         o.explicit_idx = explicit_idx.data_ptr()
@@ -278,6 +292,12 @@ def _opts(h0=0, flags=0, resid_every=0, monitor_every=0, explicit_idx=None, trac
     if timing is not None:
         o.timing = ctypes.cast(timing, ctypes.POINTER(ctypes.c_double))
     return o
+
+
+def _report(o):
+    if o._stats is not None:
+        o._stats["h"] = int(o._h.value)
+        o._stats["resid_norm"] = float(o._norm.value)
 
 
 def _check_explicit(opt, H, b):
@@ -325,6 +345,7 @@ def primal_bcd(X, y, lam, b, s, H, seed, w=None, r=None, **opt):
     o = _opts(**opt)
     _check(load().cabcd_primal_bcd(ctypes.byref(M), _ptr(y), lam, b, s, H, seed, _ptr(w),
                                    _ptr(r), ctypes.byref(o), _stream()))
+    _report(o)
     return w, r
 
 
@@ -343,6 +364,7 @@ def dual_bcd(XT, y, lam, b, s, H, seed, alpha=None, w=None, **opt):
     o = _opts(**opt)
     _check(load().cabcd_dual_bcd(ctypes.byref(M), _ptr(y), lam, b, s, H, seed, _ptr(alpha),
                                  _ptr(w), ctypes.byref(o), _stream()))
+    _report(o)
     return alpha, w
 
 
@@ -366,6 +388,32 @@ def primal_objective_t(XT, y, lam, w, r=None):
     _check(load().cabcd_primal_objective_t(ctypes.byref(M), _ptr(y), lam, _ptr(w), _ptr(r),
                                            _ptr(f), _stream()))
     return f, r
+
+
+def primal_residual(X, lam, w, r, rho=None):
+    """(||rho||_2 as a 1-element tensor, rho) with rho = -lam w - 1/n X r, the
+    full primal residual of the stopping test, from A = X."""
+    M = describe(X)
+    norm = torch.empty(1, dtype=torch.float64, device=X.device)
+    if rho is None:
+        rho = torch.empty(X.shape[0], dtype=torch.float64, device=X.device)
+    _need(rho, torch.float64, "rho", X.shape[0])
+    _check(load().cabcd_primal_residual(ctypes.byref(M), lam, _ptr(w), _ptr(r), _ptr(rho),
+                                        _ptr(norm), _stream()))
+    return norm, rho
+
+
+def dual_residual(XT, y, alpha, w, rho=None):
+    """(||rho||_2 as a 1-element tensor, rho) with rho = -X^T w + alpha + y, the
+    full dual residual of the stopping test, from A = X^T."""
+    M = describe(XT)
+    norm = torch.empty(1, dtype=torch.float64, device=XT.device)
+    if rho is None:
+        rho = torch.empty(XT.shape[0], dtype=torch.float64, device=XT.device)
+    _need(rho, torch.float64, "rho", XT.shape[0])
+    _check(load().cabcd_dual_residual(ctypes.byref(M), _ptr(y), _ptr(alpha), _ptr(w), _ptr(rho),
+                                      _ptr(norm), _stream()))
+    return norm, rho
 
 
 def dual_to_primal(XT, alpha, lam, w=None):

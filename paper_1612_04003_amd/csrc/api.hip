@@ -216,9 +216,40 @@ hipError_t mat_scatter(const Mat& M, const int32_t* idx, int64_t m, const double
 
 // out[p] = A[p] . v + beta base[p]
 hipError_t mat_rowdot(const Mat& M, const double* v, const double* base, double beta,
-                      double* out, hipStream_t st) {
-  if (!M.csr) return launch_gemv_n(M.X, M.ld, M.rows, M.cols, v, base, beta, out, st);
+                      double* out, double* scratch, hipStream_t st) {
+  if (!M.csr)
+    return launch_rowdot(M.dtype, M.lowp() ? M.Q : static_cast<const void*>(M.X), M.ld, M.rows,
+                         M.cols, M.rs, v, base, beta, out, scratch, st);
   return launch_csr_rowdot(M.C, v, base, beta, out, st);
+}
+
+// Scratch of the streaming passes over all rows of A or over sb gathered rows.
+size_t mat_scratch_doubles(const Mat& M, int64_t sb) {
+  if (M.csr) return 1;
+  size_t sc = std::max(gemv_t_scratch_doubles(sb, M.cols), gemv_t_scratch_doubles(M.rows, M.cols));
+  sc = std::max(sc, rowdot_scratch_doubles(M.rows, M.cols, M.dtype));
+  return std::max<size_t>(sc, 1);
+}
+
+// The full residual of the stopping test (Section 5.1.5) and its 2-norm
+// (device scalar), from the vectors the iteration maintains:
+//   primal (A = X, coord = w, comp = r = z - y):  rho = -lambda w - 1/n X r
+//   dual (A = X^T, coord = alpha, comp = w):      rho = -X^T w + alpha + y
+// rho (length rows) receives the vector; it may be the temporary itself.
+hipError_t full_residual(bool dual, const Mat& M, const double* y, double lambda,
+                         const double* coord, const double* comp, double* rho, double* norm,
+                         double* scratch, double* obj_scratch, int* status, hipStream_t st) {
+  hipError_t e;
+  if (!dual) {
+    const double n = (double)M.cols;
+    e = mat_rowdot(M, comp, coord, lambda * n, rho, scratch, st);   // X r + lambda n w
+    if (e != hipSuccess) return e;
+    return launch_resid_norm(rho, -1.0 / n, nullptr, 0.0, M.rows, rho, norm, obj_scratch, status,
+                             st);
+  }
+  e = mat_rowdot(M, comp, y, -1.0, rho, scratch, st);   // X^T w - y
+  if (e != hipSuccess) return e;
+  return launch_resid_norm(coord, 1.0, rho, -1.0, M.rows, rho, norm, obj_scratch, status, st);
 }
 
 cabcd_status finish(hipStream_t st, int* status_dev, bool async) {
@@ -343,10 +374,13 @@ struct StepBuffers {
   double* scratch;   // gemv row-group partials
   double* obj;       // objective scratch
   double* rtmp;      // residual temporary (monitoring)
+  double* rho;       // full residual of the stopping test (rows)
+  double* rnorm;     // its norm
 };
 
 // Layout of the step workspace.
-size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp_len) {
+size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp_len,
+              bool checks) {
   const int sb = s * b;
   B.status = c.take<int>(1);
   B.idx = c.take<int32_t>((size_t)kIdxChunkSteps * sb);
@@ -354,12 +388,11 @@ size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp
   B.Yu = c.take<double>(sb);
   B.delta = c.take<double>(sb);
   B.partials = c.take<double>(max_partials(M, sb));
-  const size_t sc = M.csr ? 1
-                          : std::max(gemv_t_scratch_doubles(sb, M.cols),
-                                     std::max(gemv_t_scratch_doubles(M.rows, M.cols), (size_t)1));
-  B.scratch = c.take<double>(sc);
+  B.scratch = c.take<double>(mat_scratch_doubles(M, sb));
   B.obj = c.take<double>(objective_scratch_doubles(0, 0));
   B.rtmp = c.take<double>(std::max<int64_t>(rtmp_len, 1));
+  B.rho = c.take<double>(checks ? M.rows : 1);
+  B.rnorm = c.take<double>(1);
   return c.off + 256;
 }
 
@@ -441,6 +474,16 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     set_error("opts.timing needs a synchronising call");
     return CABCD_EINVAL;
   }
+  if (!(o.tol >= 0.0) || std::isinf(o.tol) || o.check_every < 0 ||
+      (o.tol > 0.0 && o.check_every == 0)) {
+    set_error("opts.tol must be finite and >= 0, opts.check_every >= 0, and a tolerance "
+              "needs check_every >= 1");
+    return CABCD_EINVAL;
+  }
+  if (o.check_every > 0 && (o.flags & CABCD_FLAG_ASYNC)) {
+    set_error("residual checks (opts.check_every) need a synchronising call");
+    return CABCD_EINVAL;
+  }
   if (o.explicit_idx != nullptr) {
     cabcd_status e = check_explicit(o.explicit_idx, H, b, rows, st);
     if (e != CABCD_OK) return e;
@@ -449,12 +492,15 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   const int64_t rtmp_len = o.monitor_every > 0 ? (dual ? rows : cols) : 1;
   StepBuffers B{};
   Carve probe{nullptr};
-  const size_t need = layout(probe, B, M, b, s, rtmp_len);
+  const bool checks = o.check_every > 0;
+  const size_t need = layout(probe, B, M, b, s, rtmp_len, checks);
   void* ws = nullptr;
   cabcd_status e = get_workspace(&o, need, &ws);
   if (e != CABCD_OK) return e;
   Carve carve{static_cast<char*>(ws)};
-  layout(carve, B, M, b, s, rtmp_len);
+  layout(carve, B, M, b, s, rtmp_len, checks);
+  if (o.iters_done != nullptr) *o.iters_done = 0;
+  if (o.resid_norm != nullptr) *o.resid_norm = std::nan("");
   e = check_csr_device(M, B.status, st);
   if (e != CABCD_OK) return e;
 
@@ -481,7 +527,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       return launch_objective(comp, cols, 0.5 / n, coord, rows, 0.5 * lambda, o.trace + slot,
                               B.obj, B.status, st);
     if (dual) {   // f(w) with r = X^T w - y computed from the X^T layout
-      he = mat_rowdot(M, comp, y, -1.0, B.rtmp, st);
+      he = mat_rowdot(M, comp, y, -1.0, B.rtmp, B.scratch, st);
       if (he != hipSuccess) return he;
       return launch_objective(B.rtmp, rows, 0.5 / n, comp, cols, 0.5 * lambda, o.trace + slot,
                               B.obj, B.status, st);
@@ -543,7 +589,21 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       const int64_t sl = slot++;
       HIP_TRY(timer.run(CABCD_PHASE_MONITOR, [&] { return monitor(sl, fresh); }));
     }
+    if (checks && k % o.check_every == 0) {
+      // Section 5.1.5: the full residual, formed now and then, decides when to
+      // stop (its norm bounds the objective error).
+      HIP_TRY(timer.run(CABCD_PHASE_CHECK, [&] {
+        return full_residual(dual, M, y, lambda, coord, comp, B.rho, B.rnorm, B.scratch, B.obj,
+                             B.status, st);
+      }));
+      double nrm = 0.0;
+      HIP_TRY(hipMemcpyAsync(&nrm, B.rnorm, sizeof nrm, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (o.resid_norm != nullptr) *o.resid_norm = nrm;
+      if (!std::isfinite(nrm) || nrm <= o.tol) break;   // non-finite: reported by finish
+    }
   }
+  if (o.iters_done != nullptr) *o.iters_done = h;
   const cabcd_status fs = finish(st, B.status, (o.flags & CABCD_FLAG_ASYNC) != 0);
   HIP_TRY(timer.collect());
   return fs;
@@ -559,8 +619,8 @@ struct AuxBuffers {
 size_t aux_layout(Carve& c, AuxBuffers& B, const Mat& M, int64_t rlen) {
   B.flag = c.take<int>(1);
   B.r = c.take<double>(std::max<int64_t>(rlen, 1));
-  B.scratch = c.take<double>(M.csr ? 1 : std::max<size_t>(gemv_t_scratch_doubles(M.rows, M.cols), 1));
-  B.obj = c.take<double>(objective_scratch_doubles(0, 0));
+  B.scratch = c.take<double>(mat_scratch_doubles(M, 1));
+  B.obj = c.take<double>(objective_scratch_doubles(0, 0) + 1);   // + one norm
   return c.off + 256;
 }
 cabcd_status aux_get(const Mat& M, int64_t rlen, AuxBuffers& B) {
@@ -719,7 +779,7 @@ cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y, d
   e = check_csr_device(M, B.flag, st);
   if (e != CABCD_OK) return e;
   double* rr = r != nullptr ? r : B.r;
-  HIP_TRY(mat_rowdot(M, w, y, -1.0, rr, st));
+  HIP_TRY(mat_rowdot(M, w, y, -1.0, rr, B.scratch, st));
   if (f != nullptr)
     HIP_TRY(launch_objective(rr, M.rows, 0.5 / (double)M.rows, w, M.cols, 0.5 * lambda, f, B.obj,
                              nullptr, st));
@@ -754,6 +814,58 @@ cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha, d
   return CABCD_OK;
 }
 
+cabcd_status cabcd_primal_residual(const cabcd_matrix* X, double lambda, const double* w,
+                                   const double* r, double* rho, double* norm, void* stream) {
+  clear_error();
+  Mat M;
+  cabcd_status e = check_matrix(X, "X", &M);
+  if (e != CABCD_OK) return e;
+  if (w == nullptr || r == nullptr || !(lambda >= 0.0) || std::isinf(lambda) ||
+      (rho == nullptr && norm == nullptr)) {
+    set_error("cabcd_primal_residual: w and r must be non-NULL, lambda finite and >= 0, and "
+              "rho or norm requested");
+    return CABCD_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  AuxBuffers B{};
+  e = aux_get(M, M.rows, B);
+  if (e != CABCD_OK) return e;
+  e = check_csr_device(M, B.flag, st);
+  if (e != CABCD_OK) return e;
+  HIP_TRY(full_residual(false, M, nullptr, lambda, w, r, rho != nullptr ? rho : B.r,
+                        norm != nullptr ? norm : B.obj + objective_scratch_doubles(0, 0), B.scratch,
+                        B.obj, nullptr, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return CABCD_OK;
+}
+
+cabcd_status cabcd_dual_residual(const cabcd_matrix* XT, const double* y, const double* alpha,
+                                 const double* w, double* rho, double* norm, void* stream) {
+  clear_error();
+  Mat M;
+  cabcd_status e = check_matrix(XT, "XT", &M);
+  if (e != CABCD_OK) return e;
+  if (M.lowp()) {
+    set_error("cabcd_dual_residual: low-precision storage is not supported");
+    return CABCD_EUNSUPPORTED;
+  }
+  if (y == nullptr || alpha == nullptr || w == nullptr || (rho == nullptr && norm == nullptr)) {
+    set_error("cabcd_dual_residual: y, alpha and w must be non-NULL, and rho or norm requested");
+    return CABCD_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  AuxBuffers B{};
+  e = aux_get(M, M.rows, B);
+  if (e != CABCD_OK) return e;
+  e = check_csr_device(M, B.flag, st);
+  if (e != CABCD_OK) return e;
+  HIP_TRY(full_residual(true, M, y, 0.0, alpha, w, rho != nullptr ? rho : B.r,
+                        norm != nullptr ? norm : B.obj + objective_scratch_doubles(0, 0), B.scratch,
+                        B.obj, nullptr, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return CABCD_OK;
+}
+
 cabcd_status cabcd_quantize(const double* A, int64_t rows, int64_t cols, int64_t lda,
                             int32_t dtype, void* Q, int64_t ldq, float* row_scale,
                             void* stream) {
@@ -783,7 +895,7 @@ size_t cabcd_workspace_bytes(const cabcd_matrix* A, int32_t b, int32_t s) {
   if (b < 1 || s < 1 || (int64_t)s * b > max_rows_per_gram(M)) return 0;
   StepBuffers B{};
   Carve probe{nullptr};
-  return layout(probe, B, M, b, s, std::max(A->rows, A->cols));
+  return layout(probe, B, M, b, s, std::max(A->rows, A->cols), true);
 }
 
 }  // extern "C"

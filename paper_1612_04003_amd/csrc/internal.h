@@ -202,10 +202,20 @@ hipError_t launch_gemv_t(const double* A, int64_t ld, int64_t cols, const int32_
                          int64_t m, const double* v, double gamma, const double* base,
                          double beta, bool accumulate, double* out, double* scratch,
                          hipStream_t st);
-// out[p] = sum_k A[p][k] v[k] + beta*base[p], p < rows.
-hipError_t launch_gemv_n(const double* A, int64_t ld, int64_t rows, int64_t cols,
-                         const double* v, const double* base, double beta, double* out,
-                         hipStream_t st);
+// out[p] = s_p sum_k A[p][k] v[k] + beta*base[p], p < rows, for dense A of
+// element type dtype (row scales rs for BF16 / FP8, NULL = 1; ignored for
+// FP64).  Needs a scratch of rowdot_scratch_doubles(rows, cols, dtype) doubles
+// (may be 0).  Deterministic.
+size_t rowdot_scratch_doubles(int64_t rows, int64_t cols, int dtype);
+hipError_t launch_rowdot(int dtype, const void* A, int64_t ld, int64_t rows, int64_t cols,
+                         const float* rs, const double* v, const double* base, double beta,
+                         double* out, double* scratch, hipStream_t st);
+// t = ca a + cb b (b may be NULL), written to vec when non-NULL, and *norm =
+// ||t||_2 (device scalar); scratch holds objective_scratch_doubles() doubles;
+// a non-finite norm sets the status word (status may be NULL).  Deterministic.
+hipError_t launch_resid_norm(const double* a, double ca, const double* b, double cb, int64_t n,
+                             double* vec, double* norm, double* scratch, int* status,
+                             hipStream_t st);
 // *out = c1 * ||a||^2 + c2 * ||b||^2 (b may be NULL), deterministic; sets the
 // status word to DEV_NONFINITE when the result is not finite (status may be NULL).
 size_t objective_scratch_doubles(int64_t na, int64_t nb);

@@ -10,10 +10,16 @@
 //   order; when there are few columns the rows are split over workgroups and
 //   the row groups are summed afterwards in group order, so the result is
 //   deterministic.
-// gemv_n: out[p] = A[p] . v + beta base[p] (primal residual from the X^T
-//   layout), one wave per row.
+// rowdot: out[p] = s_p A[p] . v + beta base[p] for every row p of dense A
+//   (FP64, or BF16 / FP8 codes with row scales s_p): the primal residual from
+//   the X^T layout, and the full residuals of the stopping test (Section
+//   5.1.5): X r for the primal, X^T w for the dual.  One wave per (row, part);
+//   rows longer than one part are cut into parts whose sums are added in
+//   part order by a second pass, so the result is deterministic.
 // objective: c1 ||a||^2 + c2 ||b||^2 in two deterministic passes.
+// resid_norm: t = ca a + cb b (optionally written out) and ||t||_2.
 #include "internal.h"
+#include "lowp_dev.h"
 
 #include <algorithm>
 #include <cmath>
@@ -122,21 +128,123 @@ int gemv_t_groups(int64_t m, int64_t cols) {
   return (int)std::max<int64_t>(rg, 1);
 }
 
-__global__ __launch_bounds__(kVecThreads) void gemv_n_kernel(const double* __restrict__ A,
-                                                             int64_t ld, int64_t rows,
-                                                             int64_t cols,
-                                                             const double* __restrict__ v,
-                                                             const double* __restrict__ base,
-                                                             double beta,
-                                                             double* __restrict__ out) {
+// Row parts: 64 KiB of A per wave and part (8192 FP64, 32768 BF16, 65536 FP8
+// elements), a multiple of the 1 KiB a wave reads per load.
+constexpr int64_t kRowPartBytes = 64 * 1024;
+
+struct RowDot {
+  const uint8_t* A;
+  int64_t ld;          // elements
+  int64_t rows, cols;
+  const float* rs;     // low precision: row scales (NULL = 1)
+  const double* v;
+  const double* base;
+  double beta;
+  double* out;
+  double* part;        // rows x parts partial sums when parts > 1
+  int64_t chunk;       // elements per part
+  int parts;
+  int vec;             // A rows and v 16-byte aligned
+};
+
+// Lane l of a wave reads the 16-byte chunks l, l + 64, ... of its row part,
+// four in flight; the lane sums are combined by a butterfly.
+template <int FMT>
+__global__ __launch_bounds__(kVecThreads) void rowdot_kernel(RowDot g) {
+  constexpr int ES = FMT == CABCD_F64 ? 8 : (FMT == CABCD_BF16 ? 2 : 1);
+  constexpr int EPC = 16 / ES;     // elements per 16-byte chunk
+  constexpr int U = 4;
   const int lane = threadIdx.x & 63;
-  const int64_t p = (int64_t)blockIdx.x * (kVecThreads / 64) + (threadIdx.x >> 6);
-  if (p >= rows) return;
-  const double* a = A + p * ld;
-  double s = 0.0;
-  for (int64_t k = lane; k < cols; k += 64) s = fma(a[k], v[k], s);
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) out[p] = s + (base ? beta * base[p] : 0.0);
+  const int64_t wv = (int64_t)blockIdx.x * (kVecThreads / 64) + (threadIdx.x >> 6);
+  if (wv >= g.rows * g.parts) return;   // wave-uniform
+  const int64_t p = wv / g.parts;
+  const int q = (int)(wv - p * g.parts);
+  const int64_t k0 = (int64_t)q * g.chunk;
+  const int64_t k1 = std::min(g.cols, k0 + g.chunk);
+  const gptr<const uint8_t> row = glb(g.A) + p * g.ld * ES;
+  const gptr<const double> v = glb(g.v);
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+  double acc = 0.0;
+  auto chunk_dot = [&](const uint4& x, int64_t k) {
+    double e[EPC];
+    if constexpr (FMT == CABCD_F64) {
+      __builtin_memcpy(e, &x, 16);
+    } else {
+      ldev::lp_decode_all<FMT>(x, e);
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < EPC; j += 2) {
+      const dv2 c = *(gptr<const dv2>)(v + k + j);
+      t = fma(e[j], c.x, t);
+      t = fma(e[j + 1], c.y, t);
+    }
+    return t;
+  };
+  int64_t k = k0 + (int64_t)lane * EPC;
+  if (g.vec) {
+    typedef unsigned int uv4 __attribute__((ext_vector_type(4)));
+    for (; k + (int64_t)(U - 1) * 64 * EPC + EPC <= k1; k += (int64_t)U * 64 * EPC) {
+      uint4 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uv4 t = *(gptr<const uv4>)(row + (k + (int64_t)u * 64 * EPC) * ES);
+        x[u] = make_uint4(t.x, t.y, t.z, t.w);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += chunk_dot(x[u], k + (int64_t)u * 64 * EPC);
+    }
+    for (; k + EPC <= k1; k += 64 * EPC) {
+      const uv4 t = *(gptr<const uv4>)(row + k * ES);
+      acc += chunk_dot(make_uint4(t.x, t.y, t.z, t.w), k);
+    }
+  }
+  // element by element: unaligned rows, and the ragged end of the part
+  for (; k < k1; k += 64 * EPC) {
+    const int64_t ke = std::min<int64_t>(k + EPC, k1);
+    double t = 0.0;
+    for (int64_t kk = k; kk < ke; ++kk) {
+      double a;
+      if constexpr (FMT == CABCD_F64) {
+        a = *(gptr<const double>)(row + kk * 8);
+      } else if constexpr (FMT == CABCD_BF16) {
+        a = decode_bf16((uint32_t)row[2 * kk] | ((uint32_t)row[2 * kk + 1] << 8));
+      } else {
+        a = (double)__builtin_amdgcn_cvt_pk_f32_fp8((int)row[kk], false)[0];
+      }
+      t = fma(a, v[kk], t);
+    }
+    acc += t;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane != 0) return;
+  if (g.parts > 1) {
+    g.part[p * g.parts + q] = acc;
+    return;
+  }
+  const double sc = g.rs ? (double)g.rs[p] : 1.0;
+  g.out[p] = sc * acc + (g.base ? g.beta * g.base[p] : 0.0);
+}
+
+__global__ __launch_bounds__(kVecThreads) void rowdot_combine_kernel(RowDot g) {
+  const int64_t p = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (p >= g.rows) return;
+  double acc = 0.0;
+  for (int q = 0; q < g.parts; ++q) acc += g.part[p * g.parts + q];
+  const double sc = g.rs ? (double)g.rs[p] : 1.0;
+  g.out[p] = sc * acc + (g.base ? g.beta * g.base[p] : 0.0);
+}
+
+int rowdot_parts(int64_t rows, int64_t cols, int es, int64_t* chunk) {
+  const int64_t per = kRowPartBytes / es;
+  // Split long rows only when the rows alone give fewer than 8192 waves.
+  int64_t parts = (cols + per - 1) / per;
+  if (rows >= 8192) parts = 1;
+  parts = std::max<int64_t>(1, std::min<int64_t>(parts, 4096));
+  int64_t c = (cols + parts - 1) / parts;
+  c = (c + 1023) / 1024 * 1024;   // whole 16-byte chunks of every element size
+  *chunk = c;
+  return (int)((cols + c - 1) / c);
 }
 
 constexpr int kObjBlocks = 512;
@@ -190,7 +298,105 @@ __global__ __launch_bounds__(kVecThreads) void objective_final_kernel(
   }
 }
 
+// t = ca a + cb b (b may be NULL); t written to vec when non-NULL; per-block
+// sums of t^2 to part.
+__global__ __launch_bounds__(kVecThreads) void comb_sumsq_kernel(
+    const double* __restrict__ a, double ca, const double* __restrict__ b, double cb, int64_t n,
+    double* __restrict__ vec, double* __restrict__ part) {
+  __shared__ double red[kVecThreads];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kVecThreads) {
+    const double t = ca * a[i] + (b ? cb * b[i] : 0.0);
+    if (vec) vec[i] = t;
+    s = fma(t, t, s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kVecThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kVecThreads) void norm_final_kernel(
+    const double* __restrict__ part, int blocks, double* __restrict__ out,
+    int* __restrict__ status) {
+  __shared__ double red[kVecThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < blocks; i += kVecThreads) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kVecThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = sqrt(red[0]);
+    *out = r;
+    if (status != nullptr && !isfinite(r)) *status = DEV_NONFINITE;
+  }
+}
+
 }  // namespace
+
+size_t rowdot_scratch_doubles(int64_t rows, int64_t cols, int dtype) {
+  int64_t chunk = 0;
+  const int es = dtype == CABCD_F64 ? 8 : (dtype == CABCD_BF16 ? 2 : 1);
+  const int parts = rowdot_parts(rows, cols, es, &chunk);
+  return parts > 1 ? (size_t)parts * (size_t)rows : 0;
+}
+
+hipError_t launch_rowdot(int dtype, const void* A, int64_t ld, int64_t rows, int64_t cols,
+                         const float* rs, const double* v, const double* base, double beta,
+                         double* out, double* scratch, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int es = dtype == CABCD_F64 ? 8 : (dtype == CABCD_BF16 ? 2 : 1);
+  RowDot g{};
+  g.A = static_cast<const uint8_t*>(A);
+  g.ld = ld;
+  g.rows = rows;
+  g.cols = cols;
+  g.rs = dtype == CABCD_F64 ? nullptr : rs;
+  g.v = v;
+  g.base = base;
+  g.beta = beta;
+  g.out = out;
+  g.parts = rowdot_parts(rows, cols, es, &g.chunk);
+  g.part = g.parts > 1 ? scratch : nullptr;
+  if (g.parts > 1 && scratch == nullptr) return hipErrorInvalidValue;
+  g.vec = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && ((ld * es) & 15) == 0 &&
+           (reinterpret_cast<uintptr_t>(v) & 15) == 0)
+              ? 1
+              : 0;
+  const int64_t waves = rows * g.parts;
+  const int64_t per = kVecThreads / 64;
+  const dim3 grid((unsigned)((waves + per - 1) / per));
+  if (dtype == CABCD_F64)
+    hipLaunchKernelGGL(rowdot_kernel<CABCD_F64>, grid, dim3(kVecThreads), 0, st, g);
+  else if (dtype == CABCD_BF16)
+    hipLaunchKernelGGL(rowdot_kernel<CABCD_BF16>, grid, dim3(kVecThreads), 0, st, g);
+  else
+    hipLaunchKernelGGL(rowdot_kernel<CABCD_FP8_E4M3>, grid, dim3(kVecThreads), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.parts == 1) return e;
+  hipLaunchKernelGGL(rowdot_combine_kernel, dim3((unsigned)((rows + kVecThreads - 1) / kVecThreads)),
+                     dim3(kVecThreads), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid_norm(const double* a, double ca, const double* b, double cb, int64_t n,
+                             double* vec, double* norm, double* scratch, int* status,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(comb_sumsq_kernel, dim3(kObjBlocks), dim3(kVecThreads), 0, st, a, ca, b, cb,
+                     n, vec, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kVecThreads), 0, st, scratch, kObjBlocks,
+                     norm, status);
+  return hipGetLastError();
+}
 
 size_t gemv_t_scratch_doubles(int64_t m, int64_t cols) {
   const int rg = gemv_t_groups(m, cols);
@@ -231,16 +437,6 @@ hipError_t launch_gemv_t(const double* A, int64_t ld, int64_t cols, const int32_
   hipLaunchKernelGGL(gemv_t_combine_kernel,
                      dim3((unsigned)((cols + kVecThreads - 1) / kVecThreads)),
                      dim3(kVecThreads), 0, st, g, rg);
-  return hipGetLastError();
-}
-
-hipError_t launch_gemv_n(const double* A, int64_t ld, int64_t rows, int64_t cols,
-                         const double* v, const double* base, double beta, double* out,
-                         hipStream_t st) {
-  if (rows <= 0) return hipSuccess;
-  const int64_t per = kVecThreads / 64;
-  hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)((rows + per - 1) / per)), dim3(kVecThreads),
-                     0, st, A, ld, rows, cols, v, base, beta, out);
   return hipGetLastError();
 }
 

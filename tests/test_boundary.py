@@ -33,7 +33,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header():
     # Field order and sizes of the two structs as the header declares them.
     assert ctypes.sizeof(cabcd.Matrix) == 4 + 4 + 8 * 9
-    assert ctypes.sizeof(cabcd.Opts) == 8 + 4 + 4 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(cabcd.Opts) == (8 + 4 + 4 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8
+                                         + 8 + 4 + 4 + 8 + 8)
 
 
 def _fake_matrix(rows, cols, kind=cabcd.DENSE, dtype=cabcd.F64):
@@ -154,3 +155,38 @@ def test_batch_plan_errors():
     two[1].X.dtype = cabcd.BF16
     assert lib.cabcd_batch_create(two, 2, None, None, ctypes.byref(h)) == cabcd.EINVAL
     assert "same storage type" in lib.cabcd_last_error().decode()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tol=-1.0, check_every=1),
+    dict(tol=float("nan"), check_every=1),
+    dict(tol=float("inf"), check_every=1),
+    dict(tol=1e-3, check_every=0),           # a tolerance needs checks
+    dict(tol=0.0, check_every=-2),
+    dict(tol=1e-3, check_every=2, flags=cabcd.FLAG_ASYNC),   # checks read the norm on the host
+])
+def test_residual_check_option_errors(kw):
+    lib = cabcd.load()
+    o = cabcd._opts(**kw)
+    M = _fake_matrix(64, 1024)
+    for fn in (lib.cabcd_primal_bcd, lib.cabcd_dual_bcd):
+        st = fn(ctypes.byref(M), ctypes.c_void_p(0x2000), 1e-3, 4, 8, 10, 1,
+                ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), ctypes.byref(o), None)
+        assert st == cabcd.EINVAL
+        assert "check" in lib.cabcd_last_error().decode()
+
+
+def test_residual_entry_point_errors():
+    lib = cabcd.load()
+    M = _fake_matrix(64, 1024)
+    p = ctypes.c_void_p(0x2000)
+    assert lib.cabcd_primal_residual(None, 1e-3, p, p, p, p, None) == cabcd.EINVAL
+    assert lib.cabcd_primal_residual(ctypes.byref(M), 1e-3, None, p, p, p, None) == cabcd.EINVAL
+    assert lib.cabcd_primal_residual(ctypes.byref(M), 1e-3, p, None, p, p, None) == cabcd.EINVAL
+    assert lib.cabcd_primal_residual(ctypes.byref(M), -1.0, p, p, p, p, None) == cabcd.EINVAL
+    assert lib.cabcd_primal_residual(ctypes.byref(M), 1e-3, p, p, None, None,
+                                     None) == cabcd.EINVAL
+    assert lib.cabcd_dual_residual(ctypes.byref(M), None, p, p, p, p, None) == cabcd.EINVAL
+    assert lib.cabcd_dual_residual(ctypes.byref(M), p, p, p, None, None, None) == cabcd.EINVAL
+    M.dtype = cabcd.BF16
+    assert lib.cabcd_dual_residual(ctypes.byref(M), p, p, p, p, p, None) == cabcd.EUNSUPPORTED
