@@ -105,7 +105,10 @@ typedef struct cabcd_opts {
                                 this many outer steps (0 = never)                   */
   int32_t monitor_every;     /* write the primal objective f(w) to trace every this
                                 many outer steps (0 = never)                        */
-  int32_t reserved0;
+  uint32_t timing_mask;      /* phases bracketed by events when `timing` is set: bit
+                                p = CABCD_PHASE p; 0 = every phase.  Each event pair
+                                costs a few microseconds of GPU time, so a caller
+                                that times one kernel should mask the others.      */
   const int32_t* explicit_idx; /* optional H*b device indices replacing the sampler:
                                   block of iteration h0+i is explicit_idx[i*b ..]  */
   double* trace;             /* device, trace_len doubles (monitor output)          */

@@ -42,7 +42,7 @@ class Matrix(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("h0", ctypes.c_int64), ("flags", ctypes.c_uint32),
                 ("resid_every", ctypes.c_int32), ("monitor_every", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32),
+                ("timing_mask", ctypes.c_uint32),
                 ("explicit_idx", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("trace_len", ctypes.c_int64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
@@ -268,7 +268,7 @@ def describe(A):
 
 
 def _opts(h0=0, flags=0, resid_every=0, monitor_every=0, explicit_idx=None, trace=None,
-          workspace=None, timing=None, tol=0.0, check_every=0, stats=None):
+          workspace=None, timing=None, timing_mask=0, tol=0.0, check_every=0, stats=None):
     """cabcd_opts from keywords.  `stats`, a dict, receives "h" (inner
     iterations performed) and "resid_norm" (norm at the last residual check)
     after the call."""
@@ -291,6 +291,7 @@ def _opts(h0=0, flags=0, resid_every=0, monitor_every=0, explicit_idx=None, trac
         o.workspace, o.workspace_bytes = workspace.data_ptr(), workspace.numel()
     if timing is not None:
         o.timing = ctypes.cast(timing, ctypes.POINTER(ctypes.c_double))
+        o.timing_mask = timing_mask
     return o
 
 

@@ -298,7 +298,8 @@ cabcd_status check_explicit(const int32_t* idx_dev, int64_t H, int b, int64_t ra
 // Optional per-phase timing with HIP events on the call's stream.
 class PhaseTimer {
  public:
-  PhaseTimer(double* out, hipStream_t st) : out_(out), st_(st) {}
+  PhaseTimer(double* out, uint32_t mask, hipStream_t st)
+      : out_(out), mask_(mask == 0 ? ~0u : mask), st_(st) {}
   ~PhaseTimer() {
     for (auto& r : recs_) {
       (void)hipEventDestroy(r.a);
@@ -307,7 +308,7 @@ class PhaseTimer {
   }
   template <class F>
   hipError_t run(int phase, F&& f) {
-    if (out_ == nullptr) return f();
+    if (out_ == nullptr || !((mask_ >> phase) & 1u)) return f();
     Rec r{phase, nullptr, nullptr};
     hipError_t e = hipEventCreate(&r.a);
     if (e == hipSuccess) e = hipEventCreate(&r.b);
@@ -338,6 +339,7 @@ class PhaseTimer {
     hipEvent_t a, b;
   };
   double* out_;
+  uint32_t mask_;
   hipStream_t st_;
   std::vector<Rec> recs_;
 };
@@ -538,7 +540,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
                             B.obj, B.status, st);
   };
 
-  PhaseTimer timer(o.timing, st);
+  PhaseTimer timer(o.timing, o.timing_mask, st);
   if (!(o.flags & CABCD_FLAG_STATE_VALID))
     HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
 

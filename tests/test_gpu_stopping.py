@@ -174,6 +174,12 @@ def test_primal_checks_without_tolerance_run_to_h(gpu_lib):
     tm = gpu_lib.new_timing()
     gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), 1e-2, 3, 4, 40, 9, check_every=2, timing=tm)
     assert gpu_lib.timing_dict(tm)["check"]["launches"] == 5   # ceil(40/4) = 10 steps
+    # a timing mask brackets the selected phases only
+    tm = gpu_lib.new_timing()
+    gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), 1e-2, 3, 4, 40, 9, check_every=2, timing=tm,
+                       timing_mask=1 << gpu_lib.PHASES.index("gram"))
+    counts = {k: v["launches"] for k, v in gpu_lib.timing_dict(tm).items()}
+    assert counts["gram"] == 10 and sum(counts.values()) == 10
 
 
 def test_primal_lowp_stops_where_oracle_stops(gpu_lib):
