@@ -28,11 +28,13 @@ hipError_t launch_b(const SolveArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The one-barrier block mapping (MAP 1) whenever s BP lanes fit the workgroup.
+// The one-barrier block mapping (MAP 1) whenever s BP lanes fit the workgroup,
+// in the smallest workgroup that holds them (cheaper barriers on the chain).
 template <int BP, int PF>
 hipError_t launch_t(const SolveArgs& a, hipStream_t st) {
   const int lanes = a.s * BP;
   if constexpr (BP <= 16) {
+    if (lanes <= 256) return launch_b<BP, PF, 256, 1>(a, st);
     if (lanes <= 512) return launch_b<BP, PF, 512, 1>(a, st);
   }
   if (a.m <= 512) return launch_b<BP, PF, 512, 0>(a, st);

@@ -14,7 +14,8 @@
 // because indices within a block are distinct).
 //
 // Phases (one workgroup; thread p owns row p of the outer step):
-//  1. c, and the diagonal blocks of Gov gathered into registers;
+//  1. c, and the diagonal blocks of Gov gathered into LDS by the whole
+//     workgroup (one memory round trip);
 //  2. every diagonal block inverted by one wave with in-place Gauss-Jordan
 //     elimination, the block's entries spread over the lanes and exchanged by
 //     shuffles (no LDS round trips, no barriers).  Blocks are padded to
@@ -134,19 +135,10 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   const int u = MAP == 0 ? (active ? tid - j_of * b : 0) : tid % BP;
   const int p = MAP == 0 ? tid : (active ? j_of * b + u : m);   // row of the outer step
 
-  // ---- phase 1
-  double rhs = 0.0;
-  int ip = 0;
-  if (active) {
-    ip = a.idx[p];
-    Ix[p] = ip;
-    const double yu = glb(a.Yu)[p];
-    const double xi = glb(a.x)[ip];
-    rhs = a.mode == 0 ? (-a.lambda * xi - yu / a.n) : ((yu - xi - glb(a.y)[ip]) / a.n);
-  }
-  for (int q = tid; q < s * BP; q += THREADS) Dl[q] = 0.0;
-  if (tid < BP) R[tid] = 0.0;
-
+  // ---- phase 1: the loads that depend on nothing go out together (the ring
+  // of Gov row segments, idx and Y u, the diagonal blocks); x[idx] follows
+  // and stays in flight through the inversions.
+  //
   // Prefetch ring of Gov row segments Gov[p][jb*b + v].  Gov is symmetric, so
   // they are read as Gov[jb*b + v][p]: consecutive threads then read
   // consecutive addresses (one cache line per 16 lanes instead of one per
@@ -162,25 +154,72 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   };
 #pragma unroll
   for (int q = 0; q < PF; ++q) ring_load(q, q);
+  // idx is read through a generic pointer: the batched kernel passes indices
+  // that live in LDS
+  const int ip = active ? a.idx[p] : 0;
+  const double yu = active ? glb(a.Yu)[p] : 0.0;
 
-  // ---- phase 2: invert the diagonal blocks, SPW blocks per wave at a time
+  // ---- phase 2: the diagonal blocks, padded to BP x BP with the identity,
+  // come into LDS through loads of the whole workgroup (four per thread in
+  // flight, so about one memory round trip), then are inverted in place, SPW
+  // blocks per wave at a time
   constexpr int WAVES = THREADS / 64;
-  bool bad = false;
-  for (int j0 = wave * C::SPW; j0 < s; j0 += WAVES * C::SPW) {
-    // entry t of this lane: block blk(t), row uu(t), column vv(t)
-    auto blk = [&](int t) { return C::EPL == 1 ? j0 + lane / (BP * BP) : j0; };
-    auto eix = [&](int t) { return C::EPL == 1 ? lane % (BP * BP) : lane + 64 * t; };
-    double e[C::EPL];
+  {
+    constexpr int PER = 4;
+    const int total = s * BP * BP;
+    for (int q0 = 0; q0 < total; q0 += THREADS * PER) {
+      double v[PER];
 #pragma unroll
-    for (int t = 0; t < C::EPL; ++t) {
-      const int bj = blk(t), uu = eix(t) / BP, vv = eix(t) % BP;
-      e[t] = (bj < s && uu < b && vv < b) ? glb(a.G)[(int64_t)(bj * b + uu) * m + bj * b + vv]
-                                          : (uu == vv ? 1.0 : 0.0);   // identity padding
+      for (int i = 0; i < PER; ++i) {
+        const int q = q0 + i * THREADS + tid;
+        const int bj = q / (BP * BP), uu = (q / BP) % BP, vv = q % BP;
+        v[i] = (q < total && uu < b && vv < b)
+                   ? glb(a.G)[(int64_t)(bj * b + uu) * m + bj * b + vv]
+                   : (uu == vv ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int q = q0 + i * THREADS + tid;
+        if (q < total) Gi[q] = v[i];
+      }
     }
-    gj_invert<BP>(e, lane, bad);
+  }
+  double rhs = 0.0;
+  if (active) {
+    Ix[p] = ip;
+    const double xi = glb(a.x)[ip];
+    rhs = a.mode == 0 ? (-a.lambda * xi - yu / a.n) : ((yu - xi - glb(a.y)[ip]) / a.n);
+  }
+  for (int q = tid; q < s * BP; q += THREADS) Dl[q] = 0.0;
+  if (tid < BP) R[tid] = 0.0;
+  lds_barrier();
+  // With one entry per lane, two rounds of blocks per wave at once: their
+  // elimination chains are independent, so their latencies overlap (larger
+  // blocks have enough independent work per round and no registers to spare).
+  constexpr int RND = C::EPL == 1 ? 2 : 1;
+  bool bad = false;
+  for (int j0 = wave * C::SPW; j0 < s; j0 += RND * WAVES * C::SPW) {
+    // entry t of this lane in round r: block blk(r, t), row uu(t), column vv(t)
+    auto blk = [&](int r, int t) {
+      return (C::EPL == 1 ? j0 + lane / (BP * BP) : j0) + r * WAVES * C::SPW;
+    };
+    auto eix = [&](int t) { return C::EPL == 1 ? lane % (BP * BP) : lane + 64 * t; };
+    double e[RND][C::EPL];
 #pragma unroll
-    for (int t = 0; t < C::EPL; ++t)
-      if (blk(t) < s) Gi[((size_t)blk(t) * BP + eix(t) / BP) * BP + eix(t) % BP] = e[t];
+    for (int r = 0; r < RND; ++r)
+#pragma unroll
+      for (int t = 0; t < C::EPL; ++t) {
+        const int bj = blk(r, t), uu = eix(t) / BP, vv = eix(t) % BP;
+        e[r][t] = bj < s ? Gi[((size_t)bj * BP + uu) * BP + vv] : (uu == vv ? 1.0 : 0.0);
+      }
+#pragma unroll
+    for (int r = 0; r < RND; ++r) gj_invert<BP>(e[r], lane, bad);
+#pragma unroll
+    for (int r = 0; r < RND; ++r)
+#pragma unroll
+      for (int t = 0; t < C::EPL; ++t)
+        if (blk(r, t) < s)
+          Gi[((size_t)blk(r, t) * BP + eix(t) / BP) * BP + eix(t) % BP] = e[r][t];
   }
   if (bad) *glb(a.status) = DEV_NOTSPD;
   lds_barrier();
