@@ -48,7 +48,11 @@ def test_sampler_bit_exact(gpu_lib, seed, h0, count, b, rng):
 
 @pytest.mark.parametrize("m,cols", [(1, 1), (5, 7), (16, 300), (17, 301), (32, 4097),
                                     (33, 1000), (64, 2049), (100, 5000), (128, 777),
-                                    (200, 3001), (256, 20000), (256, 65)])
+                                    (200, 3001), (256, 20000), (256, 65),
+                                    # LDS-DMA path (128 < m <= 256, even cols): one, two
+                                    # and three tiles per slab, a partial last tile
+                                    (129, 16), (256, 32), (256, 48), (160, 1000),
+                                    (250, 4098)])
 def test_gram_matches_oracle(gpu_lib, m, cols):
     _say("gram", m, cols)
     rows = max(m + 3, 40)
