@@ -194,7 +194,7 @@ def extra_records(args, cabcd, torch, synth, X, y):
     for s in (1, 4, 16):
         sb = s * args.b
         el, ph = timed_primal(cabcd, torch, X, y, lam, args.b, s, 20, 2, 2001)
-        g = ph["gram"]["ms"] / max(ph["gram"]["launches"], 1)
+        g = ph["gram"]["ms"] / 20   # Gram time per outer step
         rec[f"primal_s{s}"] = {"ms_per_step": round(el / 20 * 1e3, 4),
                                "gram_ms": round(g, 4),
                                "gram_tflops": round(n * sb * (sb + 1) / (g * 1e-3) / 1e12, 3),
@@ -202,7 +202,7 @@ def extra_records(args, cabcd, torch, synth, X, y):
         log(f"primal s={s}: {rec[f'primal_s{s}']}")
     XT = X.t().contiguous()
     el, ph = timed_primal(cabcd, torch, XT, y, lam, args.b, args.s, 20, 2, 2001, dual=True)
-    g = ph["gram"]["ms"] / max(ph["gram"]["launches"], 1)
+    g = ph["gram"]["ms"] / 20
     sb = args.s * args.b
     rec["dual_s32"] = {"ms_per_step": round(el / 20 * 1e3, 4), "gram_ms": round(g, 4),
                        "gram_tflops": round(d * sb * (sb + 1) / (g * 1e-3) / 1e12, 3)}
@@ -218,7 +218,9 @@ def extra_records(args, cabcd, torch, synth, X, y):
     for s in (1, 8, 32):
         b = 16
         el, ph = timed_primal(cabcd, torch, A, yd, 1e-5, b, s, 20, 2, 2002, dual=True)
-        g = ph["gram"]["ms"] / max(ph["gram"]["launches"], 1)
+        # per outer step: the Grams of several future steps come from one launch,
+        # the Y u of each step from its own
+        g = ph["gram"]["ms"] / 20
         # algorithmic Gram work of the sampled rows: 2 sum_c nnz_c(I)^2 flops over the
         # nnz of the gathered rows (12 bytes each), averaged over the timed steps
         idx = cabcd.sample(2002, 2 * s, 20 * s, b, 20000).cpu().numpy().reshape(20, s * b)

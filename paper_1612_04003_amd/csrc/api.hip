@@ -35,6 +35,8 @@ namespace {
 
 constexpr int kMaxSBDense = 256;            // s*b of one dense FP64 Gram launch
 constexpr int64_t kIdxChunkSteps = 4096;    // outer steps whose indices are drawn at once
+constexpr int kCsrAhead = 64;               // CSR: outer-step Grams computed per launch (max)
+constexpr int64_t kCsrAheadDoubles = (int64_t)8 << 20;   // their buffer (64 MiB at most)
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
 
@@ -366,10 +368,18 @@ hipError_t mat_gram(const Mat& M, const int32_t* idx, int m, const double* u, do
   return timer ? timer->run(CABCD_PHASE_REDUCE, r) : r();
 }
 
+// Gram slots of the step buffers: CSR computes the Grams of several future
+// outer steps per launch (its per-step Gram is a latency-bound walk with too
+// little work to fill the GPU); dense computes one per step.
+int gram_slots(const Mat& M, int64_t sb) {
+  if (!M.csr) return 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kCsrAhead, kCsrAheadDoubles / (sb * sb)));
+}
+
 struct StepBuffers {
   int* status;
   int32_t* idx;      // kIdxChunkSteps * s * b
-  double* G;         // sb x sb
+  double* G;         // gram_slots x sb x sb
   double* Yu;        // sb
   double* delta;     // sb
   double* partials;  // dense Gram partials
@@ -386,7 +396,7 @@ size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp
   const int sb = s * b;
   B.status = c.take<int>(1);
   B.idx = c.take<int32_t>((size_t)kIdxChunkSteps * sb);
-  B.G = c.take<double>((size_t)sb * sb);
+  B.G = c.take<double>((size_t)gram_slots(M, sb) * sb * sb);
   B.Yu = c.take<double>(sb);
   B.delta = c.take<double>(sb);
   B.partials = c.take<double>(max_partials(M, sb));
@@ -544,6 +554,8 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   if (!(o.flags & CABCD_FLAG_STATE_VALID))
     HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
 
+  const int K = gram_slots(M, (int64_t)s * b);   // CSR Grams per launch
+  int ahead = 0, gslot = 0;                       // precomputed Grams left, next slot
   int64_t h = 0, k = 0, slot = 0;
   int64_t chunk_begin = -1, chunk_end = -1;
   const int64_t chunk_iters = kIdxChunkSteps * (int64_t)s;
@@ -564,9 +576,31 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       }
       idx = B.idx + (h - chunk_begin) * b;
     }
-    HIP_TRY(mat_gram(M, idx, m, comp, scale, shift, true, B.G, B.Yu, B.partials, st, &timer));
+    const double* Gk = B.G;
+    if (K > 1 && sk == s) {
+      if (ahead == 0) {
+        // the Grams of the next full outer steps whose indices are at hand
+        int64_t avail = (H - h) / s;
+        if (o.explicit_idx == nullptr) avail = std::min(avail, (chunk_end - h) / s);
+        const int nst = (int)std::min<int64_t>(K, std::max<int64_t>(avail, 1));
+        HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
+          return launch_csr_gram_steps(M.C, idx, m, nst, scale, shift, true, B.G, st);
+        }));
+        ahead = nst;
+        gslot = 0;
+      }
+      Gk = B.G + (size_t)gslot * m * m;
+      ++gslot;
+      --ahead;
+      HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
+        return launch_csr_rowdot_rows(M.C, idx, m, comp, B.Yu, st);
+      }));
+    } else {
+      HIP_TRY(
+          mat_gram(M, idx, m, comp, scale, shift, true, B.G, B.Yu, B.partials, st, &timer));
+    }
     SolveArgs sa{};
-    sa.G = B.G;
+    sa.G = Gk;
     sa.Yu = B.Yu;
     sa.idx = idx;
     sa.y = y;

@@ -10,6 +10,13 @@
 // table are processed in table-sized chunks whose dot products are added in
 // chunk order.  Y u is the same pass with u gathered at the row's columns.
 //
+// The walks are latency-bound (each probe waits for the row's column indices),
+// so a launch can cover the Grams of several future outer steps at once: the
+// Gram depends on the sampled indices only, and one workgroup per (step, row)
+// gives the machine enough independent walks to hide the latency.  The row
+// extents of the gathered rows sit in LDS, and each lane loads four entries of
+// a probed row before probing.
+//
 // The companion updates (primal r += Y^T delta, dual w -= Y^T delta/(lambda n))
 // and the exact recomputations scatter into the columns of the gathered rows;
 // columns shared by several rows (popular features) meet in FP64 atomic adds,
@@ -26,6 +33,8 @@ constexpr int kCsrWaves = kCsrThreads / 64;
 constexpr int kHashSlots = 4096;            // power of two
 constexpr int kChunk = kHashSlots / 2;      // row entries per table fill
 constexpr int kMaxBatches = 4;              // m <= 4 * 64 * kCsrWaves = 1024
+constexpr int kMaxRows = kMaxBatches * 64 * kCsrWaves;
+constexpr int kProbeU = 4;                  // row entries per lane loaded together
 
 __device__ __forceinline__ unsigned hash_col(int c) {
   return ((unsigned)c * 2654435761u) >> (32 - 12);   // log2(kHashSlots) = 12
@@ -36,18 +45,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Step blockIdx.y uses idx + step * idx_stride and writes G + step * g_stride.
 __global__ __launch_bounds__(kCsrThreads) void csr_gram_kernel(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
     const double* __restrict__ vals, const int32_t* __restrict__ idx, int m,
-    const double* __restrict__ u, double scale, double shift, int overlap,
-    double* __restrict__ G, double* __restrict__ Yu) {
+    int64_t idx_stride, const double* __restrict__ u, double scale, double shift, int overlap,
+    double* __restrict__ G, int64_t g_stride, double* __restrict__ Yu) {
   __shared__ int keys[kHashSlots];
   __shared__ double hv[kHashSlots];
+  __shared__ int64_t ext[2][kMaxRows];     // row extents of the gathered rows
+  idx += (int64_t)blockIdx.y * idx_stride;
+  G += (int64_t)blockIdx.y * g_stride;
   const int p = m - 1 - (int)blockIdx.x;   // the longest triangles start first
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  for (int q = threadIdx.x; q <= p; q += kCsrThreads) {
+    const int iq = idx[q];
+    ext[0][q] = rowptr[iq];
+    ext[1][q] = rowptr[iq + 1];
+  }
+  __syncthreads();
   const int ip = idx[p];
-  const int64_t p0 = rowptr[ip], p1 = rowptr[ip + 1];
+  const int64_t p0 = ext[0][p], p1 = ext[1][p];
 
   if (Yu != nullptr && wave == 0) {
     double t = 0.0;
@@ -80,15 +99,25 @@ __global__ __launch_bounds__(kCsrThreads) void csr_gram_kernel(
       for (int j = 0; j < 64; ++j) {
         const int q = qb + wave + kCsrWaves * j;
         if (q > p) break;
-        const int iq = idx[q];
-        const int64_t q0 = rowptr[iq], q1 = rowptr[iq + 1];
+        const int64_t q0 = ext[0][q], q1 = ext[1][q];
         double t = 0.0;
-        for (int64_t k = q0 + lane; k < q1; k += 64) {
-          const int col = colidx[k];
-          unsigned h = hash_col(col);
-          int key;
-          while ((key = keys[h]) != col && key != -1) h = (h + 1) & (kHashSlots - 1);
-          if (key == col) t = fma(vals[k], hv[h], t);
+        for (int64_t kb = q0 + lane; kb < q1; kb += 64 * kProbeU) {
+          int col[kProbeU];
+          double val[kProbeU];
+#pragma unroll
+          for (int e = 0; e < kProbeU; ++e) {   // entries kb, kb + 64, ... of this lane
+            const int64_t k = kb + 64 * e;
+            col[e] = k < q1 ? colidx[k] : -1;
+            val[e] = k < q1 ? vals[k] : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < kProbeU; ++e) {
+            if (col[e] < 0) continue;
+            unsigned h = hash_col(col[e]);
+            int key;
+            while ((key = keys[h]) != col[e] && key != -1) h = (h + 1) & (kHashSlots - 1);
+            if (key == col[e]) t = fma(val[e], hv[h], t);
+          }
         }
         t = wave_sum(t);
         if (lane == j) mine[bi] += t;
@@ -124,16 +153,18 @@ __global__ __launch_bounds__(kCsrThreads) void csr_scatter_kernel(
     unsafeAtomicAdd(out + colidx[k], c * vals[k]);   // coarse-grained memory: hardware FP64 add
 }
 
-// out[p] = A[p] . v + beta * base[p]
+// out[p] = A[row(p)] . v + beta * base[p], row(p) = idx ? idx[p] : p
 __global__ __launch_bounds__(kCsrThreads) void csr_rowdot_kernel(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-    const double* __restrict__ vals, int64_t rows, const double* __restrict__ v,
-    const double* __restrict__ base, double beta, double* __restrict__ out) {
+    const double* __restrict__ vals, const int32_t* __restrict__ idx, int64_t rows,
+    const double* __restrict__ v, const double* __restrict__ base, double beta,
+    double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * kCsrWaves + (threadIdx.x >> 6);
   if (p >= rows) return;
+  const int64_t r = idx ? (int64_t)idx[p] : p;
   double t = 0.0;
-  for (int64_t k = rowptr[p] + lane; k < rowptr[p + 1]; k += 64) t = fma(vals[k], v[colidx[k]], t);
+  for (int64_t k = rowptr[r] + lane; k < rowptr[r + 1]; k += 64) t = fma(vals[k], v[colidx[k]], t);
   t = wave_sum(t);
   if (lane == 0) out[p] = t + (base ? beta * base[p] : 0.0);
 }
@@ -178,8 +209,29 @@ __global__ void csr_check_kernel(const int64_t* __restrict__ rowptr,
 hipError_t launch_csr_gram(const CsrView& A, const int32_t* idx, int m, const double* u,
                            double scale, double shift, bool overlap, double* G, double* Yu,
                            hipStream_t st) {
-  hipLaunchKernelGGL(csr_gram_kernel, dim3(m), dim3(kCsrThreads), 0, st, A.rowptr, A.colidx,
-                     A.vals, idx, m, u, scale, shift, overlap ? 1 : 0, G, Yu);
+  if (m < 1 || m > kMaxRows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(csr_gram_kernel, dim3(m, 1), dim3(kCsrThreads), 0, st, A.rowptr, A.colidx,
+                     A.vals, idx, m, (int64_t)0, u, scale, shift, overlap ? 1 : 0, G, (int64_t)0,
+                     Yu);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_gram_steps(const CsrView& A, const int32_t* idx, int m, int nsteps,
+                                 double scale, double shift, bool overlap, double* G,
+                                 hipStream_t st) {
+  if (m < 1 || m > kMaxRows || nsteps < 1 || nsteps > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(csr_gram_kernel, dim3(m, nsteps), dim3(kCsrThreads), 0, st, A.rowptr,
+                     A.colidx, A.vals, idx, m, (int64_t)m, nullptr, scale, shift,
+                     overlap ? 1 : 0, G, (int64_t)m * m, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_rowdot_rows(const CsrView& A, const int32_t* idx, int64_t m,
+                                  const double* v, double* out, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(csr_rowdot_kernel, dim3((unsigned)((m + kCsrWaves - 1) / kCsrWaves)),
+                     dim3(kCsrThreads), 0, st, A.rowptr, A.colidx, A.vals, idx, m, v, nullptr,
+                     0.0, out);
   return hipGetLastError();
 }
 
@@ -195,8 +247,8 @@ hipError_t launch_csr_rowdot(const CsrView& A, const double* v, const double* ba
                              double* out, hipStream_t st) {
   if (A.rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(csr_rowdot_kernel, dim3((unsigned)((A.rows + kCsrWaves - 1) / kCsrWaves)),
-                     dim3(kCsrThreads), 0, st, A.rowptr, A.colidx, A.vals, A.rows, v, base, beta,
-                     out);
+                     dim3(kCsrThreads), 0, st, A.rowptr, A.colidx, A.vals, nullptr, A.rows, v,
+                     base, beta, out);
   return hipGetLastError();
 }
 

@@ -183,6 +183,15 @@ hipError_t launch_csr_gram(const CsrView& A, const int32_t* idx, int m, const do
                            double scale, double shift, bool overlap, double* G, double* Yu,
                            hipStream_t st);
 // out[col] += gamma * v[p] * A[row(p)][col], row(p) = idx ? idx[p] : p (atomic adds).
+// The Grams of nsteps outer steps of m rows each in one launch (step k uses
+// idx + k m and writes G + k m^2; no Y u): the Gram depends on the indices only.
+hipError_t launch_csr_gram_steps(const CsrView& A, const int32_t* idx, int m, int nsteps,
+                                 double scale, double shift, bool overlap, double* G,
+                                 hipStream_t st);
+// out[p] = A[idx[p]] . v for p < m (the Y u of a step whose Gram came from
+// launch_csr_gram_steps).
+hipError_t launch_csr_rowdot_rows(const CsrView& A, const int32_t* idx, int64_t m,
+                                  const double* v, double* out, hipStream_t st);
 hipError_t launch_csr_scatter(const CsrView& A, const int32_t* idx, int64_t m, const double* v,
                               double gamma, double* out, hipStream_t st);
 // out[p] = A[p] . v + beta * base[p] for every row.

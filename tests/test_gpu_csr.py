@@ -131,3 +131,19 @@ def test_csr_malformed_is_rejected(gpu_lib):
                              0.1, 2, 2, 4, 0)
     # the good matrix still works afterwards
     gpu_lib.dual_bcd(good, y, 0.1, 2, 2, 4, 0)
+
+
+def test_csr_steps_cross_index_chunks(gpu_lib):
+    """More outer steps than one index chunk (4096): the Grams computed ahead
+    stop at the chunk boundary, and a ragged last step falls back to the
+    one-step Gram."""
+    _say("csr many steps")
+    S = _random_csr(60, 300, 0.05, 21, long_rows=(3,), empty_rows=(9,))
+    rng = np.random.default_rng(4)
+    y = rng.standard_normal(60)
+    XT = gpu_lib.CSR.from_scipy(S, DEV)
+    H = 2 * 4096 + 2 * 50 + 1         # s = 2: 4146 full outer steps, then a ragged one
+    a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), 1e-2, 2, 2, H, 13)
+    ao, wo = bcd.dual_bcd(S.T.tocsc(), y, 1e-2, 2, 2, H, 13)
+    assert _rel(a.cpu(), ao) <= 1e-10
+    assert _rel(w.cpu(), wo) <= 1e-10
