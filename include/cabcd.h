@@ -208,7 +208,9 @@ cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lam
  *   alpha  in: a_0, out: a_H (n)
  *   w      in (only with CABCD_FLAG_STATE_VALID): -X a_0/(lambda n);
  *          out: w_H maintained by the recurrence (d)
- * X^T may be dense F64 or CSR F64 (low-precision storage: CABCD_EUNSUPPORTED).
+ * X^T may be dense F64, dense BF16 / FP8 (mixed precision as for the primal:
+ * the Gram on the stored codes with FP32 accumulation, everything else in
+ * FP64 on the dequantised X^; one row scale per data point) or CSR F64.
  * 1 <= b <= min(n, 32), s >= 1, s*b <= 256 dense / 1024 CSR, H >= 0, lambda > 0.
  */
 cabcd_status cabcd_dual_bcd(const cabcd_matrix* XT, const double* y, double lambda,
@@ -241,7 +243,8 @@ cabcd_status cabcd_primal_objective(const cabcd_matrix* X, const double* y,
                                     double* f, void* stream);
 
 /*
- * Primal objective f(w) evaluated with A = X^T (n x d, the dual layout):
+ * Primal objective f(w) evaluated with A = X^T (n x d, the dual layout; any
+ * storage):
  * r = A w - y, *f = 1/(2n)||r||^2 + lambda/2 ||w||^2.  Outputs may be NULL.
  */
 cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y,
@@ -261,7 +264,7 @@ cabcd_status cabcd_primal_residual(const cabcd_matrix* X, double lambda, const d
 
 /*
  * Full dual residual of the stopping test (Section 5.1.5) with A = X^T (n x d,
- * dense F64 or CSR):
+ * dense F64 / BF16 / FP8 or CSR):
  *   rho = -X^T w + alpha + y   (n),   *norm = ||rho||_2 (device scalar)
  * for the given w (the maintained one, or -X alpha/(lambda n), which makes
  * rho = n grad D(alpha)).  Either output may be NULL, not both.
@@ -271,7 +274,8 @@ cabcd_status cabcd_dual_residual(const cabcd_matrix* XT, const double* y, const 
                                  const double* w, double* rho, double* norm, void* stream);
 
 /*
- * Primal-dual map (eq. 3) with A = X^T (n x d): w = -X a / (lambda n) (d).
+ * Primal-dual map (eq. 3) with A = X^T (n x d, any storage):
+ * w = -X a / (lambda n) (d).
  */
 cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha,
                                   double lambda, double* w, void* stream);

@@ -760,10 +760,6 @@ cabcd_status cabcd_dual_bcd(const cabcd_matrix* XT, const double* y, double lamb
   Mat M;
   cabcd_status e = check_matrix(XT, "XT", &M);
   if (e != CABCD_OK) return e;
-  if (M.lowp()) {
-    set_error("cabcd_dual_bcd: low-precision storage is supported by the primal only");
-    return CABCD_EUNSUPPORTED;
-  }
   e = check_common(M, lambda, b, s, H);
   if (e != CABCD_OK) return e;
   return run_bcd(true, M, y, lambda, b, s, H, seed, alpha, w, opts, (hipStream_t)stream);
@@ -800,10 +796,6 @@ cabcd_status cabcd_primal_objective_t(const cabcd_matrix* XT, const double* y, d
   Mat M;
   cabcd_status e = check_matrix(XT, "XT", &M);
   if (e != CABCD_OK) return e;
-  if (M.lowp()) {
-    set_error("cabcd_primal_objective_t: low-precision storage is not supported");
-    return CABCD_EUNSUPPORTED;
-  }
   if (y == nullptr || w == nullptr || !(lambda >= 0.0)) {
     set_error("cabcd_primal_objective_t: y and w must be non-NULL and lambda >= 0");
     return CABCD_EINVAL;
@@ -829,10 +821,6 @@ cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha, d
   Mat M;
   cabcd_status e = check_matrix(XT, "XT", &M);
   if (e != CABCD_OK) return e;
-  if (M.lowp()) {
-    set_error("cabcd_dual_to_primal: low-precision storage is not supported");
-    return CABCD_EUNSUPPORTED;
-  }
   if (alpha == nullptr || w == nullptr || !(lambda > 0.0)) {
     set_error("cabcd_dual_to_primal: alpha and w must be non-NULL and lambda > 0");
     return CABCD_EINVAL;
@@ -881,10 +869,6 @@ cabcd_status cabcd_dual_residual(const cabcd_matrix* XT, const double* y, const 
   Mat M;
   cabcd_status e = check_matrix(XT, "XT", &M);
   if (e != CABCD_OK) return e;
-  if (M.lowp()) {
-    set_error("cabcd_dual_residual: low-precision storage is not supported");
-    return CABCD_EUNSUPPORTED;
-  }
   if (y == nullptr || alpha == nullptr || w == nullptr || (rho == nullptr && norm == nullptr)) {
     set_error("cabcd_dual_residual: y, alpha and w must be non-NULL, and rho or norm requested");
     return CABCD_EINVAL;

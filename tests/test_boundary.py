@@ -188,5 +188,5 @@ def test_residual_entry_point_errors():
                                      None) == cabcd.EINVAL
     assert lib.cabcd_dual_residual(ctypes.byref(M), None, p, p, p, p, None) == cabcd.EINVAL
     assert lib.cabcd_dual_residual(ctypes.byref(M), p, p, p, None, None, None) == cabcd.EINVAL
-    M.dtype = cabcd.BF16
-    assert lib.cabcd_dual_residual(ctypes.byref(M), p, p, p, p, p, None) == cabcd.EUNSUPPORTED
+    M.dtype = 9                           # no such storage type
+    assert lib.cabcd_dual_residual(ctypes.byref(M), p, p, p, p, p, None) == cabcd.EINVAL
