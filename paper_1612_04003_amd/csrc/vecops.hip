@@ -47,8 +47,9 @@ struct GemvT {
 };
 
 // VEC: 16-byte loads of column pairs (A 16-byte aligned, even ld).  Eight rows
-// are loaded before their products are added, so each thread keeps eight
-// loads in flight.
+// at a time: their indices and coefficients (the same for every thread) are
+// fetched first, then the eight loads go out together with no branch between
+// them, so each thread keeps eight loads in flight (sixteen measured the same).
 template <bool VEC>
 __global__ __launch_bounds__(kVecThreads) void gemv_t_kernel(GemvT g) {
   constexpr int U = 8;
@@ -58,38 +59,46 @@ __global__ __launch_bounds__(kVecThreads) void gemv_t_kernel(GemvT g) {
   if (k >= g.cols) return;
   const bool two = k + 1 < g.cols;
   const bool vec = VEC && two;
-  const gptr<const double> A = glb(g.A);
-  const gptr<const double> v = glb(g.v);
+  const gptr<const double> A = glb(g.A) + k;
+  typedef double dv2 __attribute__((ext_vector_type(2)));
   double s0 = 0.0, s1 = 0.0;
   int64_t p = p0;
-  for (; p + U <= p1; p += U) {
-    double2 x[U];
-    double c[U];
+  // the row of entry p: idx[p] (gathered rows) or p; one loop per case keeps
+  // the loop body free of branches
+  auto batches = [&](auto row) {
+    for (; p + U <= p1; p += U) {
+      int64_t off[U];
+      double c[U];
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int64_t row = g.idx ? (int64_t)g.idx[p + q] : p + q;
-      const gptr<const double> a = A + row * g.ld + k;
-      c[q] = v[p + q];
+      for (int q = 0; q < U; ++q) {
+        off[q] = row(p + q) * g.ld;
+        c[q] = g.v[p + q];
+      }
+      dv2 x[U];
       if (vec) {
-        typedef double dv2 __attribute__((ext_vector_type(2)));
-        const dv2 t = *reinterpret_cast<gptr<const dv2>>(a);
-        x[q].x = t.x;
-        x[q].y = t.y;
+#pragma unroll
+        for (int q = 0; q < U; ++q) x[q] = *reinterpret_cast<gptr<const dv2>>(A + off[q]);
       } else {
-        x[q].x = a[0];
-        x[q].y = two ? a[1] : 0.0;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          x[q].x = A[off[q]];
+          x[q].y = two ? A[off[q] + 1] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        s0 = fma(x[q].x, c[q], s0);
+        s1 = fma(x[q].y, c[q], s1);
       }
     }
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      s0 = fma(x[q].x, c[q], s0);
-      s1 = fma(x[q].y, c[q], s1);
-    }
-  }
+  };
+  if (g.idx != nullptr)
+    batches([&](int64_t r) { return (int64_t)g.idx[r]; });
+  else
+    batches([&](int64_t r) { return r; });
   for (; p < p1; ++p) {
-    const int64_t row = g.idx ? (int64_t)g.idx[p] : p;
-    const gptr<const double> a = A + row * g.ld + k;
-    const double c = v[p];
+    const gptr<const double> a = A + (g.idx ? (int64_t)g.idx[p] : p) * g.ld;
+    const double c = g.v[p];
     s0 = fma(a[0], c, s0);
     if (two) s1 = fma(a[1], c, s1);
   }
