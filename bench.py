@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--batch-no-baseline", action="store_true",
                     help="batched record without the one-problem-at-a-time baseline")
     ap.add_argument("--only-tol", action="store_true", help="run only the mixed time-to-1e-6")
+    ap.add_argument("--no-stability", action="store_true",
+                    help="skip the numerical-stability record")
+    ap.add_argument("--only-stability", action="store_true",
+                    help="run only the headline and the numerical-stability record")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per Gram launch measured by rocprofv3 counters")
     return ap.parse_args()
@@ -189,19 +193,25 @@ def headline(args, cabcd, torch, synth):
 
 
 def extra_records(args, cabcd, torch, synth, X, y):
+    """Other shapes of the path (events bracket the Gram only, so the step
+    times carry no timing overhead); per_iteration_us = step time / s, the cost
+    of one b-coordinate iteration, shows what the s-step form saves."""
     rec = {}
+    gram_only = 1 << cabcd.PHASES.index("gram")
     d, n, lam = args.d, args.n, args.lam
     for s in (1, 4, 16):
         sb = s * args.b
-        el, ph = timed_primal(cabcd, torch, X, y, lam, args.b, s, 20, 2, 2001)
+        el, ph = timed_primal(cabcd, torch, X, y, lam, args.b, s, 20, 2, 2001, mask=gram_only)
         g = ph["gram"]["ms"] / 20   # Gram time per outer step
         rec[f"primal_s{s}"] = {"ms_per_step": round(el / 20 * 1e3, 4),
+                               "per_iteration_us": round(el / 20 / s * 1e6, 2),
                                "gram_ms": round(g, 4),
                                "gram_tflops": round(n * sb * (sb + 1) / (g * 1e-3) / 1e12, 3),
                                "gram_gbs": round(sb * n * 8 / (g * 1e-3) / 1e9, 1)}
         log(f"primal s={s}: {rec[f'primal_s{s}']}")
     XT = X.t().contiguous()
-    el, ph = timed_primal(cabcd, torch, XT, y, lam, args.b, args.s, 20, 2, 2001, dual=True)
+    el, ph = timed_primal(cabcd, torch, XT, y, lam, args.b, args.s, 20, 2, 2001, dual=True,
+                          mask=gram_only)
     g = ph["gram"]["ms"] / 20
     sb = args.s * args.b
     rec["dual_s32"] = {"ms_per_step": round(el / 20 * 1e3, 4), "gram_ms": round(g, 4),
@@ -217,7 +227,8 @@ def extra_records(args, cabcd, torch, synth, X, y):
     yd = torch.tensor(ys, device="cuda")
     for s in (1, 8, 32):
         b = 16
-        el, ph = timed_primal(cabcd, torch, A, yd, 1e-5, b, s, 20, 2, 2002, dual=True)
+        el, ph = timed_primal(cabcd, torch, A, yd, 1e-5, b, s, 20, 2, 2002, dual=True,
+                              mask=gram_only)
         # per outer step: the Grams of several future steps come from one launch,
         # the Y u of each step from its own
         g = ph["gram"]["ms"] / 20
@@ -464,6 +475,79 @@ def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, chea
     return res
 
 
+def stability(cabcd, torch, X, y, lam, b=8, H=4096, seed=2005):
+    """Numerical stability (Section 6) on the synthetic stand-in: the same
+    block sequence run with s = 1 ... 32 must give the same iterates up to
+    rounding (CA-BCD reproduces BCD in exact arithmetic), in FP64 and on BF16
+    storage; and the condition numbers of the s-step Gram G and of its b x b
+    diagonal blocks (the matrices actually factorised) over sampled outer
+    steps, for the primal (rows of X) and the dual (columns of X)."""
+    import numpy as np
+    d, n = X.shape
+    log("stability: closed-form optimum")
+    M = X @ X.T
+    M /= n
+    M.diagonal().add_(lam)
+    L = torch.linalg.cholesky(M)
+    wst = torch.cholesky_solve(((X @ y) / n)[:, None], L)[:, 0]
+    del M, L
+    fst = cabcd.primal_objective(X, y, lam, wst)[0].item()
+    res = {"workload": f"the headline matrix (d={d}, n={n}, spectrum 1..1e3, lambda={lam:g}), "
+                       f"b={b}, H={H} iterations from w=0 with one block sequence",
+           "H": H, "b": b}
+    for name in ("f64", "bf16"):
+        A, fs = X, fst
+        if name == "bf16":
+            A = cabcd.quantize(X, cabcd.BF16)
+            Xh = A.dequantize()
+            M = Xh @ Xh.T
+            M /= n
+            M.diagonal().add_(lam)
+            L = torch.linalg.cholesky(M)
+            wh = torch.cholesky_solve(((Xh @ y) / n)[:, None], L)[:, 0]
+            fs = cabcd.primal_objective(Xh, y, lam, wh)[0].item()
+            del Xh, M, L, wh
+        rec, w1 = {}, None
+        for s_ in (1, 2, 4, 8, 16, 32):
+            w, _ = cabcd.primal_bcd(A, y, lam, b, s_, H, seed)
+            f = cabcd.primal_objective(A, y, lam, w)[0].item()
+            if w1 is None:
+                w1 = w.clone()
+            rec[f"s{s_}"] = {"rel_obj_err": (f - fs) / fs,
+                             "w_rel_diff_vs_s1": (torch.linalg.norm(w - w1) /
+                                                  torch.linalg.norm(w1)).item()}
+        res[name] = rec
+        log(f"stability {name}: {rec}")
+        del A
+    torch.cuda.empty_cache()
+
+    def conds(gram_of_step, steps, s_, bb):
+        cg, cb = [], []
+        for k in range(steps):
+            G = gram_of_step(k).cpu().numpy()
+            cg.append(float(np.linalg.cond(G)))
+            cb.append(max(float(np.linalg.cond(G[j * bb:(j + 1) * bb, j * bb:(j + 1) * bb]))
+                          for j in range(s_)))
+        return {"G_median": float(np.median(cg)), "G_max": max(cg),
+                "diag_block_median": float(np.median(cb)), "diag_block_max": max(cb)}
+
+    cond = {}
+    for s_ in (8, 32):
+        idx = cabcd.sample(seed, 0, 16 * s_, b, d).reshape(16, s_ * b)
+        cond[f"primal_s{s_}"] = conds(
+            lambda k: cabcd.gram(X, idx[k].contiguous(), 1.0 / n, lam)[0], 16, s_, b)
+        jdx = cabcd.sample(seed, 0, 16 * s_, b, n).reshape(16, s_ * b).long()
+        ar = torch.arange(s_ * b, dtype=torch.int32, device=X.device)
+
+        def dual_gram(k):
+            Y = X[:, jdx[k]].t().contiguous()   # the sampled data points (rows of X^T)
+            return cabcd.gram(Y, ar, 1.0 / (lam * n * n), 1.0 / n)[0]
+        cond[f"dual_s{s_}"] = conds(dual_gram, 16, s_, b)
+    res["cond"] = cond
+    log(f"stability cond: {cond}")
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -489,6 +573,9 @@ def main():
         print(json.dumps({"time_to_tol": time_to_tol(cabcd, torch, synth)}), flush=True)
         return
     out, X, y = headline(args, cabcd, torch, synth)
+    if args.only_stability:
+        print(json.dumps({"stability": stability(cabcd, torch, X, y, args.lam)}), flush=True)
+        return
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(X, y, args.lam, args.b, args.s, args.cpu_steps, 2001)
@@ -496,6 +583,8 @@ def main():
         out["cpu_baseline"] = None
     if not args.no_extra:
         out["extra"] = extra_records(args, cabcd, torch, synth, X, y)
+    if not args.no_stability:
+        out["stability"] = stability(cabcd, torch, X, y, args.lam)
     del X, y
     torch.cuda.empty_cache()
     if not args.no_tol:
