@@ -36,7 +36,9 @@ namespace {
 constexpr int kMaxSBDense = 256;            // s*b of one dense FP64 Gram launch
 constexpr int64_t kIdxChunkSteps = 4096;    // outer steps whose indices are drawn at once
 constexpr int kCsrAhead = 64;               // CSR: outer-step Grams computed per launch (max)
-constexpr int64_t kCsrAheadDoubles = (int64_t)8 << 20;   // their buffer (64 MiB at most)
+constexpr int kDenseAhead = 32;             // dense: the same, when one Gram is too small
+constexpr int kDenseFill = 512;             // workgroups that fill the GPU (two per CU)
+constexpr int64_t kAheadDoubles = (int64_t)8 << 20;   // their buffers (64 MiB at most)
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
 
@@ -230,7 +232,17 @@ size_t mat_scratch_doubles(const Mat& M, int64_t sb) {
   if (M.csr) return 1;
   size_t sc = std::max(gemv_t_scratch_doubles(sb, M.cols), gemv_t_scratch_doubles(M.rows, M.cols));
   sc = std::max(sc, rowdot_scratch_doubles(M.rows, M.cols, M.dtype));
+  sc = std::max(sc, rowdot_scratch_doubles(sb, M.cols, M.dtype));
   return std::max<size_t>(sc, 1);
+}
+
+// out[p] = A[idx[p]] . u for p < m (row scales applied): the Y u of a step
+// whose Gram was computed ahead.
+hipError_t mat_rows_dot(const Mat& M, const int32_t* idx, int m, const double* u, double* out,
+                        double* scratch, hipStream_t st) {
+  if (M.csr) return launch_csr_rowdot_rows(M.C, idx, m, u, out, st);
+  return launch_rowdot_rows(M.dtype, M.lowp() ? M.Q : static_cast<const void*>(M.X), M.ld, idx,
+                            m, M.cols, M.rs, u, out, scratch, st);
 }
 
 // The full residual of the stopping test (Section 5.1.5) and its 2-norm
@@ -368,12 +380,43 @@ hipError_t mat_gram(const Mat& M, const int32_t* idx, int m, const double* u, do
   return timer ? timer->run(CABCD_PHASE_REDUCE, r) : r();
 }
 
-// Gram slots of the step buffers: CSR computes the Grams of several future
-// outer steps per launch (its per-step Gram is a latency-bound walk with too
-// little work to fill the GPU); dense computes one per step.
+// Gram slots of the step buffers: the Grams of several future outer steps are
+// computed in one launch (they depend on the sampled indices only) when one
+// step's Gram cannot fill the GPU: always for CSR (a latency-bound walk per
+// row), and for dense rows too short to give the split-K Gram enough slabs.
 int gram_slots(const Mat& M, int64_t sb) {
-  if (!M.csr) return 1;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kCsrAhead, kCsrAheadDoubles / (sb * sb)));
+  if (M.csr)
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kCsrAhead, kAheadDoubles / (sb * sb)));
+  const GramPlan p = plan_for(M, (int)sb);
+  if (p.nsplit >= kDenseFill) return 1;
+  const int64_t per = (int64_t)gram_partial_doubles(p) + sb * sb;   // partials and G
+  int64_t k = (kDenseFill + p.nsplit - 1) / p.nsplit;
+  k = std::min<int64_t>(k, kDenseAhead);
+  k = std::min<int64_t>(k, kAheadDoubles / per);
+  return (int)std::max<int64_t>(k, 1);
+}
+
+// The Grams of nsteps full outer steps (indices idx + k m for step k) into G +
+// k m^2, without Y u.
+hipError_t mat_gram_steps(const Mat& M, const int32_t* idx, int m, int nsteps, double scale,
+                          double shift, double* G, double* partials, hipStream_t st,
+                          PhaseTimer* timer) {
+  if (M.csr)
+    return timer->run(CABCD_PHASE_GRAM, [&] {
+      return launch_csr_gram_steps(M.C, idx, m, nsteps, scale, shift, true, G, st);
+    });
+  const GramPlan plan = plan_for(M, m);
+  hipError_t e = timer->run(CABCD_PHASE_GRAM, [&] {
+    return M.lowp() ? launch_gram_lp(plan, M.dtype, M.Q, M.ld, M.cols, idx, m, nullptr, partials,
+                                     st, nsteps)
+                    : launch_gram_f64(plan, M.X, M.ld, M.cols, idx, m, nullptr, partials, st,
+                                      nsteps);
+  });
+  if (e != hipSuccess) return e;
+  return timer->run(CABCD_PHASE_REDUCE, [&] {
+    return launch_gram_reduce(plan, partials, idx, m, scale, shift, true, G, nullptr, st,
+                              M.lowp() ? 1 : 0, M.lowp() ? M.rs : nullptr, nsteps);
+  });
 }
 
 struct StepBuffers {
@@ -399,7 +442,10 @@ size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp
   B.G = c.take<double>((size_t)gram_slots(M, sb) * sb * sb);
   B.Yu = c.take<double>(sb);
   B.delta = c.take<double>(sb);
-  B.partials = c.take<double>(max_partials(M, sb));
+  const int slots = gram_slots(M, sb);
+  B.partials = c.take<double>(std::max(
+      max_partials(M, sb),
+      M.csr || slots == 1 ? (size_t)0 : (size_t)slots * gram_partial_doubles(plan_for(M, sb))));
   B.scratch = c.take<double>(mat_scratch_doubles(M, sb));
   B.obj = c.take<double>(objective_scratch_doubles(0, 0));
   B.rtmp = c.take<double>(std::max<int64_t>(rtmp_len, 1));
@@ -554,7 +600,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   if (!(o.flags & CABCD_FLAG_STATE_VALID))
     HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
 
-  const int K = gram_slots(M, (int64_t)s * b);   // CSR Grams per launch
+  const int K = gram_slots(M, (int64_t)s * b);   // Grams per launch (computed ahead)
   int ahead = 0, gslot = 0;                       // precomputed Grams left, next slot
   int64_t h = 0, k = 0, slot = 0;
   int64_t chunk_begin = -1, chunk_end = -1;
@@ -583,9 +629,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
         int64_t avail = (H - h) / s;
         if (o.explicit_idx == nullptr) avail = std::min(avail, (chunk_end - h) / s);
         const int nst = (int)std::min<int64_t>(K, std::max<int64_t>(avail, 1));
-        HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
-          return launch_csr_gram_steps(M.C, idx, m, nst, scale, shift, true, B.G, st);
-        }));
+        HIP_TRY(mat_gram_steps(M, idx, m, nst, scale, shift, B.G, B.partials, st, &timer));
         ahead = nst;
         gslot = 0;
       }
@@ -593,7 +637,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       ++gslot;
       --ahead;
       HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
-        return launch_csr_rowdot_rows(M.C, idx, m, comp, B.Yu, st);
+        return mat_rows_dot(M, idx, m, comp, B.Yu, B.scratch, st);
       }));
     } else {
       HIP_TRY(

@@ -12,13 +12,17 @@ namespace {
 
 using namespace gdev;
 
+// Several outer steps per launch: step blockIdx.y reads idx + step * m and
+// writes its partials at partials + step * pstride (u is NULL then).
 template <int NB, int RPW>
 __global__ __launch_bounds__((Cfg<NB, RPW>::THREADS)) void gram_f64_kernel(
     const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
     int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
-    int aligned) {
+    int64_t pstride, int aligned) {
   using C = Cfg<NB, RPW>;
   __shared__ __attribute__((aligned(16))) double lds[C::LDS];
+  idx += (int64_t)blockIdx.y * m;
+  partials += (int64_t)blockIdx.y * pstride;
   const int64_t k_begin = (int64_t)blockIdx.x * chunk;
   const int64_t k_end = std::min(cols, k_begin + chunk);
   gram_slab<NB, RPW>(A, ld, k_begin, k_end, idx, m, u,
@@ -27,8 +31,11 @@ __global__ __launch_bounds__((Cfg<NB, RPW>::THREADS)) void gram_f64_kernel(
 
 __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
     const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
-    int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials) {
+    int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
+    int64_t pstride) {
   __shared__ __attribute__((aligned(16))) double lds[D16::LDS];
+  idx += (int64_t)blockIdx.y * m;
+  partials += (int64_t)blockIdx.y * pstride;
   const int64_t k_begin = (int64_t)blockIdx.x * chunk;
   const int64_t k_end = std::min(cols, k_begin + chunk);
   gram_slab_dma16(A, ld, k_begin, k_end, idx, m, u,
@@ -38,6 +45,8 @@ __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
 constexpr int kRedElems = 64;    // partial entries per reduction workgroup
 constexpr int kRedGroups = 4;    // split groups per entry (one wave each)
 
+// Step blockIdx.y: partials + step * nsplit * pstride, idx + step * m,
+// G + step * m * m (Yu is NULL for several steps).
 __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
     const double* __restrict__ partials, int nsplit, int nb, const int32_t* __restrict__ idx,
     int m, double scale, double shift, int overlap, double* __restrict__ G,
@@ -45,6 +54,9 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
   __shared__ double red[kRedGroups][kRedElems];
   const int nblk = nb * (nb + 1) / 2;
   const int64_t pstride = (int64_t)nblk * 256 + 16 * nb;
+  partials += (int64_t)blockIdx.y * nsplit * pstride;
+  idx += (int64_t)blockIdx.y * m;
+  G += (int64_t)blockIdx.y * m * m;
   const int el = threadIdx.x % kRedElems;
   const int grp = threadIdx.x / kRedElems;
   const int64_t e = (int64_t)blockIdx.x * kRedElems + el;
@@ -77,18 +89,20 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
 
 template <int NB, int RPW>
 hipError_t launch_nb(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
-                     const int32_t* idx, int m, const double* u, double* partials,
+                     const int32_t* idx, int m, int nsteps, const double* u, double* partials,
                      hipStream_t st) {
   const int aligned = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (ld & 1) == 0) ? 1 : 0;
+  const int64_t pstride = (int64_t)gram_partial_doubles(p);
+  const dim3 grid((unsigned)p.nsplit, (unsigned)nsteps);
   if constexpr (NB == 16) {
     if (p.rpw == 1 && aligned) {
-      hipLaunchKernelGGL(gram_f64_dma16_kernel, dim3(p.nsplit), dim3(D16::THREADS), 0, st, A, ld,
-                         cols, idx, m, u, p.chunk, partials);
+      hipLaunchKernelGGL(gram_f64_dma16_kernel, grid, dim3(D16::THREADS), 0, st, A, ld, cols, idx,
+                         m, u, p.chunk, partials, pstride);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((gram_f64_kernel<NB, RPW>), dim3(p.nsplit), dim3(Cfg<NB, RPW>::THREADS), 0,
-                     st, A, ld, cols, idx, m, u, p.chunk, partials, aligned);
+  hipLaunchKernelGGL((gram_f64_kernel<NB, RPW>), grid, dim3(Cfg<NB, RPW>::THREADS), 0, st, A, ld,
+                     cols, idx, m, u, p.chunk, partials, pstride, aligned);
   return hipGetLastError();
 }
 
@@ -158,25 +172,28 @@ size_t gram_partial_doubles(const GramPlan& p) {
 
 hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
                            const int32_t* idx, int m, const double* u, double* partials,
-                           hipStream_t st) {
+                           hipStream_t st, int nsteps) {
+  if (nsteps < 1 || nsteps > 65535 || (nsteps > 1 && u != nullptr)) return hipErrorInvalidValue;
   switch (p.nb) {
-    case 1: return launch_nb<1, 2>(p, A, ld, cols, idx, m, u, partials, st);
-    case 2: return launch_nb<2, 2>(p, A, ld, cols, idx, m, u, partials, st);
-    case 4: return launch_nb<4, 2>(p, A, ld, cols, idx, m, u, partials, st);
-    case 8: return launch_nb<8, 2>(p, A, ld, cols, idx, m, u, partials, st);
-    case 16: return launch_nb<16, 2>(p, A, ld, cols, idx, m, u, partials, st);
+    case 1: return launch_nb<1, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 2: return launch_nb<2, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 4: return launch_nb<4, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 8: return launch_nb<8, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 16: return launch_nb<16, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const int32_t* idx,
                               int m, double scale, double shift, bool overlap, double* G,
-                              double* Yu, hipStream_t st, int layout, const float* rs) {
+                              double* Yu, hipStream_t st, int layout, const float* rs,
+                              int nsteps) {
+  if (nsteps < 1 || nsteps > 65535 || (nsteps > 1 && Yu != nullptr)) return hipErrorInvalidValue;
   const int64_t entries = (int64_t)p.nblk * 256 + 16 * p.nb;
   const int64_t blocks = (entries + kRedElems - 1) / kRedElems;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks), dim3(kRedElems * kRedGroups), 0,
-                     st, partials, p.nsplit, p.nb, idx, m, scale, shift, overlap ? 1 : 0, G, Yu,
-                     layout, rs);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks, (unsigned)nsteps),
+                     dim3(kRedElems * kRedGroups), 0, st, partials, p.nsplit, p.nb, idx, m, scale,
+                     shift, overlap ? 1 : 0, G, Yu, layout, rs);
   return hipGetLastError();
 }
 

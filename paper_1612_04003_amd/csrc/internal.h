@@ -115,19 +115,23 @@ struct GramPlan {
 GramPlan plan_gram_f64(int m, int64_t cols);
 size_t gram_partial_doubles(const GramPlan& p);   // partial G + partial Yu
 // partials: nsplit * (nblk*256 + 16*nb) doubles.
+// nsteps > 1: the Grams of nsteps outer steps in one launch (step k reads
+// idx + k m, writes partials + k gram_partial_doubles(p); u must be NULL).
 hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
                            const int32_t* idx, int m, const double* u, double* partials,
-                           hipStream_t st);
+                           hipStream_t st, int nsteps = 1);
 // G (m x m, ld m, both triangles) = scale * sum(partials) + shift * E,
 // E = I (overlap = false) or E_pq = [idx_p == idx_q] (overlap = true).
 // Yu (may be NULL) = sum of the partial Yu.
 // layout 0: partial block entries in the FP64 MFMA output order; 1: in the FP32
 // MFMA output order.  rs (may be NULL) are row scales of A applied as
 // rs[idx_p] rs[idx_q] to G and rs[idx_p] to Y u.
+// nsteps > 1: step k reduces partials + k gram_partial_doubles(p) into
+// G + k m^2 (Yu must be NULL).
 hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const int32_t* idx,
                               int m, double scale, double shift, bool overlap, double* G,
                               double* Yu, hipStream_t st, int layout = 0,
-                              const float* rs = nullptr);
+                              const float* rs = nullptr, int nsteps = 1);
 
 // ------------------------------------------------------------------ fused solve
 // One outer step's s block solves through the unrolled recurrence, followed by
@@ -163,7 +167,7 @@ GramPlan plan_gram_lp(int m, int64_t cols, int dtype);
 // partial blocks use the FP32 MFMA output layout) plus Y u of the codes in FP64.
 hipError_t launch_gram_lp(const GramPlan& p, int dtype, const void* A, int64_t ld, int64_t cols,
                           const int32_t* idx, int m, const double* u, double* partials,
-                          hipStream_t st);
+                          hipStream_t st, int nsteps = 1);
 // out = [beta base | out] + gamma sum_p s[row(p)] v[p] decode(Q[row(p)]), FP64.
 hipError_t launch_gemv_t_lp(int dtype, const void* A, int64_t ld, int64_t cols, const float* rs,
                             const int32_t* idx, int64_t m, const double* v, double gamma,
@@ -219,6 +223,10 @@ size_t rowdot_scratch_doubles(int64_t rows, int64_t cols, int dtype);
 hipError_t launch_rowdot(int dtype, const void* A, int64_t ld, int64_t rows, int64_t cols,
                          const float* rs, const double* v, const double* base, double beta,
                          double* out, double* scratch, hipStream_t st);
+// The same for the gathered rows idx[0..m): out[p] = s_row A[idx[p]] . v.
+hipError_t launch_rowdot_rows(int dtype, const void* A, int64_t ld, const int32_t* idx,
+                              int64_t m, int64_t cols, const float* rs, const double* v,
+                              double* out, double* scratch, hipStream_t st);
 // t = ca a + cb b (b may be NULL), written to vec when non-NULL, and *norm =
 // ||t||_2 (device scalar); scratch holds objective_scratch_doubles() doubles;
 // a non-finite norm sets the status word (status may be NULL).  Deterministic.

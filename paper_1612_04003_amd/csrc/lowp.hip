@@ -87,9 +87,11 @@ template <int NB, int FMT>
 __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
     const uint8_t* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
     int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
-    int aligned) {
+    int64_t pstride, int aligned) {
   using C = LpCfg<NB, FMT>;
   __shared__ __attribute__((aligned(16))) uint8_t lds[C::LDS];
+  idx += (int64_t)blockIdx.y * m;            // several outer steps per launch
+  partials += (int64_t)blockIdx.y * pstride;
   const int64_t k_begin = (int64_t)blockIdx.x * chunk;
   const int64_t k_end = std::min(cols, k_begin + chunk);
   gram_lp_slab<NB, FMT>(A, ld, k_begin, k_end, idx, m, u,
@@ -98,27 +100,27 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
 
 template <int NB, int FMT>
 hipError_t launch_lp_nb(const GramPlan& p, const void* A, int64_t ld, int64_t cols,
-                        const int32_t* idx, int m, const double* u, double* partials,
-                        hipStream_t st) {
+                        const int32_t* idx, int m, int nsteps, const double* u,
+                        double* partials, hipStream_t st) {
   using C = LpCfg<NB, FMT>;
   const int aligned =
       ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && ((ld * C::ES) & 15) == 0) ? 1 : 0;
-  hipLaunchKernelGGL((gram_lp_kernel<NB, FMT>), dim3(p.nsplit), dim3(kLpThreads), 0, st,
-                     static_cast<const uint8_t*>(A), ld, cols, idx, m, u, p.chunk, partials,
-                     aligned);
+  hipLaunchKernelGGL((gram_lp_kernel<NB, FMT>), dim3((unsigned)p.nsplit, (unsigned)nsteps),
+                     dim3(kLpThreads), 0, st, static_cast<const uint8_t*>(A), ld, cols, idx, m, u,
+                     p.chunk, partials, (int64_t)gram_partial_doubles(p), aligned);
   return hipGetLastError();
 }
 
 template <int FMT>
 hipError_t launch_lp_fmt(const GramPlan& p, const void* A, int64_t ld, int64_t cols,
-                         const int32_t* idx, int m, const double* u, double* partials,
-                         hipStream_t st) {
+                         const int32_t* idx, int m, int nsteps, const double* u,
+                         double* partials, hipStream_t st) {
   switch (p.nb) {
-    case 1: return launch_lp_nb<1, FMT>(p, A, ld, cols, idx, m, u, partials, st);
-    case 2: return launch_lp_nb<2, FMT>(p, A, ld, cols, idx, m, u, partials, st);
-    case 4: return launch_lp_nb<4, FMT>(p, A, ld, cols, idx, m, u, partials, st);
-    case 8: return launch_lp_nb<8, FMT>(p, A, ld, cols, idx, m, u, partials, st);
-    case 16: return launch_lp_nb<16, FMT>(p, A, ld, cols, idx, m, u, partials, st);
+    case 1: return launch_lp_nb<1, FMT>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 2: return launch_lp_nb<2, FMT>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 4: return launch_lp_nb<4, FMT>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 8: return launch_lp_nb<8, FMT>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+    case 16: return launch_lp_nb<16, FMT>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -199,10 +201,11 @@ GramPlan plan_gram_lp(int m, int64_t cols, int dtype) {
 
 hipError_t launch_gram_lp(const GramPlan& p, int dtype, const void* A, int64_t ld, int64_t cols,
                           const int32_t* idx, int m, const double* u, double* partials,
-                          hipStream_t st) {
+                          hipStream_t st, int nsteps) {
+  if (nsteps < 1 || nsteps > 65535 || (nsteps > 1 && u != nullptr)) return hipErrorInvalidValue;
   if (dtype == CABCD_BF16)
-    return launch_lp_fmt<CABCD_BF16>(p, A, ld, cols, idx, m, u, partials, st);
-  return launch_lp_fmt<CABCD_FP8_E4M3>(p, A, ld, cols, idx, m, u, partials, st);
+    return launch_lp_fmt<CABCD_BF16>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+  return launch_lp_fmt<CABCD_FP8_E4M3>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
 }
 
 hipError_t launch_gemv_t_lp(int dtype, const void* A, int64_t ld, int64_t cols, const float* rs,

@@ -144,6 +144,7 @@ constexpr int64_t kRowPartBytes = 64 * 1024;
 struct RowDot {
   const uint8_t* A;
   int64_t ld;          // elements
+  const int32_t* idx;  // gathered rows (row p is idx[p]) or NULL
   int64_t rows, cols;
   const float* rs;     // low precision: row scales (NULL = 1)
   const double* v;
@@ -170,7 +171,8 @@ __global__ __launch_bounds__(kVecThreads) void rowdot_kernel(RowDot g) {
   const int q = (int)(wv - p * g.parts);
   const int64_t k0 = (int64_t)q * g.chunk;
   const int64_t k1 = std::min(g.cols, k0 + g.chunk);
-  const gptr<const uint8_t> row = glb(g.A) + p * g.ld * ES;
+  const int64_t ar = g.idx ? (int64_t)g.idx[p] : p;   // row of A
+  const gptr<const uint8_t> row = glb(g.A) + ar * g.ld * ES;
   const gptr<const double> v = glb(g.v);
   typedef double dv2 __attribute__((ext_vector_type(2)));
   double acc = 0.0;
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(kVecThreads) void rowdot_kernel(RowDot g) {
     g.part[p * g.parts + q] = acc;
     return;
   }
-  const double sc = g.rs ? (double)g.rs[p] : 1.0;
+  const double sc = g.rs ? (double)g.rs[ar] : 1.0;
   g.out[p] = sc * acc + (g.base ? g.beta * g.base[p] : 0.0);
 }
 
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(kVecThreads) void rowdot_combine_kernel(RowDot g) {
   if (p >= g.rows) return;
   double acc = 0.0;
   for (int q = 0; q < g.parts; ++q) acc += g.part[p * g.parts + q];
-  const double sc = g.rs ? (double)g.rs[p] : 1.0;
+  const double sc = g.rs ? (double)g.rs[g.idx ? (int64_t)g.idx[p] : p] : 1.0;
   g.out[p] = sc * acc + (g.base ? g.beta * g.base[p] : 0.0);
 }
 
@@ -357,14 +359,34 @@ size_t rowdot_scratch_doubles(int64_t rows, int64_t cols, int dtype) {
   return parts > 1 ? (size_t)parts * (size_t)rows : 0;
 }
 
+static hipError_t launch_rowdot_any(int dtype, const void* A, int64_t ld, const int32_t* idx,
+                                    int64_t rows, int64_t cols, const float* rs,
+                                    const double* v, const double* base, double beta,
+                                    double* out, double* scratch, hipStream_t st);
+
 hipError_t launch_rowdot(int dtype, const void* A, int64_t ld, int64_t rows, int64_t cols,
                          const float* rs, const double* v, const double* base, double beta,
                          double* out, double* scratch, hipStream_t st) {
+  return launch_rowdot_any(dtype, A, ld, nullptr, rows, cols, rs, v, base, beta, out, scratch,
+                           st);
+}
+
+hipError_t launch_rowdot_rows(int dtype, const void* A, int64_t ld, const int32_t* idx,
+                              int64_t m, int64_t cols, const float* rs, const double* v,
+                              double* out, double* scratch, hipStream_t st) {
+  return launch_rowdot_any(dtype, A, ld, idx, m, cols, rs, v, nullptr, 0.0, out, scratch, st);
+}
+
+static hipError_t launch_rowdot_any(int dtype, const void* A, int64_t ld, const int32_t* idx,
+                                    int64_t rows, int64_t cols, const float* rs,
+                                    const double* v, const double* base, double beta,
+                                    double* out, double* scratch, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   const int es = dtype == CABCD_F64 ? 8 : (dtype == CABCD_BF16 ? 2 : 1);
   RowDot g{};
   g.A = static_cast<const uint8_t*>(A);
   g.ld = ld;
+  g.idx = idx;
   g.rows = rows;
   g.cols = cols;
   g.rs = dtype == CABCD_F64 ? nullptr : rs;
