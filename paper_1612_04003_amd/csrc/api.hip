@@ -38,6 +38,7 @@ constexpr int64_t kIdxChunkSteps = 4096;    // outer steps whose indices are dra
 constexpr int kCsrAhead = 64;               // CSR: outer-step Grams computed per launch (max)
 constexpr int kDenseAhead = 32;             // dense: the same, when one Gram is too small
 constexpr int kDenseFill = 512;             // workgroups that fill the GPU (two per CU)
+constexpr int64_t kAheadRowBytes = 8 << 20; // dense: gathered rows small enough to read twice
 constexpr int64_t kAheadDoubles = (int64_t)8 << 20;   // their buffers (64 MiB at most)
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
@@ -384,9 +385,13 @@ hipError_t mat_gram(const Mat& M, const int32_t* idx, int m, const double* u, do
 // computed in one launch (they depend on the sampled indices only) when one
 // step's Gram cannot fill the GPU: always for CSR (a latency-bound walk per
 // row), and for dense rows too short to give the split-K Gram enough slabs.
+// Y u then takes a second pass over the gathered rows, so dense look-ahead is
+// kept to gathered rows of a few MiB.
 int gram_slots(const Mat& M, int64_t sb) {
   if (M.csr)
     return (int)std::max<int64_t>(1, std::min<int64_t>(kCsrAhead, kAheadDoubles / (sb * sb)));
+  const int64_t elem = M.dtype == CABCD_F64 ? 8 : (M.dtype == CABCD_BF16 ? 2 : 1);
+  if (sb * M.cols * elem > kAheadRowBytes) return 1;
   const GramPlan p = plan_for(M, (int)sb);
   if (p.nsplit >= kDenseFill) return 1;
   const int64_t per = (int64_t)gram_partial_doubles(p) + sb * sb;   // partials and G

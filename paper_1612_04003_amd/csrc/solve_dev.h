@@ -16,12 +16,13 @@
 // Phases (one workgroup; thread p owns row p of the outer step):
 //  1. c, and the diagonal blocks of Gov gathered into LDS by the whole
 //     workgroup (one memory round trip);
-//  2. every diagonal block inverted by one wave with in-place Gauss-Jordan
-//     elimination, the block's entries spread over the lanes and exchanged by
-//     shuffles (no LDS round trips, no barriers).  Blocks are padded to
-//     BP = 2^k >= b with the identity, whose inverse keeps the padding.  On an
-//     SPD matrix the Gauss-Jordan pivots are the LDL^T pivots, so a pivot <= 0
-//     or NaN is reported as "not positive definite";
+//  2. every diagonal block inverted with in-place Gauss-Jordan elimination:
+//     blocks up to 8 x 8 one per lane in registers, larger ones by one wave
+//     with the entries spread over the lanes and exchanged by shuffles (no
+//     LDS round trips, no barriers).  Blocks are padded to BP = 2^k >= b with
+//     the identity, whose inverse keeps the padding.  On an SPD matrix the
+//     Gauss-Jordan pivots are the LDL^T pivots, so a pivot <= 0 or NaN is
+//     reported as "not positive definite";
 //  3. the dependent chain over j: delta_j = Gamma_j^{-1} rhs_j, then every later
 //     row subtracts its Gov row segment times delta_j.  Row segments of the
 //     next PF blocks are prefetched into registers; the barriers order LDS
@@ -51,6 +52,8 @@ template <int BP>
 struct SolveCfg {
   static constexpr int EPL = BP * BP > 64 ? BP * BP / 64 : 1;   // block entries per lane
   static constexpr int SPW = BP * BP < 64 ? 64 / (BP * BP) : 1; // blocks per wave
+  static constexpr int GS = BP * BP + 1;   // LDS stride of the blocks (odd: no bank conflicts
+                                           // when each lane reads its own block)
 };
 
 // In-place Gauss-Jordan inversion of the SPW blocks held by one wave.
@@ -104,6 +107,80 @@ __device__ __forceinline__ unsigned hash_idx(int i, int slots) {
   return ((unsigned)i * 2654435761u) & (unsigned)(slots - 1);
 }
 
+// x of lane l (l the same in every lane) in every lane.
+__device__ __forceinline__ double read_lane(double x, int l) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)bits, l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __hiloint2double(hi, lo);
+}
+
+// The s diagonal blocks held in Gi inverted one per lane (thread j takes block
+// j), each in registers with the Gauss-Jordan steps of gj_invert, so the
+// results are the same; with no shuffles the cost is one block's arithmetic.
+template <int BP, int THREADS>
+__device__ __forceinline__ void invert_per_lane(double* Gi, int s, int tid, bool& bad) {
+  using C = SolveCfg<BP>;
+  for (int j = tid; j < s; j += THREADS) {
+    double* g = Gi + (size_t)j * C::GS;
+    double e[BP][BP];
+#pragma unroll
+    for (int u = 0; u < BP; ++u)
+#pragma unroll
+      for (int v = 0; v < BP; ++v) e[u][v] = g[u * BP + v];
+#pragma unroll
+    for (int k = 0; k < BP; ++k) {
+      const double piv = e[k][k];
+      bad |= !(piv > 0.0);
+      const double rp = 1.0 / piv;
+#pragma unroll
+      for (int v = 0; v < BP; ++v) e[k][v] = (v == k ? 1.0 : e[k][v]) * rp;
+#pragma unroll
+      for (int u = 0; u < BP; ++u) {
+        if (u == k) continue;
+        const double f = e[u][k];
+#pragma unroll
+        for (int v = 0; v < BP; ++v) e[u][v] = (v == k ? 0.0 : e[u][v]) - f * e[k][v];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BP; ++u)
+#pragma unroll
+      for (int v = 0; v < BP; ++v) g[u * BP + v] = e[u][v];
+  }
+}
+
+// Inverts the s diagonal blocks held in Gi ([s][BP][BP], padded with the
+// identity) in place: wave w takes blocks w SPW, w SPW + WAVES SPW, ..., RND
+// rounds of them per pass.
+template <int BP, int RND, int WAVES>
+__device__ __forceinline__ void invert_rounds(double* Gi, int s, int wave, int lane, bool& bad) {
+  using C = SolveCfg<BP>;
+  for (int j0 = wave * C::SPW; j0 < s; j0 += RND * WAVES * C::SPW) {
+    // entry t of this lane in round r: block blk(r, t), row uu(t), column vv(t)
+    auto blk = [&](int r, int t) {
+      return (C::EPL == 1 ? j0 + lane / (BP * BP) : j0) + r * WAVES * C::SPW;
+    };
+    auto eix = [&](int t) { return C::EPL == 1 ? lane % (BP * BP) : lane + 64 * t; };
+    double e[RND][C::EPL];
+#pragma unroll
+    for (int r = 0; r < RND; ++r)
+#pragma unroll
+      for (int t = 0; t < C::EPL; ++t) {
+        const int bj = blk(r, t), uu = eix(t) / BP, vv = eix(t) % BP;
+        e[r][t] = bj < s ? Gi[(size_t)bj * C::GS + uu * BP + vv] : (uu == vv ? 1.0 : 0.0);
+      }
+#pragma unroll
+    for (int r = 0; r < RND; ++r) gj_invert<BP>(e[r], lane, bad);
+#pragma unroll
+    for (int r = 0; r < RND; ++r)
+#pragma unroll
+      for (int t = 0; t < C::EPL; ++t)
+        if (blk(r, t) < s)
+          Gi[(size_t)blk(r, t) * C::GS + eix(t)] = e[r][t];
+  }
+}
+
 // One outer step's fused solve by one workgroup of THREADS threads; sm holds
 // solve_lds_bytes(m, b) bytes of LDS.
 //   MAP 0: thread p owns row p (THREADS >= m); per block two barriers: the
@@ -120,7 +197,7 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   // Dl [s][BP] (zero-padded delta), Ix [m]
   const int slots = std::max(kHashMin, pow2_at_least(2 * m));
   const size_t gi_doubles =
-      std::max((size_t)s * BP * BP, ((size_t)slots * 3 * sizeof(int) + 7) / sizeof(double));
+      std::max((size_t)s * C::GS, ((size_t)slots * 3 * sizeof(int) + 7) / sizeof(double));
   double* Gi = sm;
   double* R = Gi + gi_doubles;
   double* Dl = R + BP;
@@ -180,7 +257,7 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int q = q0 + i * THREADS + tid;
-        if (q < total) Gi[q] = v[i];
+        if (q < total) Gi[(size_t)(q / (BP * BP)) * C::GS + q % (BP * BP)] = v[i];
       }
     }
   }
@@ -193,34 +270,17 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   for (int q = tid; q < s * BP; q += THREADS) Dl[q] = 0.0;
   if (tid < BP) R[tid] = 0.0;
   lds_barrier();
-  // With one entry per lane, two rounds of blocks per wave at once: their
-  // elimination chains are independent, so their latencies overlap (larger
-  // blocks have enough independent work per round and no registers to spare).
-  constexpr int RND = C::EPL == 1 ? 2 : 1;
+  // Blocks of up to 8 x 8 are inverted one per lane when the workgroup's waves
+  // have registers to spare (THREADS <= 256: one wave per SIMD).  Otherwise a
+  // wave inverts its blocks with the entries spread over the lanes, two at
+  // once (rounds) when a block has one entry per lane: their elimination
+  // chains are independent, so their latencies overlap.  Larger blocks have
+  // enough independent work per round and no registers to spare.
   bool bad = false;
-  for (int j0 = wave * C::SPW; j0 < s; j0 += RND * WAVES * C::SPW) {
-    // entry t of this lane in round r: block blk(r, t), row uu(t), column vv(t)
-    auto blk = [&](int r, int t) {
-      return (C::EPL == 1 ? j0 + lane / (BP * BP) : j0) + r * WAVES * C::SPW;
-    };
-    auto eix = [&](int t) { return C::EPL == 1 ? lane % (BP * BP) : lane + 64 * t; };
-    double e[RND][C::EPL];
-#pragma unroll
-    for (int r = 0; r < RND; ++r)
-#pragma unroll
-      for (int t = 0; t < C::EPL; ++t) {
-        const int bj = blk(r, t), uu = eix(t) / BP, vv = eix(t) % BP;
-        e[r][t] = bj < s ? Gi[((size_t)bj * BP + uu) * BP + vv] : (uu == vv ? 1.0 : 0.0);
-      }
-#pragma unroll
-    for (int r = 0; r < RND; ++r) gj_invert<BP>(e[r], lane, bad);
-#pragma unroll
-    for (int r = 0; r < RND; ++r)
-#pragma unroll
-      for (int t = 0; t < C::EPL; ++t)
-        if (blk(r, t) < s)
-          Gi[((size_t)blk(r, t) * BP + eix(t) / BP) * BP + eix(t) % BP] = e[r][t];
-  }
+  if constexpr (BP <= 8 && THREADS <= 256)
+    invert_per_lane<BP, THREADS>(Gi, s, tid, bad);
+  else
+    invert_rounds<BP, (C::EPL == 1 ? 2 : 1), WAVES>(Gi, s, wave, lane, bad);
   if (bad) *glb(a.status) = DEV_NOTSPD;
   lds_barrier();
 
@@ -230,25 +290,32 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   if constexpr (MAP == 1) {
     double gi[BP];   // row u of Gamma_{j_of}^-1 (identity rows for padding)
 #pragma unroll
-    for (int v = 0; v < BP; ++v) gi[v] = j_of >= 0 ? Gi[((size_t)j_of * BP + u) * BP + v] : 0.0;
-    const int l0 = lane - u;   // first lane of this thread's block
+    for (int v = 0; v < BP; ++v) gi[v] = j_of >= 0 ? Gi[(size_t)j_of * C::GS + u * BP + v] : 0.0;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     for (int j0 = 0; j0 < s; j0 += PF) {
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         const int j = j0 + q;
-        if (j_of == j) {
-          double d = 0.0;
+        if (wv == (j * BP) >> 6) {   // the wave that holds block j
+          // its rhs entries, read from their lanes into scalar registers
+          const int lb = (j * BP) & 63;
+          double rv[BP];
 #pragma unroll
-          for (int v = 0; v < BP; ++v) d += gi[v] * __shfl(rhs, l0 + v, 64);
-          Dl[j * BP + u] = u < b ? d : 0.0;
+          for (int v = 0; v < BP; ++v) rv[v] = read_lane(rhs, lb + v);
+          if (j_of == j) {
+            double d[2] = {0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < BP; ++v) d[v & 1] = fma(gi[v], rv[v], d[v & 1]);
+            Dl[j * BP + u] = u < b ? d[0] + d[1] : 0.0;
+          }
         }
         lds_barrier();
         if (active && j_of > j) {
           const double* dj = Dl + j * BP;
-          double acc = 0.0;
+          double acc[2] = {0.0, 0.0};
 #pragma unroll
-          for (int v = 0; v < BP; ++v) acc += ring[q][v] * dj[v];
-          rhs -= acc;
+          for (int v = 0; v < BP; ++v) acc[v & 1] = fma(ring[q][v], dj[v], acc[v & 1]);
+          rhs -= acc[0] + acc[1];
         }
         ring_load(q, j + PF);
       }
