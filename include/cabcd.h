@@ -137,14 +137,16 @@ typedef struct cabcd_opts {
 
 /* Phases reported through cabcd_opts.timing (the breakdown of one outer step). */
 #define CABCD_PHASE_SAMPLE 0    /* block sampler                                   */
-#define CABCD_PHASE_GRAM 1      /* gathered-row Gram + Y u (split-K kernel)        */
+#define CABCD_PHASE_GRAM 1      /* gathered-row Gram (with Y u when fused)         */
 #define CABCD_PHASE_REDUCE 2    /* sum of the Gram partials, scale and overlap     */
 #define CABCD_PHASE_SOLVE 3     /* s Cholesky solves + recurrence + x[idx] += d    */
 #define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta                 */
 #define CABCD_PHASE_RECOMPUTE 5 /* exact companion recomputation                   */
 #define CABCD_PHASE_MONITOR 6   /* objective evaluation                            */
 #define CABCD_PHASE_CHECK 7     /* full residual of the stopping test              */
-#define CABCD_NPHASES 8
+#define CABCD_PHASE_YU 8        /* Y u as its own gathered-row pass (steps whose
+                                   Gram was computed ahead)                        */
+#define CABCD_NPHASES 9
 
 /* Fill *o with defaults: h0 0, no flags, no recompute, no monitor, sampler on,
    no residual checks. */

@@ -74,8 +74,8 @@ class BatchInfo(ctypes.Structure):
 
 BATCH_NO_GRAPH = 1
 
-NPHASES = 8
-PHASES = ["sample", "gram", "reduce", "solve", "update", "recompute", "monitor", "check"]
+NPHASES = 9
+PHASES = ["sample", "gram", "reduce", "solve", "update", "recompute", "monitor", "check", "yu"]
 
 
 _lib = None

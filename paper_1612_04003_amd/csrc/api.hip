@@ -641,7 +641,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       Gk = B.G + (size_t)gslot * m * m;
       ++gslot;
       --ahead;
-      HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
+      HIP_TRY(timer.run(CABCD_PHASE_YU, [&] {
         return mat_rows_dot(M, idx, m, comp, B.Yu, B.scratch, st);
       }));
     } else {

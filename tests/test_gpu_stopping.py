@@ -179,8 +179,8 @@ def test_primal_checks_without_tolerance_run_to_h(gpu_lib):
     gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), 1e-2, 3, 4, 40, 9, check_every=2, timing=tm,
                        timing_mask=1 << gpu_lib.PHASES.index("gram"))
     counts = {k: v["launches"] for k, v in gpu_lib.timing_dict(tm).items()}
-    # ten steps: at least one Gram launch each (Grams computed ahead add theirs)
-    assert counts["gram"] >= 10 and sum(counts.values()) == counts["gram"]
+    # ten steps: one Gram launch each, or fewer when Grams are computed ahead
+    assert 1 <= counts["gram"] <= 10 and sum(counts.values()) == counts["gram"]
 
 
 def test_primal_lowp_stops_where_oracle_stops(gpu_lib):
