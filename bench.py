@@ -348,18 +348,37 @@ def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, la
                 break
         return time.perf_counter() - t0, steps, err
 
+    def gram_rate(A, elem, steps=8):
+        """The Gram kernel alone over `steps` outer steps (HIP events around the
+        Gram launches only): ms per launch, algorithmic bytes (the gathered
+        rows) per second against the HBM peak, and flops per second."""
+        w = torch.zeros(d, dtype=torch.float64, device="cuda")
+        r = torch.empty(n, dtype=torch.float64, device="cuda")
+        tm = cabcd.new_timing()
+        cabcd.primal_bcd(A, y, lam, b, s, steps * s, 11, w=w, r=r, timing=tm,
+                         timing_mask=1 << cabcd.PHASES.index("gram"))
+        g = cabcd.timing_dict(tm)["gram"]
+        ms = g["ms"] / max(g["launches"], 1)
+        sb = s * b
+        gbs = sb * n * elem / (ms * 1e-3) / 1e9
+        return {"gram_ms": round(ms, 4), "gram_gbs": round(gbs, 1),
+                "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                "gram_tflops": round(n * sb * (sb + 1) / (ms * 1e-3) / 1e12, 2)}
+
     for name, code in (("bf16", cabcd.BF16), ("fp8", cabcd.FP8_E4M3)):
         Q = cabcd.quantize(X, code)
         Xh = Q.dequantize()
         fstar = closed_form_fstar(Xh)
         t64, st64, e64 = run(Xh, fstar)
+        g64 = gram_rate(Xh, 8)
         del Xh
         torch.cuda.empty_cache()
         tq, stq, eq = run(Q, fstar)
+        gq = gram_rate(Q, 2 if name == "bf16" else 1)
         res[name] = {"fp64_on_xhat_s": round(t64, 5), "fp64_outer_steps": st64,
                      "fp64_rel_err": e64,
                      "mixed_s": round(tq, 5), "mixed_outer_steps": stq, "mixed_rel_err": eq,
-                     "speedup": round(t64 / tq, 3)}
+                     "speedup": round(t64 / tq, 3), "gram_fp64": g64, "gram_" + name: gq}
         log(f"time-to-tol {name}: {res[name]}")
         del Q
         torch.cuda.empty_cache()

@@ -98,6 +98,236 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
                         partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP), aligned, lds);
 }
 
+// ---------------------------------------------------------------------------
+// sb in (128, 256] (NB = 16) with 16-byte aligned rows: the slab is fed by
+// LDS-DMA (gfx950 global_load_lds_dwordx4), as in the FP64 kernel.  A tile is
+// 256 rows x 256 bytes of codes (128 BF16 / 256 FP8 columns): the longer row
+// pieces keep the HBM pages busier than 128-byte pieces, and a 64 KiB tile
+// per workgroup in flight (one workgroup per CU, double-buffered in 130 KiB
+// of LDS) covers the memory latency.  The sixteen 16-byte chunks of a row
+// are stored XOR-swizzled (chunk c of row r at c ^ (r & 15)), so the sixteen
+// rows of a fragment read fall in distinct banks.  Y u is formed from LDS:
+// thread t decodes chunk t % 16 of rows t / 16 + 32 j (j < 8) against the
+// tile's u segment (DMA'd beside the rows) and keeps one FP64 sum per row;
+// the sixteen chunk sums of a row are added in chunk order at the end.
+template <int FMT>
+struct LD16 {
+  static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;   // element bytes
+  static constexpr int SBP = 256, NBLK = 136;
+  static constexpr int RB = 256;                         // row bytes per tile
+  static constexpr int KT = RB / ES;                     // tile width in elements
+  static constexpr int EPC = 16 / ES;                    // elements per chunk
+  static constexpr int TILE = SBP * RB;                  // 64 KiB of codes
+  static constexpr int UB = KT * 8;                      // the tile's u segment
+  static constexpr int BUF = TILE + UB;
+  static constexpr int LDS = 2 * BUF;
+  static constexpr int DMA_PER_WAVE = TILE / 1024 / 8;   // 8 instructions of 1 KiB
+  static constexpr int UDMA = UB / 1024;                 // 1 (BF16) or 2 (FP8)
+};
+
+template <int FMT, int W>
+__device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t ld,
+                                          int64_t k_begin, int64_t k_end, const int32_t* idx,
+                                          int m, const double* __restrict__ u,
+                                          double* __restrict__ part, uint8_t* lds) {
+  using C = LD16<FMT>;
+  typedef __attribute__((address_space(3))) void* lds_vptr;
+  typedef __attribute__((address_space(1))) const void* glb_vptr;
+  constexpr int R1 = W, R2 = 15 - W;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int ntiles = (int)((k_end - k_begin + C::KT - 1) / C::KT);
+  const int64_t end_b = k_end * C::ES;   // row bytes in range
+
+  // DMA instruction i of this wave fills tile bytes (8 W + i) KiB + 16 lane:
+  // row 4 (8 W + i) + lane / 16, position lane % 16, chunk (lane % 16) ^ (row % 16).
+  gptr<const uint8_t> src[C::DMA_PER_WAVE];
+  int cof[C::DMA_PER_WAVE];
+  const gptr<const uint8_t> Ag = glb(A);
+#pragma unroll
+  for (int i = 0; i < C::DMA_PER_WAVE; ++i) {
+    const int r = 4 * (C::DMA_PER_WAVE * W + i) + (lane >> 4);
+    cof[i] = 16 * ((lane & 15) ^ (r & 15));
+    src[i] = Ag + (int64_t)idx[r < m ? r : 0] * ld * C::ES;   // rows past m: any valid row
+  }
+  const bool want_u = u != nullptr;
+  const gptr<const double> ug = glb(u);
+  const bool u_dma = want_u && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  // A tile inside the slab is all DMA; the last tile of a slab that ends
+  // inside a tile is filled by a compact loop of ordinary loads (zeros past
+  // the end), kept out of line of the DMA path to keep the loop body small.
+  auto issue = [&](int t, int slot) {
+    const int64_t k0 = k_begin + (int64_t)t * C::KT;
+    uint8_t* T = lds + slot * C::BUF;
+    if (k0 + C::KT <= k_end) {
+#pragma unroll
+      for (int i = 0; i < C::DMA_PER_WAVE; ++i)
+        __builtin_amdgcn_global_load_lds((glb_vptr)(src[i] + k0 * C::ES + cof[i]),
+                                         (lds_vptr)(T + (C::DMA_PER_WAVE * W + i) * 1024), 16,
+                                         0, 0);
+      if (want_u && W == 7) {   // the tile's u segment, unswizzled after the rows
+#pragma unroll
+        for (int j = 0; j < C::UDMA; ++j) {
+          uint8_t* dst = T + C::TILE + j * 1024;
+          const int64_t ku = k0 + 2 * (64 * j + lane);
+          if (u_dma) {
+            __builtin_amdgcn_global_load_lds((glb_vptr)(ug + ku), (lds_vptr)dst, 16, 0, 0);
+          } else {
+            double2 v;
+            v.x = ug[ku];
+            v.y = ug[ku + 1];
+            *reinterpret_cast<double2*>(dst + 16 * lane) = v;
+          }
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < C::DMA_PER_WAVE; ++i) {
+      const int64_t kb = k0 * C::ES + cof[i];
+      uint64_t lo = 0, hi = 0;
+#pragma clang loop unroll(disable)
+      for (int e = 0; e < 16; ++e) {
+        const uint64_t v = kb + e < end_b ? (uint64_t)src[i][kb + e] : 0;
+        if (e < 8)
+          lo |= v << (8 * e);
+        else
+          hi |= v << (8 * (e - 8));
+      }
+      *reinterpret_cast<uint4*>(T + (C::DMA_PER_WAVE * W + i) * 1024 + 16 * lane) =
+          make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    }
+    if (want_u && W == 7) {
+#pragma clang loop unroll(disable)
+      for (int j = 0; j < C::UDMA; ++j) {
+        const int64_t ku = k0 + 2 * (64 * j + lane);
+        double2 v;
+        v.x = ku < k_end ? ug[ku] : 0.0;
+        v.y = ku + 1 < k_end ? ug[ku + 1] : 0.0;
+        *reinterpret_cast<double2*>(T + C::TILE + j * 1024 + 16 * lane) = v;
+      }
+    }
+  };
+
+  // fragment offsets of the four 64-byte windows: row lane % 16 of a block row,
+  // chunk 4 w + lane / 16, swizzled
+  int lane_off[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    lane_off[w] = (lane & 15) * C::RB + 16 * ((4 * w + (lane >> 4)) ^ (lane & 15));
+
+  f4 acc[17];
+#pragma unroll
+  for (int a = 0; a < 17; ++a) acc[a] = f4{0.f, 0.f, 0.f, 0.f};
+  // Y u: chunk yc of rows yr0 + 32 j
+  const int yc = tid & 15, yr0 = tid >> 4;
+  double yu[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) yu[j] = 0.0;
+
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);   // the LDS-DMA writes count on the vector memory counter
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) issue(t + 1, (t + 1) & 1);
+    const uint8_t* tile = lds + (t & 1) * C::BUF;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint8_t* base = tile + lane_off[w];
+      auto frag = [&](int r) { return *reinterpret_cast<const uint4*>(base + r * 16 * C::RB); };
+      const uint4 f1 = frag(R1);
+      const uint4 f2 = frag(R2);
+#pragma unroll
+      for (int c = 0; c <= R2; ++c) {
+        const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
+        if (c <= R1) acc[c] = lp_mma<FMT>(f1, fc, acc[c]);
+        acc[R1 + 1 + c] = lp_mma<FMT>(f2, fc, acc[R1 + 1 + c]);
+      }
+    }
+    if (want_u) {
+      const double* us = reinterpret_cast<const double*>(tile + C::TILE) + yc * C::EPC;
+      double ub[C::EPC];
+#pragma unroll
+      for (int e = 0; e < C::EPC; ++e) ub[e] = us[e];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int r = yr0 + 32 * j;
+        const uint4 v = *reinterpret_cast<const uint4*>(tile + r * C::RB + 16 * (yc ^ (r & 15)));
+        double dv[C::EPC];
+        lp_decode_all<FMT>(v, dv);
+#pragma unroll
+        for (int e = 0; e < C::EPC; ++e) yu[j] = fma(dv[e], ub[e], yu[j]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // tile t + 1 is in LDS
+    __syncthreads();
+  }
+
+  gptr<double> pg = glb(part);
+#pragma unroll
+  for (int a = 0; a < 17; ++a) {
+    gptr<double> dst = pg + lp_acc_block<16>(W, a) * 256 + lane;
+    dst[0] = acc[a][0];
+    dst[64] = acc[a][1];
+    dst[128] = acc[a][2];
+    dst[192] = acc[a][3];
+  }
+  if (want_u) {   // the sixteen chunk sums of each row, in chunk order
+    double* ys = reinterpret_cast<double*>(lds);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ys[(yr0 + 32 * j) * 16 + yc] = yu[j];
+    __syncthreads();
+    if (tid < C::SBP) {
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) sum += ys[tid * 16 + q];
+      pg[C::NBLK * 256 + tid] = sum;
+    }
+  }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kLpThreads) void gram_lp_dma16_kernel(
+    const uint8_t* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
+    int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
+    int64_t pstride) {
+  using C = LD16<FMT>;
+  extern __shared__ __attribute__((aligned(16))) uint8_t dyn_lds[];
+  idx += (int64_t)blockIdx.y * m;            // several outer steps per launch
+  partials += (int64_t)blockIdx.y * pstride;
+  const int64_t k_begin = (int64_t)blockIdx.x * chunk;
+  const int64_t k_end = std::min(cols, k_begin + chunk);
+  double* part = partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP);
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: lp16_slab<FMT, 0>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+    case 1: lp16_slab<FMT, 1>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+    case 2: lp16_slab<FMT, 2>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+    case 3: lp16_slab<FMT, 3>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+    case 4: lp16_slab<FMT, 4>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+    case 5: lp16_slab<FMT, 5>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+    case 6: lp16_slab<FMT, 6>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+    default: lp16_slab<FMT, 7>(A, ld, k_begin, k_end, idx, m, u, part, dyn_lds); break;
+  }
+}
+
+template <int FMT>
+hipError_t launch_lp_dma16(const GramPlan& p, const void* A, int64_t ld, int64_t cols,
+                           const int32_t* idx, int m, int nsteps, const double* u,
+                           double* partials, hipStream_t st) {
+  using C = LD16<FMT>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_lp_dma16_kernel<FMT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((gram_lp_dma16_kernel<FMT>), dim3((unsigned)p.nsplit, (unsigned)nsteps),
+                     dim3(kLpThreads), C::LDS, st, static_cast<const uint8_t*>(A), ld, cols, idx,
+                     m, u, p.chunk, partials, (int64_t)gram_partial_doubles(p));
+  return hipGetLastError();
+}
+
 template <int NB, int FMT>
 hipError_t launch_lp_nb(const GramPlan& p, const void* A, int64_t ld, int64_t cols,
                         const int32_t* idx, int m, int nsteps, const double* u,
@@ -105,6 +335,10 @@ hipError_t launch_lp_nb(const GramPlan& p, const void* A, int64_t ld, int64_t co
   using C = LpCfg<NB, FMT>;
   const int aligned =
       ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && ((ld * C::ES) & 15) == 0) ? 1 : 0;
+  if constexpr (NB == 16) {
+    if (aligned && p.chunk % LD16<FMT>::KT == 0)
+      return launch_lp_dma16<FMT>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
+  }
   hipLaunchKernelGGL((gram_lp_kernel<NB, FMT>), dim3((unsigned)p.nsplit, (unsigned)nsteps),
                      dim3(kLpThreads), 0, st, static_cast<const uint8_t*>(A), ld, cols, idx, m, u,
                      p.chunk, partials, (int64_t)gram_partial_doubles(p), aligned);
@@ -189,6 +423,16 @@ GramPlan plan_gram_lp(int m, int64_t cols, int dtype) {
   const int es = dtype == CABCD_BF16 ? 2 : 1;
   p.kt = (2048 / nb) / es;
   p.rpw = 2;
+  if (nb == 16) {
+    // the LDS-DMA kernel (aligned rows): one workgroup per CU, 256-byte tile
+    // rows; its slabs also suit the register-fed kernel (a multiple of kt)
+    const int64_t kt = 256 / es;
+    int64_t chunk = std::max<int64_t>(kt, (cols + 255) / 256);
+    chunk = ((chunk + kt - 1) / kt) * kt;
+    p.chunk = chunk;
+    p.nsplit = (int)((cols + chunk - 1) / chunk);
+    return p;
+  }
   // HBM-bound: about two workgroups per CU, and slabs long enough that the
   // partial blocks (nblk*2 KiB per workgroup) stay small next to the slab.
   const int64_t min_chunk = std::max<int64_t>(p.kt, (int64_t)p.nblk * 2048 * 8 / (16 * nb * es));

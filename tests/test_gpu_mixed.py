@@ -51,7 +51,11 @@ def test_quantize_bit_exact(gpu_lib, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
-@pytest.mark.parametrize("m,cols", [(5, 77), (16, 4096), (100, 10001), (256, 20000)])
+@pytest.mark.parametrize("m,cols", [(5, 77), (16, 4096), (100, 10001), (256, 20000),
+                                    # sb in (128, 256]: the LDS-DMA kernel on aligned rows
+                                    # (several tiles per slab, a partial last tile), and the
+                                    # register-fed kernel on unaligned rows
+                                    (129, 1024), (200, 4112), (256, 70000), (200, 4099)])
 def test_lowp_gram_against_fp64_gram_of_dequantised(gpu_lib, dtype, m, cols):
     _say("lowp gram", dtype, m, cols)
     rows = m + 7
