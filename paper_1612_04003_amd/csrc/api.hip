@@ -359,6 +359,11 @@ class PhaseTimer {
   std::vector<Rec> recs_;
 };
 
+// Layout of the Gram partials a launch of `plan` writes for the dense M.
+int partial_layout(const Mat& M, const GramPlan& plan) {
+  return M.lowp() ? gram_lp_partial_layout(plan, M.dtype, M.Q, M.ld) : 0;
+}
+
 // scale * Y Y^T + shift * E and Y u for the rows idx[0..m) of A.
 hipError_t mat_gram(const Mat& M, const int32_t* idx, int m, const double* u, double scale,
                     double shift, bool overlap, double* G, double* Yu, double* partials,
@@ -374,7 +379,7 @@ hipError_t mat_gram(const Mat& M, const int32_t* idx, int m, const double* u, do
   };
   auto r = [&] {
     return launch_gram_reduce(plan, partials, idx, m, scale, shift, overlap, G, Yu, st,
-                              M.lowp() ? 1 : 0, M.lowp() ? M.rs : nullptr);
+                              partial_layout(M, plan), M.lowp() ? M.rs : nullptr);
   };
   hipError_t e = timer ? timer->run(CABCD_PHASE_GRAM, g) : g();
   if (e != hipSuccess) return e;
@@ -420,7 +425,7 @@ hipError_t mat_gram_steps(const Mat& M, const int32_t* idx, int m, int nsteps, d
   if (e != hipSuccess) return e;
   return timer->run(CABCD_PHASE_REDUCE, [&] {
     return launch_gram_reduce(plan, partials, idx, m, scale, shift, true, G, nullptr, st,
-                              M.lowp() ? 1 : 0, M.lowp() ? M.rs : nullptr, nsteps);
+                              partial_layout(M, plan), M.lowp() ? M.rs : nullptr, nsteps);
   });
 }
 

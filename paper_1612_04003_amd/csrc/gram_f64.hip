@@ -66,7 +66,19 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
   const int sp0 = grp * per;
   const int sp1 = min(nsplit, sp0 + per);
   double s = 0.0;
-  if (e < pstride) {
+  if (layout == 2 && e < (int64_t)nblk * 256) {   // FP32 block entries
+    const float* p = reinterpret_cast<const float*>(partials) + e;
+    const int64_t fstride = 2 * pstride;
+    int sp = sp0;
+    for (; sp + 8 <= sp1; sp += 8) {
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[(int64_t)(sp + q) * fstride];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += (double)v[q];
+    }
+    for (; sp < sp1; ++sp) s += (double)p[(int64_t)sp * fstride];
+  } else if (e < pstride) {
     const double* p = partials + e;
     int sp = sp0;
     for (; sp + 8 <= sp1; sp += 8) {

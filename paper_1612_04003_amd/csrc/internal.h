@@ -124,7 +124,8 @@ hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64
 // E = I (overlap = false) or E_pq = [idx_p == idx_q] (overlap = true).
 // Yu (may be NULL) = sum of the partial Yu.
 // layout 0: partial block entries in the FP64 MFMA output order; 1: in the FP32
-// MFMA output order.  rs (may be NULL) are row scales of A applied as
+// MFMA output order; 2: as 1, the block entries stored as FP32 (the first
+// nblk*256 floats of each partial set; Y u stays FP64 at its place).  rs (may be NULL) are row scales of A applied as
 // rs[idx_p] rs[idx_q] to G and rs[idx_p] to Y u.
 // nsteps > 1: step k reduces partials + k gram_partial_doubles(p) into
 // G + k m^2 (Yu must be NULL).
@@ -163,6 +164,10 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t st);
 hipError_t launch_quantize(const double* A, int64_t rows, int64_t cols, int64_t lda, int dtype,
                            void* Q, int64_t ldq, float* row_scale, hipStream_t st);
 GramPlan plan_gram_lp(int m, int64_t cols, int dtype);
+// Partial layout a low-precision Gram launch of plan p writes for A (ld in
+// elements): 1 = FP64 entries in the FP32 MFMA output order, 2 = the same
+// entries stored as FP32 (the LDS-DMA kernel); Y u is FP64 in both.
+int gram_lp_partial_layout(const GramPlan& p, int dtype, const void* A, int64_t ld);
 // Gram partials of stored codes (FP32 MFMA accumulation, FP64 partials; the
 // partial blocks use the FP32 MFMA output layout) plus Y u of the codes in FP64.
 hipError_t launch_gram_lp(const GramPlan& p, int dtype, const void* A, int64_t ld, int64_t cols,

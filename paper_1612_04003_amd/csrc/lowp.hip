@@ -263,10 +263,13 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
     __syncthreads();
   }
 
+  // partial blocks as FP32 (what the accumulators hold; half the bytes of
+  // FP64), Y u as FP64 at its usual place
   gptr<double> pg = glb(part);
+  const gptr<float> pf = (gptr<float>)pg;
 #pragma unroll
   for (int a = 0; a < 17; ++a) {
-    gptr<double> dst = pg + lp_acc_block<16>(W, a) * 256 + lane;
+    gptr<float> dst = pf + lp_acc_block<16>(W, a) * 256 + lane;
     dst[0] = acc[a][0];
     dst[64] = acc[a][1];
     dst[128] = acc[a][2];
@@ -441,6 +444,12 @@ GramPlan plan_gram_lp(int m, int64_t cols, int dtype) {
   p.chunk = chunk;
   p.nsplit = (int)((cols + chunk - 1) / chunk);
   return p;
+}
+
+int gram_lp_partial_layout(const GramPlan& p, int dtype, const void* A, int64_t ld) {
+  const int es = dtype == CABCD_BF16 ? 2 : 1;
+  const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && ((ld * es) & 15) == 0;
+  return p.nb == 16 && aligned && p.chunk % (256 / es) == 0 ? 2 : 1;
 }
 
 hipError_t launch_gram_lp(const GramPlan& p, int dtype, const void* A, int64_t ld, int64_t cols,
