@@ -110,6 +110,8 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
 // thread t decodes chunk t % 16 of rows t / 16 + 32 j (j < 8) against the
 // tile's u segment (DMA'd beside the rows) and keeps one FP64 sum per row;
 // the sixteen chunk sums of a row are added in chunk order at the end.
+typedef int i8v __attribute__((ext_vector_type(8)));
+
 template <int FMT>
 struct LD16 {
   static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;   // element bytes
@@ -210,11 +212,15 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   };
 
   // fragment offsets of the four 64-byte windows: row lane % 16 of a block row,
-  // chunk 4 w + lane / 16, swizzled
+  // chunk 4 w + lane / 16, swizzled.  FP8 takes the K = 128 instruction of
+  // gfx950 on 128-byte halves: chunks 8 h + 2 (lane / 16) and the next one.
   int lane_off[4];
 #pragma unroll
-  for (int w = 0; w < 4; ++w)
-    lane_off[w] = (lane & 15) * C::RB + 16 * ((4 * w + (lane >> 4)) ^ (lane & 15));
+  for (int w = 0; w < 4; ++w) {
+    const int ch = FMT == CABCD_BF16 ? 4 * w + (lane >> 4)
+                                     : 8 * (w >> 1) + 2 * (lane >> 4) + (w & 1);
+    lane_off[w] = (lane & 15) * C::RB + 16 * (ch ^ (lane & 15));
+  }
 
   f4 acc[17];
 #pragma unroll
@@ -231,17 +237,43 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) issue(t + 1, (t + 1) & 1);
     const uint8_t* tile = lds + (t & 1) * C::BUF;
+    if constexpr (FMT == CABCD_BF16) {
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const uint8_t* base = tile + lane_off[w];
-      auto frag = [&](int r) { return *reinterpret_cast<const uint4*>(base + r * 16 * C::RB); };
-      const uint4 f1 = frag(R1);
-      const uint4 f2 = frag(R2);
+      for (int w = 0; w < 4; ++w) {
+        const uint8_t* base = tile + lane_off[w];
+        auto frag = [&](int r) { return *reinterpret_cast<const uint4*>(base + r * 16 * C::RB); };
+        const uint4 f1 = frag(R1);
+        const uint4 f2 = frag(R2);
 #pragma unroll
-      for (int c = 0; c <= R2; ++c) {
-        const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-        if (c <= R1) acc[c] = lp_mma<FMT>(f1, fc, acc[c]);
-        acc[R1 + 1 + c] = lp_mma<FMT>(f2, fc, acc[R1 + 1 + c]);
+        for (int c = 0; c <= R2; ++c) {
+          const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
+          if (c <= R1) acc[c] = lp_mma<FMT>(f1, fc, acc[c]);
+          acc[R1 + 1 + c] = lp_mma<FMT>(f2, fc, acc[R1 + 1 + c]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint8_t* b0 = tile + lane_off[2 * h];
+        const uint8_t* b1 = tile + lane_off[2 * h + 1];
+        auto frag = [&](int r) {   // 32 codes of row r: two 16-byte chunks
+          const uint4 x = *reinterpret_cast<const uint4*>(b0 + r * 16 * C::RB);
+          const uint4 y = *reinterpret_cast<const uint4*>(b1 + r * 16 * C::RB);
+          return i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z,
+                     (int)y.w};
+        };
+        const i8v f1 = frag(R1);
+        const i8v f2 = frag(R2);
+#pragma unroll
+        for (int c = 0; c <= R2; ++c) {
+          const i8v fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
+          // E4M3 codes for both operands (format 0), no block scaling
+          if (c <= R1)
+            acc[c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(f1, fc, acc[c], 0, 0, 0, 0,
+                                                                      0, 0);
+          acc[R1 + 1 + c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              f2, fc, acc[R1 + 1 + c], 0, 0, 0, 0, 0, 0);
+        }
       }
     }
     if (want_u) {
