@@ -110,8 +110,6 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
 // thread t decodes chunk t % 16 of rows t / 16 + 32 j (j < 8) against the
 // tile's u segment (DMA'd beside the rows) and keeps one FP64 sum per row;
 // the sixteen chunk sums of a row are added in chunk order at the end.
-typedef int i8v __attribute__((ext_vector_type(8)));
-
 template <int FMT>
 struct LD16 {
   static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;   // element bytes
@@ -247,8 +245,8 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
 #pragma unroll
         for (int c = 0; c <= R2; ++c) {
           const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-          if (c <= R1) acc[c] = lp_mma<FMT>(f1, fc, acc[c]);
-          acc[R1 + 1 + c] = lp_mma<FMT>(f2, fc, acc[R1 + 1 + c]);
+          if (c <= R1) acc[c] = lp_mma_bf16(f1, fc, acc[c]);
+          acc[R1 + 1 + c] = lp_mma_bf16(f2, fc, acc[R1 + 1 + c]);
         }
       }
     } else {
@@ -259,20 +257,16 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
         auto frag = [&](int r) {   // 32 codes of row r: two 16-byte chunks
           const uint4 x = *reinterpret_cast<const uint4*>(b0 + r * 16 * C::RB);
           const uint4 y = *reinterpret_cast<const uint4*>(b1 + r * 16 * C::RB);
-          return i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z,
-                     (int)y.w};
+          return lp_i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z,
+                        (int)y.w};
         };
-        const i8v f1 = frag(R1);
-        const i8v f2 = frag(R2);
+        const lp_i8v f1 = frag(R1);
+        const lp_i8v f2 = frag(R2);
 #pragma unroll
         for (int c = 0; c <= R2; ++c) {
-          const i8v fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-          // E4M3 codes for both operands (format 0), no block scaling
-          if (c <= R1)
-            acc[c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(f1, fc, acc[c], 0, 0, 0, 0,
-                                                                      0, 0);
-          acc[R1 + 1 + c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-              f2, fc, acc[R1 + 1 + c], 0, 0, 0, 0, 0, 0);
+          const lp_i8v fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
+          if (c <= R1) acc[c] = lp_mma_k128(f1, fc, acc[c]);
+          acc[R1 + 1 + c] = lp_mma_k128(f2, fc, acc[R1 + 1 + c]);
         }
       }
     }

@@ -18,7 +18,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kLpThreads = 512;   // 8 waves, two block rows each
 
 // FMT: CABCD_BF16 (2-byte elements, one MFMA per 16-byte fragment) or
-// CABCD_FP8_E4M3 (1-byte elements, two MFMAs per 16-byte fragment).
+// CABCD_FP8_E4M3 (1-byte elements, one K = 128 MFMA per two 16-byte fragments).
 template <int NB, int FMT>
 struct LpCfg {
   static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;      // element bytes
@@ -51,19 +51,20 @@ __device__ __forceinline__ int lp_acc_block(int bw, int a) {
   return a <= r1 ? lp_blk_index(r1, a) : lp_blk_index(r2, a - r1 - 1);
 }
 
-template <int FMT>
-__device__ __forceinline__ f4 lp_mma(const uint4& a, const uint4& b, f4 c) {
-  if constexpr (FMT == CABCD_BF16) {
-    bf16x8 x, y;
-    __builtin_memcpy(&x, &a, 16);
-    __builtin_memcpy(&y, &b, 16);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
-  } else {
-    const long a0 = (long)(((uint64_t)a.y << 32) | a.x), b0 = (long)(((uint64_t)b.y << 32) | b.x);
-    const long a1 = (long)(((uint64_t)a.w << 32) | a.z), b1 = (long)(((uint64_t)b.w << 32) | b.z);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
-  }
+// BF16 x BF16, K = 32: each lane brings 8 codes of its row.
+__device__ __forceinline__ f4 lp_mma_bf16(const uint4& a, const uint4& b, f4 c) {
+  bf16x8 x, y;
+  __builtin_memcpy(&x, &a, 16);
+  __builtin_memcpy(&y, &b, 16);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+}
+
+typedef int lp_i8v __attribute__((ext_vector_type(8)));
+
+// E4M3 x E4M3 on the gfx950 K = 128 instruction (format 0 for both operands,
+// no block scaling): each lane brings 32 codes of its row.
+__device__ __forceinline__ f4 lp_mma_k128(const lp_i8v& a, const lp_i8v& b, f4 c) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
 }
 
 template <int NB, int FMT, int W>
@@ -73,19 +74,44 @@ __device__ __forceinline__ void lp_tile(const uint8_t* __restrict__ tile, int la
   constexpr int R1 = NB >= 2 ? W : 0;
   constexpr int R2 = NB >= 2 ? NB - 1 - W : 0;
   const uint8_t* base = tile + (lane & 15) * C::RSB + 16 * (lane >> 4);
+  if constexpr (FMT == CABCD_BF16) {
 #pragma unroll
-  for (int p = 0; p < C::WIN / C::KG; ++p) {
-    const int off = 64 * (kg + p * C::KG);
-    auto frag = [&](int r) {
-      return *reinterpret_cast<const uint4*>(base + r * 16 * C::RSB + off);
-    };
-    const uint4 f1 = frag(R1);
-    const uint4 f2 = NB >= 2 ? frag(R2) : f1;
+    for (int p = 0; p < C::WIN / C::KG; ++p) {
+      const int off = 64 * (kg + p * C::KG);
+      auto frag = [&](int r) {
+        return *reinterpret_cast<const uint4*>(base + r * 16 * C::RSB + off);
+      };
+      const uint4 f1 = frag(R1);
+      const uint4 f2 = NB >= 2 ? frag(R2) : f1;
 #pragma unroll
-    for (int c = 0; c <= R2; ++c) {
-      const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-      if (c <= R1) acc[c] = lp_mma<FMT>(f1, fc, acc[c]);
-      if constexpr (NB >= 2) acc[R1 + 1 + c] = lp_mma<FMT>(f2, fc, acc[R1 + 1 + c]);
+      for (int c = 0; c <= R2; ++c) {
+        const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
+        if (c <= R1) acc[c] = lp_mma_bf16(f1, fc, acc[c]);
+        if constexpr (NB >= 2) acc[R1 + 1 + c] = lp_mma_bf16(f2, fc, acc[R1 + 1 + c]);
+      }
+    }
+  } else {
+    // FP8: two of this group's 64-byte windows per K = 128 instruction (the
+    // same 32 codes of a row for both operands, so which columns pair up
+    // does not matter for Y Y^T)
+    static_assert((C::WIN / C::KG) % 2 == 0, "windows pair up");
+#pragma unroll
+    for (int p = 0; p < C::WIN / C::KG; p += 2) {
+      const int off0 = 64 * (kg + p * C::KG), off1 = 64 * (kg + (p + 1) * C::KG);
+      auto frag = [&](int r) {
+        const uint4 x = *reinterpret_cast<const uint4*>(base + r * 16 * C::RSB + off0);
+        const uint4 y = *reinterpret_cast<const uint4*>(base + r * 16 * C::RSB + off1);
+        return lp_i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z,
+                      (int)y.w};
+      };
+      const lp_i8v f1 = frag(R1);
+      const lp_i8v f2 = NB >= 2 ? frag(R2) : f1;
+#pragma unroll
+      for (int c = 0; c <= R2; ++c) {
+        const lp_i8v fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
+        if (c <= R1) acc[c] = lp_mma_k128(f1, fc, acc[c]);
+        if constexpr (NB >= 2) acc[R1 + 1 + c] = lp_mma_k128(f2, fc, acc[R1 + 1 + c]);
+      }
     }
   }
 }
