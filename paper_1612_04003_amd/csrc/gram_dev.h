@@ -302,6 +302,227 @@ __device__ __forceinline__ void gram_slab(const double* __restrict__ A, int64_t 
 
 
 // ---------------------------------------------------------------------------
+// NB <= 8 fed by LDS-DMA (the decomposition of gram_slab<NB, 2>: waves own
+// block-row pairs and split a tile's k-steps): a 32 KiB tile of SBP rows x
+// KT = 256 / NB columns goes from HBM straight into LDS, rows unpadded with the
+// 16-byte chunks of each aligned group of sixteen XOR-swizzled by the row
+// (chunk c of row r at c ^ (r & 15)), so the sixteen rows of a fragment read
+// fall in distinct banks; a thread forms Y u for its four (row, chunk) pairs
+// from LDS after the tile lands.  Rows of 256 bytes (NB = 8) to 2 KiB (NB = 1)
+// per tile keep the HBM pages busy.
+template <int NB>
+struct DN {
+  using C = Cfg<NB, 2>;
+  static constexpr int DMA_PER_WAVE = C::SBP * C::CH / 64 / 8;   // 4 instructions
+  static constexpr int UDMA = (C::KT / 2 + 63) / 64;              // u slots, 64 a time
+  static constexpr int TILE = C::SBP * C::KT + C::KT;            // doubles: rows, then u
+  static constexpr int LDS = std::max(std::max(2 * TILE, C::RED), C::YUS);
+};
+
+template <int NB, int W>
+__device__ __forceinline__ void mma_tile_dma(const double* __restrict__ tile, int lane, int kg,
+                                             d4 (&acc)[Cfg<NB, 2>::NACC]) {
+  using C = Cfg<NB, 2>;
+  constexpr int NR = NB >= 2 ? 2 : 1;
+  const int rl = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int p = 0; p < C::PAIRS / C::KG; ++p) {
+    const int ch = 4 * (kg + p * C::KG) + g;            // chunk (two columns) of this lane
+    const double* base = tile + rl * C::KT + 2 * (ch ^ rl);
+    auto frag = [&](int r) { return *reinterpret_cast<const double2*>(base + r * 16 * C::KT); };
+    double2 fo[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) fo[i] = frag(owned_row(NB, 2, W, i));
+    constexpr int CMAX = NB >= 2 ? NB - 1 - W : 0;        // largest owned row
+#pragma unroll
+    for (int c = 0; c <= CMAX; ++c) {
+      double2 fc = {0.0, 0.0};
+      bool own = false;
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+        if (owned_row(NB, 2, W, i) == c) {
+          fc = fo[i];
+          own = true;
+        }
+      if (!own) fc = frag(c);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int r = owned_row(NB, 2, W, i);
+        if (c <= r) {
+          const int a = acc_offset(NB, 2, W, i) + c;
+          acc[a] = mfma(fo[i].x, fc.x, acc[a]);
+          acc[a] = mfma(fo[i].y, fc.y, acc[a]);
+        }
+      }
+    }
+  }
+}
+
+template <int NB, int W = 0>
+__device__ __forceinline__ void mma_dispatch_dma(int bw, const double* __restrict__ tile, int lane,
+                                                 int kg, d4 (&acc)[Cfg<NB, 2>::NACC]) {
+  if constexpr (W < Cfg<NB, 2>::BW) {
+    if (bw == W)
+      mma_tile_dma<NB, W>(tile, lane, kg, acc);
+    else
+      mma_dispatch_dma<NB, W + 1>(bw, tile, lane, kg, acc);
+  }
+}
+
+// The slab of gram_slab<NB, 2> on the DMA path (A 16-byte aligned with an even
+// ld); same arguments and partial layout.  lds holds DN<NB>::LDS doubles.
+template <int NB>
+__device__ __forceinline__ void gram_slab_dma(const double* __restrict__ A, int64_t ld,
+                                              int64_t k_begin, int64_t k_end, const int32_t* idx,
+                                              int m, const double* __restrict__ u,
+                                              double* __restrict__ part, double* lds) {
+  using C = Cfg<NB, 2>;
+  using D = DN<NB>;
+  typedef __attribute__((address_space(3))) void* lds_vptr;
+  typedef __attribute__((address_space(1))) const void* glb_vptr;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int bw = __builtin_amdgcn_readfirstlane(wave % C::BW);
+  const int kg = __builtin_amdgcn_readfirstlane(wave / C::BW);
+  const int ntiles = (int)((k_end - k_begin + C::KT - 1) / C::KT);
+
+  // DMA instruction i of this wave fills slots (4 wave + i) * 64 + lane:
+  // row slot / CH, position slot % CH, chunk position ^ (row % 16).
+  gptr<const double> src[D::DMA_PER_WAVE];
+  int cofs[D::DMA_PER_WAVE];
+  const gptr<const double> Ag = glb(A);
+#pragma unroll
+  for (int i = 0; i < D::DMA_PER_WAVE; ++i) {
+    const int q = (D::DMA_PER_WAVE * wave + i) * 64 + lane;
+    const int r = q / C::CH;
+    cofs[i] = 2 * ((q % C::CH) ^ (r & 15));
+    src[i] = Ag + (int64_t)idx[r < m ? r : 0] * ld;   // rows past m: any valid row
+  }
+  const bool want_u = u != nullptr;
+  const gptr<const double> ug = glb(u);
+  const bool u_dma = want_u && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  auto issue = [&](int t, int slot) {
+    const int64_t k0 = k_begin + (int64_t)t * C::KT;
+    double* T = lds + slot * D::TILE;
+    const bool full = k0 + C::KT <= k_end;
+#pragma unroll
+    for (int i = 0; i < D::DMA_PER_WAVE; ++i) {
+      double* dst = T + (D::DMA_PER_WAVE * wave + i) * 128;   // 64 slots of 2 doubles
+      const int64_t k = k0 + cofs[i];
+      if (full) {
+        __builtin_amdgcn_global_load_lds((glb_vptr)(src[i] + k), (lds_vptr)dst, 16, 0, 0);
+      } else {
+        double2 v;
+        v.x = k < k_end ? src[i][k] : 0.0;
+        v.y = k + 1 < k_end ? src[i][k + 1] : 0.0;
+        *reinterpret_cast<double2*>(dst + 2 * lane) = v;
+      }
+    }
+    if (want_u && wave == 7) {   // the tile's KT entries of u, unswizzled after the rows
+#pragma unroll
+      for (int j = 0; j < D::UDMA; ++j) {
+        if (64 * j + lane < C::KT / 2) {
+          double* dst = T + C::SBP * C::KT + 128 * j;
+          const int64_t k = k0 + 2 * (64 * j + lane);
+          if (full && u_dma) {
+            __builtin_amdgcn_global_load_lds((glb_vptr)(ug + k), (lds_vptr)dst, 16, 0, 0);
+          } else {
+            double2 v;
+            v.x = k < k_end ? ug[k] : 0.0;
+            v.y = k + 1 < k_end ? ug[k + 1] : 0.0;
+            *reinterpret_cast<double2*>(dst + 2 * lane) = v;
+          }
+        }
+      }
+    }
+  };
+
+  // Y u: chunk c of rows tid / CH + (THREADS / CH) i, as in gram_slab
+  const int c = tid % C::CH;
+  int rho[C::NCH];
+#pragma unroll
+  for (int i = 0; i < C::NCH; ++i) rho[i] = tid / C::CH + (C::THREADS / C::CH) * i;
+  double yu[C::NCH];
+#pragma unroll
+  for (int i = 0; i < C::NCH; ++i) yu[i] = 0.0;
+
+  d4 acc[C::NACC];
+#pragma unroll
+  for (int a = 0; a < C::NACC; ++a) acc[a] = d4{0.0, 0.0, 0.0, 0.0};
+
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);   // the LDS-DMA writes count on the vector memory counter
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) issue(t + 1, (t + 1) & 1);
+    const double* tile = lds + (t & 1) * D::TILE;
+    mma_dispatch_dma<NB>(bw, tile, lane, kg, acc);
+    if (want_u) {
+      const double2 ub = *reinterpret_cast<const double2*>(tile + C::SBP * C::KT + 2 * c);
+#pragma unroll
+      for (int i = 0; i < C::NCH; ++i) {
+        const int r = rho[i];
+        const double2 v =
+            *reinterpret_cast<const double2*>(tile + r * C::KT + 2 * (c ^ (r & 15)));
+        yu[i] = fma(v.x, ub.x, yu[i]);
+        yu[i] = fma(v.y, ub.y, yu[i]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // tile t + 1 is in LDS
+    __syncthreads();
+  }
+
+  // Sum the k-groups (waves with the same blocks) through LDS, in group order.
+  if constexpr (C::KG > 1) {
+    if (kg > 0) {
+#pragma unroll
+      for (int a = 0; a < C::NACC; ++a) {
+        double* dst = lds + ((kg - 1) * C::NBLK + acc_block<NB, 2>(bw, a)) * 256 + lane;
+        dst[0] = acc[a][0];
+        dst[64] = acc[a][1];
+        dst[128] = acc[a][2];
+        dst[192] = acc[a][3];
+      }
+    }
+    __syncthreads();
+    if (kg == 0) {
+      for (int g = 1; g < C::KG; ++g) {
+#pragma unroll
+        for (int a = 0; a < C::NACC; ++a) {
+          const double* srcp = lds + ((g - 1) * C::NBLK + acc_block<NB, 2>(bw, a)) * 256 + lane;
+          acc[a][0] += srcp[0];
+          acc[a][1] += srcp[64];
+          acc[a][2] += srcp[128];
+          acc[a][3] += srcp[192];
+        }
+      }
+    }
+  }
+  if (kg == 0) {
+#pragma unroll
+    for (int a = 0; a < C::NACC; ++a) {
+      gptr<double> dst = glb(part) + acc_block<NB, 2>(bw, a) * 256 + lane;
+      dst[0] = acc[a][0];
+      dst[64] = acc[a][1];
+      dst[128] = acc[a][2];
+      dst[192] = acc[a][3];
+    }
+  }
+  if (want_u) {
+    __syncthreads();   // LDS is reused for the row sums of Y u
+#pragma unroll
+    for (int i = 0; i < C::NCH; ++i) lds[rho[i] * C::CH + c] = yu[i];
+    __syncthreads();
+    if (tid < C::SBP) {
+      double sum = 0.0;
+      for (int q = 0; q < C::CH; ++q) sum += lds[tid * C::CH + q];
+      glb(part)[C::NBLK * 256 + tid] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // NB = 16 fed by LDS-DMA loads (gfx950 global_load_lds_dwordx4): the tile goes
 // from global memory straight into LDS, so there are no staging registers and
 // no ds_write instructions.  A DMA instruction writes 64 consecutive 16-byte

@@ -29,6 +29,21 @@ __global__ __launch_bounds__((Cfg<NB, RPW>::THREADS)) void gram_f64_kernel(
                      partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP), aligned, lds);
 }
 
+template <int NB>
+__global__ __launch_bounds__((Cfg<NB, 2>::THREADS)) void gram_f64_dma_kernel(
+    const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
+    int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
+    int64_t pstride) {
+  using C = Cfg<NB, 2>;
+  __shared__ __attribute__((aligned(16))) double lds[DN<NB>::LDS];
+  idx += (int64_t)blockIdx.y * m;
+  partials += (int64_t)blockIdx.y * pstride;
+  const int64_t k_begin = (int64_t)blockIdx.x * chunk;
+  const int64_t k_end = std::min(cols, k_begin + chunk);
+  gram_slab_dma<NB>(A, ld, k_begin, k_end, idx, m, u,
+                    partials + (int64_t)blockIdx.x * (C::NBLK * 256 + C::SBP), lds);
+}
+
 __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
     const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
     int m, const double* __restrict__ u, int64_t chunk, double* __restrict__ partials,
@@ -113,6 +128,13 @@ hipError_t launch_nb(const GramPlan& p, const double* A, int64_t ld, int64_t col
       return hipGetLastError();
     }
   }
+  if constexpr (NB <= 8 && RPW == 2) {
+    if (p.rpw == 1 && aligned) {
+      hipLaunchKernelGGL((gram_f64_dma_kernel<NB>), grid, dim3(Cfg<NB, 2>::THREADS), 0, st, A,
+                         ld, cols, idx, m, u, p.chunk, partials, pstride);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((gram_f64_kernel<NB, RPW>), grid, dim3(Cfg<NB, RPW>::THREADS), 0, st, A, ld,
                      cols, idx, m, u, p.chunk, partials, pstride, aligned);
   return hipGetLastError();
@@ -169,12 +191,10 @@ GramPlan plan_gram_f64(int m, int64_t cols) {
   // Eight waves with two block rows each.  Four waves with four rows each (one
   // wave per SIMD, accumulators in AGPRs) measured slower at nb = 8 (30.9 vs
   // 38.3 TFLOP/s) and does not fit the registers at nb = 16.
-  p.rpw = 2;
-  if (nb == 16) {
-    // rpw = 1: the LDS-DMA variant of the same decomposition (aligned A only).
-    const char* env = std::getenv("CABCD_GRAM_DMA");
-    p.rpw = (env != nullptr && std::atoi(env) == 0) ? 2 : 1;
-  }
+  // rpw = 1: the LDS-DMA variant of the same decomposition (aligned A only;
+  // CABCD_GRAM_DMA=0 selects the register-fed kernels instead).
+  const char* env = std::getenv("CABCD_GRAM_DMA");
+  p.rpw = (env != nullptr && std::atoi(env) == 0) ? 2 : 1;
   return p;
 }
 

@@ -52,7 +52,11 @@ def test_sampler_bit_exact(gpu_lib, seed, h0, count, b, rng):
                                     # LDS-DMA path (128 < m <= 256, even cols): one, two
                                     # and three tiles per slab, a partial last tile
                                     (129, 16), (256, 32), (256, 48), (160, 1000),
-                                    (250, 4098)])
+                                    (250, 4098),
+                                    # LDS-DMA path for m <= 128 (even cols): every block
+                                    # class, several tiles per slab, partial tiles
+                                    (8, 770), (32, 4096), (20, 5000), (64, 2048),
+                                    (128, 778), (100, 40000), (128, 65536)])
 def test_gram_matches_oracle(gpu_lib, m, cols):
     _say("gram", m, cols)
     rows = max(m + 3, 40)
