@@ -389,15 +389,25 @@ __device__ __forceinline__ void gram_slab_dma(const double* __restrict__ A, int6
 
   // DMA instruction i of this wave fills slots (4 wave + i) * 64 + lane:
   // row slot / CH, position slot % CH, chunk position ^ (row % 16).
+  // Rows past m (padding of the last block row) are never loaded: they are
+  // zeroed once in both buffers.
   gptr<const double> src[D::DMA_PER_WAVE];
   int cofs[D::DMA_PER_WAVE];
+  bool live[D::DMA_PER_WAVE];
   const gptr<const double> Ag = glb(A);
 #pragma unroll
   for (int i = 0; i < D::DMA_PER_WAVE; ++i) {
     const int q = (D::DMA_PER_WAVE * wave + i) * 64 + lane;
     const int r = q / C::CH;
     cofs[i] = 2 * ((q % C::CH) ^ (r & 15));
-    src[i] = Ag + (int64_t)idx[r < m ? r : 0] * ld;   // rows past m: any valid row
+    live[i] = r < m;
+    src[i] = Ag + (int64_t)idx[r < m ? r : 0] * ld;
+    if (!live[i]) {
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl)
+        *reinterpret_cast<double2*>(lds + sl * D::TILE + (D::DMA_PER_WAVE * wave + i) * 128 +
+                                    2 * lane) = double2{0.0, 0.0};
+    }
   }
   const bool want_u = u != nullptr;
   const gptr<const double> ug = glb(u);
@@ -410,7 +420,9 @@ __device__ __forceinline__ void gram_slab_dma(const double* __restrict__ A, int6
     for (int i = 0; i < D::DMA_PER_WAVE; ++i) {
       double* dst = T + (D::DMA_PER_WAVE * wave + i) * 128;   // 64 slots of 2 doubles
       const int64_t k = k0 + cofs[i];
-      if (full) {
+      if (!live[i]) {
+        // padding row: stays zero
+      } else if (full) {
         __builtin_amdgcn_global_load_lds((glb_vptr)(src[i] + k), (lds_vptr)dst, 16, 0, 0);
       } else {
         double2 v;

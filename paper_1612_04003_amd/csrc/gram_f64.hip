@@ -58,7 +58,7 @@ __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
 }
 
 constexpr int kRedElems = 64;    // partial entries per reduction workgroup
-constexpr int kRedGroups = 4;    // split groups per entry (one wave each)
+constexpr int kRedGroups = 16;   // split groups per entry (one wave each)
 
 // Step blockIdx.y: partials + step * nsplit * pstride, idx + step * m,
 // G + step * m * m (Yu is NULL for several steps).
@@ -162,11 +162,16 @@ GramPlan plan_gram_f64(int m, int64_t cols) {
   const double pbytes_per = ((double)p.nblk * 256 + 16.0 * nb) * 8.0;
   double best = 1e300;
   int64_t best_chunk = cols;
+  // A CU streams at most its share of the HBM rate, so fewer slabs than CUs
+  // leave bandwidth unused.
+  auto hbm_time = [&](int64_t nsplit) {
+    return ybytes / (hbm * std::min(1.0, (double)nsplit / 256.0));
+  };
   for (int64_t chunk = p.kt; ; chunk *= 2) {
     const int64_t nsplit = (cols + chunk - 1) / chunk;
     const double per_wg = 2.0 * ((double)chunk / (4.0 * kg)) * nacc * 64.0 / clock;
     const double rounds = std::ceil((double)nsplit / 256.0);
-    const double t = std::max(rounds * per_wg, ybytes / hbm) +
+    const double t = std::max(rounds * per_wg, hbm_time(nsplit)) +
                      2.0 * nsplit * pbytes_per / hbm + (nsplit > 1024 ? 1e-3 : 0.0);
     if (t < best) {
       best = t;
@@ -180,7 +185,7 @@ GramPlan plan_gram_f64(int m, int64_t cols) {
     chunk = ((chunk + p.kt - 1) / p.kt) * p.kt;
     const int64_t nsplit = (cols + chunk - 1) / chunk;
     const double per_wg = 2.0 * ((double)chunk / (4.0 * kg)) * nacc * 64.0 / clock;
-    const double t = std::max(per_wg, ybytes / hbm) + 2.0 * nsplit * pbytes_per / hbm;
+    const double t = std::max(per_wg, hbm_time(nsplit)) + 2.0 * nsplit * pbytes_per / hbm;
     if (t < best) {
       best = t;
       best_chunk = chunk;
