@@ -249,6 +249,16 @@ __device__ __noinline__ void gram_call_dma16(const double* A, int64_t ld, int64_
                         uni_ptr(u), uni_ptr(part), dyn_sm);
 }
 
+// NB <= 8 fed by LDS-DMA (16-byte aligned A, even ld).
+template <int NB>
+__device__ __noinline__ void gram_call_dma(const double* A, int64_t ld, int64_t k0, int64_t k1,
+                                           const int32_t* idx, int m, const double* u,
+                                           double* part) {
+  extern __shared__ __attribute__((aligned(16))) double dyn_sm[];
+  gdev::gram_slab_dma<NB>(uni_ptr(A), uni64(ld), uni64(k0), uni64(k1), uni_ptr(idx), uni(m),
+                          uni_ptr(u), uni_ptr(part), dyn_sm);
+}
+
 template <int NB>
 __device__ __noinline__ void gram_call(const double* A, int64_t ld, int64_t k0, int64_t k1,
                                        const int32_t* idx, int m, const double* u, double* part,
@@ -276,11 +286,24 @@ __device__ __forceinline__ void gram_any(int nb, const void* A, int64_t ld, int6
                                          double* part, int aligned) {
   if constexpr (FMT == CABCD_F64) {
     const double* a = static_cast<const double*>(A);
+    const bool dma = uni(aligned) != 0;
     switch (nb) {
-      case 1: gram_call<1>(a, ld, k0, k1, idx, m, u, part, aligned); break;
-      case 2: gram_call<2>(a, ld, k0, k1, idx, m, u, part, aligned); break;
-      case 4: gram_call<4>(a, ld, k0, k1, idx, m, u, part, aligned); break;
-      case 8: gram_call<8>(a, ld, k0, k1, idx, m, u, part, aligned); break;
+      case 1:
+        if (dma) gram_call_dma<1>(a, ld, k0, k1, idx, m, u, part);
+        else gram_call<1>(a, ld, k0, k1, idx, m, u, part, aligned);
+        break;
+      case 2:
+        if (dma) gram_call_dma<2>(a, ld, k0, k1, idx, m, u, part);
+        else gram_call<2>(a, ld, k0, k1, idx, m, u, part, aligned);
+        break;
+      case 4:
+        if (dma) gram_call_dma<4>(a, ld, k0, k1, idx, m, u, part);
+        else gram_call<4>(a, ld, k0, k1, idx, m, u, part, aligned);
+        break;
+      case 8:
+        if (dma) gram_call_dma<8>(a, ld, k0, k1, idx, m, u, part);
+        else gram_call<8>(a, ld, k0, k1, idx, m, u, part, aligned);
+        break;
       default:
         if (uni(aligned)) gram_call_dma16(a, ld, k0, k1, idx, m, u, part);
         else gram_call<16>(a, ld, k0, k1, idx, m, u, part, aligned);
@@ -849,6 +872,8 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
     area = std::max<int>(area, gdev::Cfg<16, 2>::LDS);
     area = std::max<int>(area, gdev::Cfg<1, 2>::LDS);
     area = std::max<int>(area, gdev::D16::LDS);
+    area = std::max<int>(area, std::max(gdev::DN<1>::LDS, gdev::DN<2>::LDS));
+    area = std::max<int>(area, std::max(gdev::DN<4>::LDS, gdev::DN<8>::LDS));
   } else {
     const int lp = B->dtype == CABCD_BF16
                        ? std::max(ldev::LpCfg<16, CABCD_BF16>::LDS, ldev::LpCfg<1, CABCD_BF16>::LDS)
