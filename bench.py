@@ -452,6 +452,17 @@ def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, chea
             k = f"b{i['b']}s{i['s']}"
             pairs[k] = pairs.get(k, 0) + 1
         rec["bs_choices"] = pairs
+        # streamed bytes per problem: every outer step reads the gathered rows
+        # twice (Gram, deferred update) plus r; an exact recomputation (a full
+        # pass over X) at every (cheap + 1)-th monitor point
+        e = 8 if name == "f64" else 2
+        byts = 0.0
+        for p, i in enumerate(infos):
+            sb_p, n_p, st_p = i["b"] * i["s"], ns[p], i["steps"]
+            exact = st_p // (monitor * (cheap + 1))
+            byts += st_p * (2.0 * sb_p * n_p * e + 16.0 * n_p) + exact * (ds[p] * n_p * e + 16.0 * n_p)
+        rec["stream_gb"] = round(byts / 1e9, 2)
+        rec["hbm_gbs"] = round(byts / max(t2 - t1, 1e-9) / 1e9, 1)
         log(f"batched {name}: {rec}")
         if name == "f64" and baseline:
             # one problem at a time, same (b, s), same stopping rule
