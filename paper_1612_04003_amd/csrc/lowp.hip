@@ -110,6 +110,8 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
 // thread t decodes chunk t % 16 of rows t / 16 + 32 j (j < 8) against the
 // tile's u segment (DMA'd beside the rows) and keeps one FP64 sum per row;
 // the sixteen chunk sums of a row are added in chunk order at the end.
+__host__ __device__ constexpr int blk_index16(int r, int c) { return r * (r + 1) / 2 + c; }
+
 template <int FMT>
 struct LD16 {
   static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;   // element bytes
@@ -125,6 +127,56 @@ struct LD16 {
   static constexpr int UDMA = UB / 1024;                 // 1 (BF16) or 2 (FP8)
 };
 
+// Blocks of the 16 x 16 block triangle by wave, in 4 x 4 super-blocks: waves
+// 0-5 take the six off-diagonal super-blocks (16 blocks, 4 row and 4 column
+// fragments per k-step), waves 6 and 7 two diagonal ones each (10 + 10
+// blocks, 4 + 4 fragments).  Every wave reads 8 fragments per k-step where
+// block-row pairs read 18, so the tile is read from LDS less than half as
+// often; waves 6 and 7 carry 20 instead of 17 blocks.
+constexpr int kSbI[6] = {1, 2, 3, 2, 3, 3};
+constexpr int kSbJ[6] = {0, 0, 0, 1, 1, 2};
+__host__ __device__ constexpr int lp16_sb_nacc(int W) { return W < 6 ? 16 : 20; }
+__host__ __device__ constexpr int lp16_sb_block(int W, int a) {
+  if (W < 6) return blk_index16(4 * kSbI[W] + a / 4, 4 * kSbJ[W] + a % 4);
+  const int d = a < 10 ? (W == 6 ? 0 : 1) : (W == 6 ? 3 : 2);
+  const int t = a % 10;                        // t = r (r + 1) / 2 + c, c <= r < 4
+  const int r = t < 1 ? 0 : t < 3 ? 1 : t < 6 ? 2 : 3;
+  return blk_index16(4 * d + r, 4 * d + t - r * (r + 1) / 2);
+}
+
+// One k-step of wave W's blocks: frag(r) gives the fragment of block row r,
+// mma(row, col, acc) one matrix instruction.
+template <int W, class Frag, class Mma>
+__device__ __forceinline__ void lp16_sb_step(Frag frag, Mma mma, f4 (&acc)[20]) {
+  if constexpr (W < 6) {
+    constexpr int I = kSbI[W], J = kSbJ[W];
+    decltype(frag(0)) rf[4], cf[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) rf[a] = frag(4 * I + a);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cf[b] = frag(4 * J + b);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[4 * a + b] = mma(rf[a], cf[b], acc[4 * a + b]);
+  } else {
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      const int d = di == 0 ? (W == 6 ? 0 : 1) : (W == 6 ? 3 : 2);
+      decltype(frag(0)) f[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) f[a] = frag(4 * d + a);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+          const int i = 10 * di + r * (r + 1) / 2 + c;
+          acc[i] = mma(f[r], f[c], acc[i]);
+        }
+    }
+  }
+}
+
 template <int FMT, int W>
 __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t ld,
                                           int64_t k_begin, int64_t k_end, const int32_t* idx,
@@ -133,7 +185,6 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   using C = LD16<FMT>;
   typedef __attribute__((address_space(3))) void* lds_vptr;
   typedef __attribute__((address_space(1))) const void* glb_vptr;
-  constexpr int R1 = W, R2 = 15 - W;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int ntiles = (int)((k_end - k_begin + C::KT - 1) / C::KT);
@@ -220,9 +271,9 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
     lane_off[w] = (lane & 15) * C::RB + 16 * (ch ^ (lane & 15));
   }
 
-  f4 acc[17];
+  f4 acc[20];
 #pragma unroll
-  for (int a = 0; a < 17; ++a) acc[a] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int a = 0; a < 20; ++a) acc[a] = f4{0.f, 0.f, 0.f, 0.f};
   // Y u: chunk yc of rows yr0 + 32 j
   const int yc = tid & 15, yr0 = tid >> 4;
   double yu[8];
@@ -235,39 +286,23 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) issue(t + 1, (t + 1) & 1);
     const uint8_t* tile = lds + (t & 1) * C::BUF;
-    if constexpr (FMT == CABCD_BF16) {
+    // 4 windows (BF16, K = 32) or 2 halves (FP8, K = 128) per tile
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const uint8_t* base = tile + lane_off[w];
-        auto frag = [&](int r) { return *reinterpret_cast<const uint4*>(base + r * 16 * C::RB); };
-        const uint4 f1 = frag(R1);
-        const uint4 f2 = frag(R2);
-#pragma unroll
-        for (int c = 0; c <= R2; ++c) {
-          const uint4 fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-          if (c <= R1) acc[c] = lp_mma_bf16(f1, fc, acc[c]);
-          acc[R1 + 1 + c] = lp_mma_bf16(f2, fc, acc[R1 + 1 + c]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < (FMT == CABCD_BF16 ? 4 : 2); ++h) {
+      if constexpr (FMT == CABCD_BF16) {
+        const uint8_t* base = tile + lane_off[h];
+        lp16_sb_step<W>([&](int r) {
+          return *reinterpret_cast<const uint4*>(base + r * 16 * C::RB);
+        }, [](const uint4& x, const uint4& y, f4 c) { return lp_mma_bf16(x, y, c); }, acc);
+      } else {
         const uint8_t* b0 = tile + lane_off[2 * h];
         const uint8_t* b1 = tile + lane_off[2 * h + 1];
-        auto frag = [&](int r) {   // 32 codes of row r: two 16-byte chunks
+        lp16_sb_step<W>([&](int r) {   // 32 codes of row r: two 16-byte chunks
           const uint4 x = *reinterpret_cast<const uint4*>(b0 + r * 16 * C::RB);
           const uint4 y = *reinterpret_cast<const uint4*>(b1 + r * 16 * C::RB);
           return lp_i8v{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z,
                         (int)y.w};
-        };
-        const lp_i8v f1 = frag(R1);
-        const lp_i8v f2 = frag(R2);
-#pragma unroll
-        for (int c = 0; c <= R2; ++c) {
-          const lp_i8v fc = c == R1 ? f1 : (c == R2 ? f2 : frag(c));
-          if (c <= R1) acc[c] = lp_mma_k128(f1, fc, acc[c]);
-          acc[R1 + 1 + c] = lp_mma_k128(f2, fc, acc[R1 + 1 + c]);
-        }
+        }, [](const lp_i8v& x, const lp_i8v& y, f4 c) { return lp_mma_k128(x, y, c); }, acc);
       }
     }
     if (want_u) {
@@ -294,8 +329,8 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   gptr<double> pg = glb(part);
   const gptr<float> pf = (gptr<float>)pg;
 #pragma unroll
-  for (int a = 0; a < 17; ++a) {
-    gptr<float> dst = pf + lp_acc_block<16>(W, a) * 256 + lane;
+  for (int a = 0; a < lp16_sb_nacc(W); ++a) {
+    gptr<float> dst = pf + lp16_sb_block(W, a) * 256 + lane;
     dst[0] = acc[a][0];
     dst[64] = acc[a][1];
     dst[128] = acc[a][2];
