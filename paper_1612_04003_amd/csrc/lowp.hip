@@ -441,17 +441,18 @@ __global__ __launch_bounds__(kLvThreads) void gemv_t_lp_kernel(
 #pragma unroll
   for (int e = 0; e < EPC; ++e) acc[e] = 0.0;
   int64_t p = 0;
-  for (; p + 4 <= m; p += 4) {
-    uint4 x[4];
-    double c[4];
+  constexpr int RIF = 8;   // rows in flight
+  for (; p + RIF <= m; p += RIF) {
+    uint4 x[RIF];
+    double c[RIF];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < RIF; ++q) {
       const int64_t row = idx ? (int64_t)idx[p + q] : p + q;
       c[q] = v[p + q] * (rs ? (double)rs[row] : 1.0);
       x[q] = lp_load<FMT>(A + row * ld * ES, k, cols, aligned != 0);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < RIF; ++q) {
       double dv[EPC];
       lp_decode_all<FMT>(x[q], dv);
 #pragma unroll
