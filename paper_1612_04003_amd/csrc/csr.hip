@@ -138,6 +138,143 @@ __global__ __launch_bounds__(kCsrThreads) void csr_gram_kernel(
   }
 }
 
+// The Grams of several outer steps (no Y u) with kTP gathered rows per
+// workgroup: the hash table maps a column to the values of the tile's rows at
+// that column (zero where a row lacks it), so each probed row q is read once
+// per tile instead of once per row of the tile, and one probe feeds kTP
+// products.  Lane j of wave w keeps the kTP sums of rows q = w + W j (+ 256
+// per batch) across table fills; chunks of the tile's entries are added in
+// chunk order, so the result is deterministic.
+constexpr int kTP = 3;                      // gathered rows per workgroup
+constexpr int kTSlots = 2048;               // power of two
+constexpr int kTChunk = kTSlots / 2;        // tile entries per table fill
+constexpr int kTMaxRows = 512;              // m of this kernel
+
+__device__ __forceinline__ unsigned hash_col_t(int c) {
+  return ((unsigned)c * 2654435761u) >> (32 - 11);   // log2(kTSlots) = 11
+}
+
+__global__ __launch_bounds__(kCsrThreads) void csr_gram_tile_kernel(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ vals, const int32_t* __restrict__ idx, int m,
+    int64_t idx_stride, double scale, double shift, int overlap, double* __restrict__ G,
+    int64_t g_stride) {
+  __shared__ int keys[kTSlots];
+  __shared__ double hv[kTSlots][kTP];
+  __shared__ int64_t ext[2][kTMaxRows];     // row extents of the gathered rows
+  idx += (int64_t)blockIdx.y * idx_stride;
+  G += (int64_t)blockIdx.y * g_stride;
+  const int ntile = (m + kTP - 1) / kTP;
+  const int p0 = kTP * (ntile - 1 - (int)blockIdx.x);   // the longest triangles start first
+  const int qmax = min(m, p0 + kTP);                      // rows q < qmax meet the tile
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int q = threadIdx.x; q < qmax; q += kCsrThreads) {
+    const int iq = idx[q];
+    ext[0][q] = rowptr[iq];
+    ext[1][q] = rowptr[iq + 1];
+  }
+  __syncthreads();
+  // the tile's entries, row after row: row i starts at tbeg[i]
+  int64_t tbeg[kTP + 1];
+  tbeg[0] = 0;
+#pragma unroll
+  for (int i = 0; i < kTP; ++i)
+    tbeg[i + 1] = tbeg[i] + (p0 + i < m ? ext[1][p0 + i] - ext[0][p0 + i] : 0);
+  const int64_t tot = tbeg[kTP];
+
+  double mine[2][kTP];   // q = qb + wave + W lane, batches qb = 0, 256
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int i = 0; i < kTP; ++i) mine[bi][i] = 0.0;
+  for (int64_t c0 = 0;; c0 += kTChunk) {
+    const int64_t c1 = min(tot, c0 + kTChunk);
+    for (int sl = threadIdx.x; sl < kTSlots; sl += kCsrThreads) {
+      keys[sl] = -1;
+#pragma unroll
+      for (int i = 0; i < kTP; ++i) hv[sl][i] = 0.0;
+    }
+    __syncthreads();
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += kCsrThreads) {
+      int i = 0;
+      int64_t eb = 0;                                     // tile row of entry e
+#pragma unroll
+      for (int r = 1; r < kTP; ++r)
+        if (e >= tbeg[r]) {
+          i = r;
+          eb = tbeg[r];
+        }
+      const int64_t k = ext[0][p0 + i] + (e - eb);
+      const int col = colidx[k];
+      unsigned h = hash_col_t(col);
+      for (;;) {
+        const int old = atomicCAS(&keys[h], -1, col);
+        if (old == -1 || old == col) break;
+        h = (h + 1) & (kTSlots - 1);
+      }
+      hv[h][i] = vals[k];   // a column appears once per row: one writer per (slot, row)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int qb = bi * 64 * kCsrWaves;
+      for (int j = 0; j < 64; ++j) {
+        const int q = qb + wave + kCsrWaves * j;
+        if (q >= qmax) break;
+        const int64_t q0 = ext[0][q], q1 = ext[1][q];
+        double t[kTP];
+#pragma unroll
+        for (int i = 0; i < kTP; ++i) t[i] = 0.0;
+        for (int64_t kb = q0 + lane; kb < q1; kb += 64 * kProbeU) {
+          int col[kProbeU];
+          double val[kProbeU];
+#pragma unroll
+          for (int u = 0; u < kProbeU; ++u) {
+            const int64_t k = kb + 64 * u;
+            col[u] = k < q1 ? colidx[k] : -1;
+            val[u] = k < q1 ? vals[k] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kProbeU; ++u) {
+            if (col[u] < 0) continue;
+            unsigned h = hash_col_t(col[u]);
+            int key;
+            while ((key = keys[h]) != col[u] && key != -1) h = (h + 1) & (kTSlots - 1);
+            if (key == col[u]) {
+#pragma unroll
+              for (int i = 0; i < kTP; ++i) t[i] = fma(val[u], hv[h][i], t[i]);
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kTP; ++i) {
+          const double r = wave_sum(t[i]);
+          if (lane == j) mine[bi][i] += r;
+        }
+      }
+    }
+    __syncthreads();
+    if (c1 >= tot) break;
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+    const int q = bi * 64 * kCsrWaves + wave + kCsrWaves * lane;
+    if (q < qmax) {
+#pragma unroll
+      for (int i = 0; i < kTP; ++i) {
+        const int p = p0 + i;
+        if (p < m && q <= p) {
+          const bool on = overlap ? (idx[q] == idx[p]) : (q == p);
+          const double v = scale * mine[bi][i] + (on ? shift : 0.0);
+          G[(int64_t)p * m + q] = v;
+          G[(int64_t)q * m + p] = v;
+        }
+      }
+    }
+  }
+}
+
 // out[col] += gamma * v[p] * A[row(p)][col] for the entries of rows p < m.
 __global__ __launch_bounds__(kCsrThreads) void csr_scatter_kernel(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
@@ -220,6 +357,12 @@ hipError_t launch_csr_gram_steps(const CsrView& A, const int32_t* idx, int m, in
                                  double scale, double shift, bool overlap, double* G,
                                  hipStream_t st) {
   if (m < 1 || m > kMaxRows || nsteps < 1 || nsteps > 65535) return hipErrorInvalidValue;
+  if (m >= 64 && m <= kTMaxRows) {   // small steps: one row per workgroup keeps more of them
+    hipLaunchKernelGGL(csr_gram_tile_kernel, dim3((m + kTP - 1) / kTP, nsteps), dim3(kCsrThreads),
+                       0, st, A.rowptr, A.colidx, A.vals, idx, m, (int64_t)m, scale, shift,
+                       overlap ? 1 : 0, G, (int64_t)m * m);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(csr_gram_kernel, dim3(m, nsteps), dim3(kCsrThreads), 0, st, A.rowptr,
                      A.colidx, A.vals, idx, m, (int64_t)m, nullptr, scale, shift,
                      overlap ? 1 : 0, G, (int64_t)m * m, nullptr);
