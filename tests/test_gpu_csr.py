@@ -68,6 +68,20 @@ def zipf_small():
     return A, y
 
 
+def test_csr_long_rows_tile_chunks(gpu_lib):
+    """Rows of 600 entries: the three rows of a Gram tile exceed one hash-table
+    fill, so their entries are taken in chunks whose sums are added."""
+    _say("csr long rows")
+    rowptr, colidx, vals, y, _ = synth.zipf_csr_ridge(300, 1 << 14, 600, 1009)
+    A = scipy.sparse.csr_matrix((vals, colidx, rowptr), shape=(300, 1 << 14))
+    XT = gpu_lib.CSR.from_scipy(A, DEV)
+    lam, b, s, H, seed = 1e-3, 16, 4, 48, 5
+    a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), lam, b, s, H, seed)
+    ao, wo = bcd.dual_bcd(A.T.tocsc(), y, lam, b, s, H, seed)
+    assert _rel(a.cpu(), ao) <= 1e-10
+    assert _rel(w.cpu(), wo) <= 1e-10
+
+
 @pytest.mark.parametrize("s", [1, 8, 32])
 def test_csr_dual_matches_oracle(gpu_lib, zipf_small, s):
     _say("csr dual", s)
