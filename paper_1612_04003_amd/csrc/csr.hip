@@ -216,22 +216,27 @@ __global__ __launch_bounds__(kCsrThreads) void csr_gram_tile_kernel(
       hv[h][i] = vals[k];   // a column appears once per row: one writer per (slot, row)
     }
     __syncthreads();
+    // A wave takes four probed rows at a time, sixteen lanes each, so the
+    // per-row sums need four shuffle steps inside a sixteen-lane group; lane
+    // 4 jj + s then collects the sums of group s.
+    const int sub = lane >> 4, l16 = lane & 15;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
       const int qb = bi * 64 * kCsrWaves;
-      for (int j = 0; j < 64; ++j) {
-        const int q = qb + wave + kCsrWaves * j;
-        if (q >= qmax) break;
-        const int64_t q0 = ext[0][q], q1 = ext[1][q];
+      for (int jj = 0; jj < 16; ++jj) {
+        if (qb + wave + kCsrWaves * 4 * jj >= qmax) break;   // no row of this quartet
+        const int q = qb + wave + kCsrWaves * (4 * jj + sub);
+        const bool live = q < qmax;
+        const int64_t q0 = live ? ext[0][q] : 0, q1 = live ? ext[1][q] : 0;
         double t[kTP];
 #pragma unroll
         for (int i = 0; i < kTP; ++i) t[i] = 0.0;
-        for (int64_t kb = q0 + lane; kb < q1; kb += 64 * kProbeU) {
+        for (int64_t kb = q0 + l16; kb < q1; kb += 16 * kProbeU) {
           int col[kProbeU];
           double val[kProbeU];
 #pragma unroll
           for (int u = 0; u < kProbeU; ++u) {
-            const int64_t k = kb + 64 * u;
+            const int64_t k = kb + 16 * u;
             col[u] = k < q1 ? colidx[k] : -1;
             val[u] = k < q1 ? vals[k] : 0.0;
           }
@@ -249,8 +254,10 @@ __global__ __launch_bounds__(kCsrThreads) void csr_gram_tile_kernel(
         }
 #pragma unroll
         for (int i = 0; i < kTP; ++i) {
-          const double r = wave_sum(t[i]);
-          if (lane == j) mine[bi][i] += r;
+          double r = t[i];
+          for (int off = 1; off < 16; off <<= 1) r += __shfl_xor(r, off, 64);
+          const double g = __shfl(r, (lane & 3) << 4, 64);
+          if ((lane >> 2) == jj) mine[bi][i] += g;
         }
       }
     }
