@@ -328,7 +328,7 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
       if (j_of == j) R[u] = rhs;
       lds_barrier();
       if (p < b && j < s) {
-        const double* g = Gi + ((size_t)j * BP + p) * BP;
+        const double* g = Gi + (size_t)j * C::GS + p * BP;
         double t = 0.0;
 #pragma unroll
         for (int v = 0; v < BP; ++v) t += g[v] * R[v];

@@ -125,6 +125,28 @@ def test_csr_primal_matches_oracle(gpu_lib):
     assert abs(f.item() - bcd.primal_objective(S, y, 1e-2, w.cpu().numpy())) <= 1e-12 * f.item()
 
 
+def test_csr_repeated_indices_row_per_thread(gpu_lib):
+    # s b = 450 rows over 50 samples (dual) or 40 features (primal): every
+    # index repeats about ten times, and s * 4 lanes exceed one 512-thread
+    # workgroup, so the solve takes one row per thread
+    _say("csr repeated indices")
+    rng = np.random.default_rng(12)
+    S = _random_csr(50, 2000, 0.05, 12, long_rows=(3,), empty_rows=(7,))
+    y = rng.standard_normal(50)
+    XT = gpu_lib.CSR.from_scipy(S, DEV)
+    a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), 1e-2, 3, 150, 300, 11)
+    ao, wo = bcd.dual_bcd(S.T.tocsc(), y, 1e-2, 3, 150, 300, 11)
+    assert _rel(a.cpu(), ao) <= 1e-10
+    assert _rel(w.cpu(), wo) <= 1e-10
+    P = _random_csr(40, 3000, 0.05, 13)
+    yp = rng.standard_normal(3000)
+    X = gpu_lib.CSR.from_scipy(P, DEV)
+    wp, rp = gpu_lib.primal_bcd(X, torch.tensor(yp, device=DEV), 1e-2, 3, 150, 300, 12)
+    wpo, zpo = bcd.primal_bcd(P, yp, 1e-2, 3, 150, 300, 12)
+    assert _rel(wp.cpu(), wpo) <= 1e-10
+    assert _rel(rp.cpu(), zpo - yp) <= 1e-10
+
+
 def test_csr_malformed_is_rejected(gpu_lib):
     _say("csr malformed")
     S = _random_csr(50, 200, 0.05, 1)

@@ -101,6 +101,8 @@ PRIMAL_CASES = [
     (20, 333, 3, 5, 23, 0.05, 3),          # odd n (unaligned rows), overlapping blocks
     (40, 777, 16, 16, 33, 1e-3, 9),        # sb = 256, overlaps across blocks
     (9, 50, 9, 1, 2, 0.1, 1),              # b = d: one Newton step
+    (10, 400, 8, 32, 70, 0.1, 4),          # sb = 256 over 10 coordinates: ~25 repeats each
+    (30, 300, 17, 15, 40, 0.1, 8),         # b = 17, one row per thread: ~8.5 repeats each
 ]
 
 
@@ -233,6 +235,7 @@ DUAL_CASES = [
     (500, 300, 16, 8, 45, 1e-3, 5),        # d > n: the dual's natural shape
     (77, 1001, 5, 7, 33, 1e-2, 2),         # odd d (unaligned rows of X^T)
     (12, 30, 30, 1, 2, 0.03, 1),           # b' = n: one exact step
+    (40, 12, 4, 32, 40, 0.1, 6),           # 128 rows over 12 samples: ~11 repeats each
 ]
 
 
