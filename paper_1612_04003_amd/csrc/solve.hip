@@ -55,9 +55,8 @@ size_t solve_lds_bytes(int m, int b) {
   const int bp = pow2_at_least(b);
   const int s = (m + b - 1) / b;
   const int slots = std::max(kHashMin, pow2_at_least(2 * m));
-  const size_t gi = std::max((size_t)s * (bp * bp + 1),
-                             ((size_t)slots * 3 * sizeof(int) + 7) / sizeof(double));
-  return sizeof(double) * (gi + (size_t)bp + (size_t)s * bp) + sizeof(int) * (size_t)m;
+  const size_t gi = std::max((size_t)s * (bp * bp + 1), sdev::hash_doubles(m, slots));
+  return sizeof(double) * (gi + (size_t)bp + (size_t)s * bp);
 }
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t st) {

@@ -29,8 +29,10 @@
 //     only, so the prefetches stay in flight; vectors in LDS are zero-padded to
 //     BP so every read is unconditional;
 //  4. delta written out, and x[idx] += delta: an LDS hash of the indices gives
-//     each coordinate's first occurrence and count; the first occurrence adds
-//     the duplicates in block order (single writer).
+//     each coordinate's first occurrence and count; the rows whose index
+//     repeats are compacted, in row order, into a short LDS list, and the
+//     first occurrence adds its duplicates from that list in block order
+//     (single writer).
 #pragma once
 
 #include "internal.h"
@@ -102,6 +104,13 @@ __device__ __forceinline__ void gj_invert(double (&e)[SolveCfg<BP>::EPL], int la
 }
 
 constexpr int kHashMin = 2048;   // LDS hash slots for the scatter (>= 2 m)
+constexpr int kMaxSolveWaves = 16;
+// Doubles of LDS that phase 4 of the solve uses: the hash table (key, first
+// row, count per slot), the list of repeated rows (two ints per row) and the
+// per-wave counts.
+__host__ __device__ constexpr size_t hash_doubles(int m, int slots) {
+  return (((size_t)slots * 3 + (size_t)m * 2 + kMaxSolveWaves) * sizeof(int) + 7) / sizeof(double);
+}
 
 __device__ __forceinline__ unsigned hash_idx(int i, int slots) {
   return ((unsigned)i * 2654435761u) & (unsigned)(slots - 1);
@@ -193,15 +202,13 @@ template <int BP, int PF, int THREADS, int MAP = 0>
 __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   using C = SolveCfg<BP>;
   const int m = a.m, b = a.b, s = a.s;
-  // LDS: Ginv [s][BP][BP] (reused as the hash table in phase 4), R [BP],
-  // Dl [s][BP] (zero-padded delta), Ix [m]
+  // LDS: Ginv [s][BP][BP] (reused by phase 4: hash table, list of repeated
+  // indices, per-wave counts), R [BP], Dl [s][BP] (zero-padded delta)
   const int slots = std::max(kHashMin, pow2_at_least(2 * m));
-  const size_t gi_doubles =
-      std::max((size_t)s * C::GS, ((size_t)slots * 3 * sizeof(int) + 7) / sizeof(double));
+  const size_t gi_doubles = std::max((size_t)s * C::GS, hash_doubles(m, slots));
   double* Gi = sm;
   double* R = Gi + gi_doubles;
   double* Dl = R + BP;
-  int* Ix = reinterpret_cast<int*>(Dl + (size_t)s * BP);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -263,7 +270,6 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   }
   double rhs = 0.0;
   if (active) {
-    Ix[p] = ip;
     const double xi = glb(a.x)[ip];
     rhs = a.mode == 0 ? (-a.lambda * xi - yu / a.n) : ((yu - xi - glb(a.y)[ip]) / a.n);
   }
@@ -346,10 +352,14 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
     }
   }
 
-  // ---- phase 4: outputs.  Gi is free now and holds the hash table.
+  // ---- phase 4: outputs.  Gi is free now and holds the hash table, the
+  // list of rows whose index repeats ({index, delta slot}, in row order) and
+  // the per-wave counts of that list.
   int* hkey = reinterpret_cast<int*>(Gi);
   int* hmin = hkey + slots;
   int* hcnt = hmin + slots;
+  int2* dup = reinterpret_cast<int2*>(hcnt + slots);   // slots is even: 8-byte aligned
+  int* wcnt = reinterpret_cast<int*>(dup + m);
   for (int q = tid; q < slots; q += THREADS) {
     hkey[q] = -1;
     hmin[q] = INT_MAX;
@@ -358,8 +368,9 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   lds_barrier();
   unsigned h = 0;
   double dp = 0.0;
+  const int dslot = j_of >= 0 ? j_of * BP + u : 0;
   if (active) {
-    dp = Dl[j_of * BP + u];
+    dp = Dl[dslot];
     glb(a.delta)[p] = dp;
     if (!isfinite(dp)) *glb(a.status) = DEV_NONFINITE;
     h = hash_idx(ip, slots);
@@ -372,14 +383,40 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
     atomicAdd(&hcnt[h], 1);
   }
   lds_barrier();
+  // Row order is thread order (both mappings), so a ballot prefix within the
+  // wave plus the counts of the lower waves places each repeated row.
+  const int cnt = active ? hcnt[h] : 0;
+  const uint64_t bal = __ballot(cnt > 1);
+  const int below = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wcnt[wave] = __popcll(bal);
+  lds_barrier();
+  int pos = below, ndup = 0;
+  for (int w = 0; w < WAVES; ++w) {
+    const int c = wcnt[w];
+    pos += w < wave ? c : 0;
+    ndup += c;
+  }
+  if (cnt > 1) dup[pos] = make_int2(ip, dslot);
+  lds_barrier();
   if (active && hmin[h] == p) {
     const gptr<double> x = glb(a.x);
-    if (hcnt[h] == 1) {
+    if (cnt == 1) {
       x[ip] += dp;
     } else {
-      double acc = x[ip];
-      for (int q = p; q < m; ++q)
-        if (Ix[q] == ip) acc += Dl[(q / b) * BP + q % b];
+      // the later occurrences follow this row in the list, in row order
+      double acc = x[ip] + dp;
+      int need = cnt - 1;
+      for (int k = pos + 1; need > 0 && k < ndup; k += 4) {
+        int2 e[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) e[t] = k + t < ndup ? dup[k + t] : make_int2(-1, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (e[t].x == ip) {
+            acc += Dl[e[t].y];
+            --need;
+          }
+      }
       x[ip] = acc;
     }
   }
