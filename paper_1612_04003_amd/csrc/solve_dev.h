@@ -17,9 +17,10 @@
 //  1. c, and the diagonal blocks of Gov gathered into LDS by the whole
 //     workgroup (one memory round trip);
 //  2. every diagonal block inverted with in-place Gauss-Jordan elimination:
-//     blocks up to 8 x 8 one per lane in registers, larger ones by one wave
-//     with the entries spread over the lanes and exchanged by shuffles (no
-//     LDS round trips, no barriers).  Blocks are padded to BP = 2^k >= b with
+//     blocks up to 8 x 8 one per lane in registers, 16 x 16 blocks four per
+//     wave with one row per lane and the pivot row sent by DPP row broadcasts,
+//     32 x 32 blocks by one wave with the entries spread over the lanes and
+//     exchanged by shuffles (no LDS round trips, no barriers).  Blocks are padded to BP = 2^k >= b with
 //     the identity, whose inverse keeps the padding.  On an SPD matrix the
 //     Gauss-Jordan pivots are the LDL^T pivots, so a pivot <= 0 or NaN is
 //     reported as "not positive definite";
@@ -27,7 +28,9 @@
 //     row subtracts its Gov row segment times delta_j.  Row segments of the
 //     next PF blocks are prefetched into registers; the barriers order LDS
 //     only, so the prefetches stay in flight; vectors in LDS are zero-padded to
-//     BP so every read is unconditional;
+//     BP so every read is unconditional.  The segment loads pass through the
+//     CU's vector cache at its data rate, so a wave stops loading once the
+//     chain has passed its last block (about half the bytes);
 //  4. delta written out, and x[idx] += delta: an LDS hash of the indices gives
 //     each coordinate's first occurrence and count; the rows whose index
 //     repeats are compacted, in row order, into a short LDS list, and the
@@ -39,6 +42,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 namespace cabcd {
 namespace sdev {
@@ -156,6 +160,59 @@ __device__ __forceinline__ void invert_per_lane(double* Gi, int s, int tid, bool
     for (int u = 0; u < BP; ++u)
 #pragma unroll
       for (int v = 0; v < BP; ++v) g[u * BP + v] = e[u][v];
+  }
+}
+
+// x of lane 16 (lane / 16) + K in every lane of that group of sixteen (DPP
+// row broadcast: no LDS round trip).
+template <int K>
+__device__ __forceinline__ double bcast16(double x) {
+  const long bits = __builtin_amdgcn_update_dpp(0l, (long)__double_as_longlong(x), 0x150 + K,
+                                                0xF, 0xF, false);
+  return __longlong_as_double((long long)bits);
+}
+
+// Gauss-Jordan step K.. of a 16 x 16 block held one row per lane (row u in
+// lane u of a group of sixteen); the pivot row r comes to every lane by row
+// broadcasts.  Row K becomes r / r_K, every other row u subtracts
+// (a_uK / r_K) r with its column K cleared first, so column K becomes
+// -a_uK / r_K: one multiply and one FMA per entry (the pivot row takes a zero
+// base and the factor -1 / r_K).
+template <int K>
+__device__ __forceinline__ void gj_rows16(double (&e)[16], int u, bool& bad) {
+  if constexpr (K < 16) {
+    const double piv = bcast16<K>(e[K]);
+    bad |= !(piv > 0.0);
+    const double rp = 1.0 / piv;
+    const bool pivot_row = u == K;
+    const double keep = pivot_row ? 0.0 : 1.0;
+    const double fr = pivot_row ? -rp : e[K] * rp;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const double rv = v == K ? 1.0 : bcast16<K>(e[v]);
+      e[v] = fma(-fr, rv, v == K ? 0.0 : e[v] * keep);
+    }
+    gj_rows16<K + 1>(e, u, bad);
+  }
+}
+
+// The s diagonal 16 x 16 blocks held in Gi inverted in place, four per wave at
+// a time (one per group of sixteen lanes, one row per lane): the four
+// elimination chains run side by side with no shuffles through LDS.
+template <int WAVES>
+__device__ __forceinline__ void invert_rows16(double* Gi, int s, int wave, int lane, bool& bad) {
+  constexpr int GS = SolveCfg<16>::GS;
+  const int u = lane & 15;
+  for (int j0 = wave * 4; j0 < s; j0 += WAVES * 4) {
+    const int bj = j0 + (lane >> 4);
+    double e[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) e[v] = bj < s ? Gi[(size_t)bj * GS + u * 16 + v] : (u == v ? 1.0 : 0.0);
+    gj_rows16<0>(e, u, bad);
+    if (bj < s) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) Gi[(size_t)bj * GS + u * 16 + v] = e[v];
+    }
   }
 }
 
@@ -285,6 +342,8 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   bool bad = false;
   if constexpr (BP <= 8 && THREADS <= 256)
     invert_per_lane<BP, THREADS>(Gi, s, tid, bad);
+  else if constexpr (BP == 16)
+    invert_rows16<WAVES>(Gi, s, wave, lane, bad);
   else
     invert_rounds<BP, (C::EPL == 1 ? 2 : 1), WAVES>(Gi, s, wave, lane, bad);
   if (bad) *glb(a.status) = DEV_NOTSPD;
@@ -298,7 +357,11 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
 #pragma unroll
     for (int v = 0; v < BP; ++v) gi[v] = j_of >= 0 ? Gi[(size_t)j_of * C::GS + u * BP + v] : 0.0;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    for (int j0 = 0; j0 < s; j0 += PF) {
+    // the last block with a row in this wave: once the chain is past it, the
+    // wave needs no more row segments, so it stops loading (the two loops keep
+    // the load counts uniform for the waits)
+    const int jlast = min(s - 1, (64 * wv + 63) / BP);
+    auto rounds = [&](int j0, auto load) {
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         const int j = j0 + q;
@@ -323,9 +386,12 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
           for (int v = 0; v < BP; ++v) acc[v & 1] = fma(ring[q][v], dj[v], acc[v & 1]);
           rhs -= acc[0] + acc[1];
         }
-        ring_load(q, j + PF);
+        if constexpr (decltype(load)::value) ring_load(q, j + PF);
       }
-    }
+    };
+    int j0 = 0;
+    for (; j0 < s && j0 + PF < jlast; j0 += PF) rounds(j0, std::true_type{});
+    for (; j0 < s; j0 += PF) rounds(j0, std::false_type{});
   } else
   for (int j0 = 0; j0 < s; j0 += PF) {
 #pragma unroll
