@@ -425,9 +425,19 @@ hipError_t launch_lp_fmt(const GramPlan& p, const void* A, int64_t ld, int64_t c
 
 // ---------------------------------------------------------------- streaming pass
 // out[k] = (accumulate ? out[k] : beta base[k]) + gamma sum_p s[row(p)] v[p] dec(Q[row(p)][k])
+//
+// Each thread owns 16 bytes of codes per row (EPC columns); the RS threads of
+// a column chunk split the rows into RS consecutive ranges whose sums are
+// added in range order through LDS (deterministic).  FP8 takes two ranges: with
+// 16 columns per thread a pass over 2^20 columns has one wave per SIMD, too few
+// loads in flight to stream (3.6 TB/s; two ranges: 5.7 TB/s, four: 4.7).  BF16
+// (8 columns per thread) already has two waves per SIMD and streams best with
+// one range.  RIF rows are in flight per thread (16 measured slower).
 constexpr int kLvThreads = 256;
+template <int FMT> constexpr int kLvSlices = FMT == CABCD_BF16 ? 1 : 2;
+constexpr int kLvRif = 8;
 
-template <int FMT>
+template <int FMT, int RS>
 __global__ __launch_bounds__(kLvThreads) void gemv_t_lp_kernel(
     const uint8_t* __restrict__ A, int64_t ld, int64_t cols, const float* __restrict__ rs,
     const int32_t* __restrict__ idx, int64_t m, const double* __restrict__ v, double gamma,
@@ -435,14 +445,25 @@ __global__ __launch_bounds__(kLvThreads) void gemv_t_lp_kernel(
     int aligned) {
   constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;
   constexpr int EPC = 16 / ES;
-  const int64_t k = ((int64_t)blockIdx.x * kLvThreads + threadIdx.x) * EPC;
-  if (k >= cols) return;
+  constexpr int CPB = kLvThreads / RS;   // column chunks per workgroup
+  constexpr int RIF = kLvRif;
+  static_assert(CPB % 64 == 0, "a row range is a whole number of waves");
+  const int tc = threadIdx.x % CPB;
+  // the row range is uniform in a wave, so the row indices and coefficients
+  // stay scalar loads; lanes past the last column load zeros (lp_load)
+  const int sl = __builtin_amdgcn_readfirstlane(threadIdx.x / CPB);
+  const int64_t k = ((int64_t)blockIdx.x * CPB + tc) * EPC;
+  const bool live = k < cols;
+  if constexpr (RS == 1) {
+    if (!live) return;
+  }
+  const int64_t per = (m + RS - 1) / RS;
+  const int64_t p1 = std::min<int64_t>(m, (sl + 1) * per);
   double acc[EPC];
 #pragma unroll
   for (int e = 0; e < EPC; ++e) acc[e] = 0.0;
-  int64_t p = 0;
-  constexpr int RIF = 8;   // rows in flight
-  for (; p + RIF <= m; p += RIF) {
+  int64_t p = sl * per;
+  for (; p + RIF <= p1; p += RIF) {
     uint4 x[RIF];
     double c[RIF];
 #pragma unroll
@@ -459,7 +480,7 @@ __global__ __launch_bounds__(kLvThreads) void gemv_t_lp_kernel(
       for (int e = 0; e < EPC; ++e) acc[e] = fma(dv[e], c[q], acc[e]);
     }
   }
-  for (; p < m; ++p) {
+  for (; p < p1; ++p) {
     const int64_t row = idx ? (int64_t)idx[p] : p;
     const double cq = v[p] * (rs ? (double)rs[row] : 1.0);
     const uint4 x = lp_load<FMT>(A + row * ld * ES, k, cols, aligned != 0);
@@ -468,6 +489,20 @@ __global__ __launch_bounds__(kLvThreads) void gemv_t_lp_kernel(
 #pragma unroll
     for (int e = 0; e < EPC; ++e) acc[e] = fma(dv[e], cq, acc[e]);
   }
+  if constexpr (RS > 1) {
+    __shared__ double red[RS - 1][EPC][CPB];
+    if (sl > 0) {
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) red[sl - 1][e][tc] = acc[e];
+    }
+    __syncthreads();
+    if (sl > 0) return;
+#pragma unroll
+    for (int r = 0; r < RS - 1; ++r)
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) acc[e] += red[r][e][tc];
+  }
+  if (!live) return;
 #pragma unroll
   for (int e = 0; e < EPC; ++e) {
     if (k + e < cols) {
@@ -531,15 +566,19 @@ hipError_t launch_gemv_t_lp(int dtype, const void* A, int64_t ld, int64_t cols, 
   const int es = dtype == CABCD_BF16 ? 2 : 1;
   const int epc = 16 / es;
   const int aligned = ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && ((ld * es) & 15) == 0);
-  const int64_t blocks = (cols + (int64_t)kLvThreads * epc - 1) / ((int64_t)kLvThreads * epc);
+  const int slices = dtype == CABCD_BF16 ? kLvSlices<CABCD_BF16> : kLvSlices<CABCD_FP8_E4M3>;
+  const int64_t per_block = (int64_t)(kLvThreads / slices) * epc;
+  const int64_t blocks = (cols + per_block - 1) / per_block;
   if (dtype == CABCD_BF16)
-    hipLaunchKernelGGL(gemv_t_lp_kernel<CABCD_BF16>, dim3((unsigned)blocks), dim3(kLvThreads), 0,
-                       st, static_cast<const uint8_t*>(A), ld, cols, rs, idx, m, v, gamma, base,
-                       beta, accumulate ? 1 : 0, out, aligned);
+    hipLaunchKernelGGL((gemv_t_lp_kernel<CABCD_BF16, kLvSlices<CABCD_BF16>>),
+                       dim3((unsigned)blocks), dim3(kLvThreads), 0, st,
+                       static_cast<const uint8_t*>(A), ld, cols, rs, idx, m, v, gamma, base, beta,
+                       accumulate ? 1 : 0, out, aligned);
   else
-    hipLaunchKernelGGL(gemv_t_lp_kernel<CABCD_FP8_E4M3>, dim3((unsigned)blocks),
-                       dim3(kLvThreads), 0, st, static_cast<const uint8_t*>(A), ld, cols, rs, idx,
-                       m, v, gamma, base, beta, accumulate ? 1 : 0, out, aligned);
+    hipLaunchKernelGGL((gemv_t_lp_kernel<CABCD_FP8_E4M3, kLvSlices<CABCD_FP8_E4M3>>),
+                       dim3((unsigned)blocks), dim3(kLvThreads), 0, st,
+                       static_cast<const uint8_t*>(A), ld, cols, rs, idx, m, v, gamma, base, beta,
+                       accumulate ? 1 : 0, out, aligned);
   return hipGetLastError();
 }
 

@@ -87,6 +87,27 @@ def test_lowp_gram_against_fp64_gram_of_dequantised(gpu_lib, dtype, m, cols):
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("d,n", [(37, 70001), (3, 4097), (130, 2 * 4096 + 19)])
+def test_lowp_companion_pass_entrywise(gpu_lib, dtype, d, n):
+    # r = X^T w - y over all rows of the stored codes (the exact recomputation
+    # pass): odd row counts split into unequal row ranges, fewer rows than are
+    # kept in flight, and a last column chunk that is partly past the end
+    _say("lowp companion pass", dtype, d, n)
+    X = _matrix(d, n, 40 + d) if d > 2 else np.random.default_rng(d).standard_normal((d, n))
+    rng = np.random.default_rng(n)
+    y = rng.standard_normal(n)
+    w = rng.standard_normal(d)
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(torch.tensor(X, device=DEV), code)
+    Xh = Q.dequantize().cpu().numpy()
+    _, r = gpu_lib.primal_bcd(Q, torch.tensor(y, device=DEV), 1e-3, 1, 1, 0, 1,
+                              w=torch.tensor(w, device=DEV))
+    ro = Xh.T @ w - y
+    bound = np.abs(Xh).T @ np.abs(w) + np.abs(y)
+    assert np.all(np.abs(r.cpu().numpy() - ro) <= 1e-12 * bound)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 def test_mixed_primal_reaches_1e6_on_dequantised_problem(gpu_lib, dtype):
     _say("mixed primal", dtype)
     X, y, _, _ = synth.colscaled_ridge(128, 8192, 7)
