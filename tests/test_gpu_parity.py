@@ -53,6 +53,9 @@ def test_sampler_bit_exact(gpu_lib, seed, h0, count, b, rng):
                                     # and three tiles per slab, a partial last tile
                                     (129, 16), (256, 32), (256, 48), (160, 1000),
                                     (250, 4098),
+                                    # three tiles in rotation: four and five tiles per
+                                    # slab, and many with a partial last one
+                                    (256, 64), (256, 80), (192, 4130),
                                     # LDS-DMA path for m <= 128 (even cols): every block
                                     # class, several tiles per slab, partial tiles
                                     (8, 770), (32, 4096), (20, 5000), (64, 2048),
