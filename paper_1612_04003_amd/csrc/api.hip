@@ -611,6 +611,14 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
 
   const int K = gram_slots(M, (int64_t)s * b);   // Grams per launch (computed ahead)
+  // Grams computed ahead get their diagonal blocks inverted in one launch when
+  // the solve runs in one 256-thread workgroup (b <= 16 and s BP <= 256 lanes:
+  // b = 16 at s = 1 / 8, 11.9 -> 8.9 / 15.9 -> 12.4 us per sparse solve); the
+  // 512-thread solve (b = 16, s = 32) measured slower without its own
+  // inversion (43 -> 52 us) and keeps it.
+  int bp = 1;
+  while (bp < b) bp *= 2;
+  const bool pre_inv = K > 1 && bp <= 16 && (int64_t)s * bp <= 256;
   int ahead = 0, gslot = 0;                       // precomputed Grams left, next slot
   int64_t h = 0, k = 0, slot = 0;
   int64_t chunk_begin = -1, chunk_end = -1;
@@ -633,13 +641,19 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       idx = B.idx + (h - chunk_begin) * b;
     }
     const double* Gk = B.G;
-    if (K > 1 && sk == s) {
+    const bool from_ahead = K > 1 && sk == s;
+    if (from_ahead) {
       if (ahead == 0) {
         // the Grams of the next full outer steps whose indices are at hand
         int64_t avail = (H - h) / s;
         if (o.explicit_idx == nullptr) avail = std::min(avail, (chunk_end - h) / s);
         const int nst = (int)std::min<int64_t>(K, std::max<int64_t>(avail, 1));
         HIP_TRY(mat_gram_steps(M, idx, m, nst, scale, shift, B.G, B.partials, st, &timer));
+        // their diagonal blocks inverted together, off the solves' chains
+        if (pre_inv)
+          HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] {
+            return launch_invert_diag(B.G, nst, m, b, B.status, st);
+          }));
         ahead = nst;
         gslot = 0;
       }
@@ -667,6 +681,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     sa.mode = dual ? 1 : 0;
     sa.lambda = lambda;
     sa.n = n;
+    sa.pre_inverted = from_ahead && pre_inv ? 1 : 0;
     HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] { return launch_solve(sa, st); }));
     HIP_TRY(timer.run(CABCD_PHASE_UPDATE, [&] {
       return mat_scatter(M, idx, m, B.delta, gamma, nullptr, 0.0, true, comp, B.scratch, st);

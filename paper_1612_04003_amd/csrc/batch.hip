@@ -338,6 +338,7 @@ __device__ __noinline__ void solve_call(const SolveArgs& in) {
   a.mode = uni(in.mode);
   a.lambda = __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, in.lambda)));
   a.n = __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, in.n)));
+  a.pre_inverted = 0;
   sdev::solve_block<BP, PF, kBT, 1>(a, dyn_sm);   // s BP <= 2 s b <= 512 lanes
 }
 
@@ -448,6 +449,7 @@ __global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict
     a.mode = 0;
     a.lambda = pr.lambda;
     a.n = (double)pr.n;
+    a.pre_inverted = 0;
     solve_any(pr.bp, a);
     __syncthreads();
     if (tid == 0) {

@@ -151,12 +151,17 @@ struct SolveArgs {
   int m, b, s;
   int mode;
   double lambda, n;
+  int pre_inverted;    // 1: the diagonal blocks of G hold Gamma_j^-1 (launch_invert_diag)
 };
 constexpr int kSolveMaxRows = 1024;
 constexpr int kSolveMaxB = 32;
 constexpr size_t kSolveMaxLds = 160 * 1024;
 size_t solve_lds_bytes(int m, int b);   // dynamic LDS of one solve launch
 hipError_t launch_solve(const SolveArgs& a, hipStream_t st);
+// Inverts in place the diagonal b x b blocks (Gamma_j, b <= 16) of nsteps
+// consecutive m x m Grams (s = m / b blocks each), as the solve would; a pivot
+// that is not positive sets *status to "not positive definite".
+hipError_t launch_invert_diag(double* G, int nsteps, int m, int b, int* status, hipStream_t st);
 
 // ------------------------------------------------------------------ low precision
 // Codes of A (rows x cols, FP64, ld lda) into Q (ld ldq elements) with FP32

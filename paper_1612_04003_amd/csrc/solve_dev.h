@@ -131,6 +131,25 @@ __device__ __forceinline__ double read_lane(double x, int l) {
 // The s diagonal blocks held in Gi inverted one per lane (thread j takes block
 // j), each in registers with the Gauss-Jordan steps of gj_invert, so the
 // results are the same; with no shuffles the cost is one block's arithmetic.
+template <int BP>
+__device__ __forceinline__ void gj_lane(double (&e)[BP][BP], bool& bad) {
+#pragma unroll
+  for (int k = 0; k < BP; ++k) {
+    const double piv = e[k][k];
+    bad |= !(piv > 0.0);
+    const double rp = 1.0 / piv;
+#pragma unroll
+    for (int v = 0; v < BP; ++v) e[k][v] = (v == k ? 1.0 : e[k][v]) * rp;
+#pragma unroll
+    for (int u = 0; u < BP; ++u) {
+      if (u == k) continue;
+      const double f = e[u][k];
+#pragma unroll
+      for (int v = 0; v < BP; ++v) e[u][v] = (v == k ? 0.0 : e[u][v]) - f * e[k][v];
+    }
+  }
+}
+
 template <int BP, int THREADS>
 __device__ __forceinline__ void invert_per_lane(double* Gi, int s, int tid, bool& bad) {
   using C = SolveCfg<BP>;
@@ -141,21 +160,7 @@ __device__ __forceinline__ void invert_per_lane(double* Gi, int s, int tid, bool
     for (int u = 0; u < BP; ++u)
 #pragma unroll
       for (int v = 0; v < BP; ++v) e[u][v] = g[u * BP + v];
-#pragma unroll
-    for (int k = 0; k < BP; ++k) {
-      const double piv = e[k][k];
-      bad |= !(piv > 0.0);
-      const double rp = 1.0 / piv;
-#pragma unroll
-      for (int v = 0; v < BP; ++v) e[k][v] = (v == k ? 1.0 : e[k][v]) * rp;
-#pragma unroll
-      for (int u = 0; u < BP; ++u) {
-        if (u == k) continue;
-        const double f = e[u][k];
-#pragma unroll
-        for (int v = 0; v < BP; ++v) e[u][v] = (v == k ? 0.0 : e[u][v]) - f * e[k][v];
-      }
-    }
+    gj_lane<BP>(e, bad);
 #pragma unroll
     for (int u = 0; u < BP; ++u)
 #pragma unroll
@@ -255,7 +260,7 @@ __device__ __forceinline__ void invert_rounds(double* Gi, int s, int wave, int l
 //          rows are BP consecutive lanes of one wave: they apply Gamma_j^-1
 //          (rows kept in registers) to their rhs with in-wave shuffles, and
 //          one barrier per block publishes delta_j.
-template <int BP, int PF, int THREADS, int MAP = 0>
+template <int BP, int PF, int THREADS, int MAP = 0, bool PRE = false>
 __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   using C = SolveCfg<BP>;
   const int m = a.m, b = a.b, s = a.s;
@@ -339,8 +344,12 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   // once (rounds) when a block has one entry per lane: their elimination
   // chains are independent, so their latencies overlap.  Larger blocks have
   // enough independent work per round and no registers to spare.
+  // PRE: launch_invert_diag has inverted them already (a compile-time choice:
+  // a runtime branch here changed the register allocation of the chain)
   bool bad = false;
-  if constexpr (BP <= 8 && THREADS <= 256)
+  if constexpr (PRE)
+    ;
+  else if constexpr (BP <= 8 && THREADS <= 256)
     invert_per_lane<BP, THREADS>(Gi, s, tid, bad);
   else if constexpr (BP == 16)
     invert_rows16<WAVES>(Gi, s, wave, lane, bad);

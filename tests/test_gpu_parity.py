@@ -239,6 +239,7 @@ DUAL_CASES = [
     (77, 1001, 5, 7, 33, 1e-2, 2),         # odd d (unaligned rows of X^T)
     (12, 30, 30, 1, 2, 0.03, 1),           # b' = n: one exact step
     (40, 12, 4, 32, 40, 0.1, 6),           # 128 rows over 12 samples: ~11 repeats each
+    (200, 300, 20, 4, 40, 1e-2, 12),       # b = 20: Grams ahead, one row per thread
 ]
 
 
