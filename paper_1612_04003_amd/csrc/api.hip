@@ -611,14 +611,14 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     HIP_TRY(timer.run(CABCD_PHASE_RECOMPUTE, exact_companion));
 
   const int K = gram_slots(M, (int64_t)s * b);   // Grams per launch (computed ahead)
-  // Grams computed ahead get their diagonal blocks inverted in one launch when
-  // the solve runs in one 256-thread workgroup (b <= 16 and s BP <= 256 lanes:
-  // b = 16 at s = 1 / 8, 11.9 -> 8.9 / 15.9 -> 12.4 us per sparse solve); the
-  // 512-thread solve (b = 16, s = 32) measured slower without its own
-  // inversion (43 -> 52 us) and keeps it.
+  // Grams computed ahead get their diagonal blocks inverted in one launch, and
+  // the one-barrier solves (b <= 16, s BP <= 512 lanes) skip their own
+  // inversion: sparse dual solve at b = 16, s = 1 / 8 / 32: 11.9 -> 8.9 /
+  // 15.9 -> 12.3 / 43 -> 34 us (the 512-thread solve without the inversion
+  // code also stops spilling registers).
   int bp = 1;
   while (bp < b) bp *= 2;
-  const bool pre_inv = K > 1 && bp <= 16 && (int64_t)s * bp <= 256;
+  const bool pre_inv = K > 1 && bp <= 16 && (int64_t)s * bp <= 512;
   int ahead = 0, gslot = 0;                       // precomputed Grams left, next slot
   int64_t h = 0, k = 0, slot = 0;
   int64_t chunk_begin = -1, chunk_end = -1;

@@ -29,11 +29,11 @@ hipError_t launch_k(const SolveArgs& a, hipStream_t st) {
 }
 
 // Diagonal blocks inverted ahead (a.pre_inverted) are taken by the one-barrier
-// 256-thread solves only, the ones the drivers ask it for.
+// solves (s BP <= 512 lanes) only, the ones the drivers ask it for.
 template <int BP, int PF, int THREADS, int MAP>
 hipError_t launch_b(const SolveArgs& a, hipStream_t st) {
   if (!a.pre_inverted) return launch_k<BP, PF, THREADS, MAP, false>(a, st);
-  if constexpr (THREADS <= 256 && MAP == 1) return launch_k<BP, PF, THREADS, MAP, true>(a, st);
+  if constexpr (THREADS <= 512 && MAP == 1) return launch_k<BP, PF, THREADS, MAP, true>(a, st);
   return hipErrorInvalidValue;
 }
 
