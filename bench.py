@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--batch-no-baseline", action="store_true",
                     help="batched record without the one-problem-at-a-time baseline")
     ap.add_argument("--only-tol", action="store_true", help="run only the mixed time-to-1e-6")
+    ap.add_argument("--only-extra", action="store_true",
+                    help="run only the extra records (s sweep, dual, sparse, residual stops)")
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the numerical-stability record")
     ap.add_argument("--only-stability", action="store_true",
@@ -601,6 +603,12 @@ def main():
         return
     if args.only_tol:
         print(json.dumps({"time_to_tol": time_to_tol(cabcd, torch, synth)}), flush=True)
+        return
+    if args.only_extra:
+        log(f"generating X ({args.d} x {args.n}, FP64) on the GPU")
+        X, y, _ = synth.spectral_ridge(args.d, args.n, 1001, device="cuda:0")
+        torch.cuda.synchronize()
+        print(json.dumps({"extra": extra_records(args, cabcd, torch, synth, X, y)}), flush=True)
         return
     out, X, y = headline(args, cabcd, torch, synth)
     if args.only_stability:
