@@ -307,8 +307,26 @@ __global__ __launch_bounds__(kCsrThreads) void csr_rowdot_kernel(
   const int64_t p = (int64_t)blockIdx.x * kCsrWaves + (threadIdx.x >> 6);
   if (p >= rows) return;
   const int64_t r = idx ? (int64_t)idx[p] : p;
+  const int64_t end = rowptr[r + 1];
   double t = 0.0;
-  for (int64_t k = rowptr[r] + lane; k < rowptr[r + 1]; k += 64) t = fma(vals[k], v[colidx[k]], t);
+  // kProbeU entries per lane in flight (the gathers of v depend on the column
+  // loads); each lane still adds its entries in index order
+  for (int64_t k0 = rowptr[r] + lane; k0 < end; k0 += 64 * kProbeU) {
+    int col[kProbeU];
+    double val[kProbeU];
+#pragma unroll
+    for (int u = 0; u < kProbeU; ++u) {
+      const int64_t k = k0 + 64 * u;
+      col[u] = k < end ? colidx[k] : -1;
+      val[u] = k < end ? vals[k] : 0.0;
+    }
+    double x[kProbeU];
+#pragma unroll
+    for (int u = 0; u < kProbeU; ++u) x[u] = col[u] >= 0 ? v[col[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kProbeU; ++u)
+      if (col[u] >= 0) t = fma(val[u], x[u], t);
+  }
   t = wave_sum(t);
   if (lane == 0) out[p] = t + (base ? beta * base[p] : 0.0);
 }
