@@ -198,7 +198,8 @@ cabcd_status cabcd_gram(const cabcd_matrix* A, const int32_t* idx, int32_t m,
  * X may be dense F64, dense BF16 / FP8 (mixed precision: the Gram on the
  * stored codes with FP32 accumulation, everything else in FP64 on X^; set
  * opts->resid_every to recompute r exactly every few outer steps) or CSR F64.
- * 1 <= b <= min(d, 32), s >= 1, s*b <= 256 dense / 1024 CSR, H >= 0, lambda > 0.
+ * 1 <= b <= min(d, 32), s >= 1, s*b <= 256 dense / 1024 CSR (512 when
+ * b > 16), H >= 0, lambda > 0; a larger s*b is CABCD_EUNSUPPORTED.
  */
 cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lambda,
                               int32_t b, int32_t s, int64_t H, uint64_t seed,
@@ -215,7 +216,8 @@ cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lam
  * X^T may be dense F64, dense BF16 / FP8 (mixed precision as for the primal:
  * the Gram on the stored codes with FP32 accumulation, everything else in
  * FP64 on the dequantised X^; one row scale per data point) or CSR F64.
- * 1 <= b <= min(n, 32), s >= 1, s*b <= 256 dense / 1024 CSR, H >= 0, lambda > 0.
+ * 1 <= b <= min(n, 32), s >= 1, s*b <= 256 dense / 1024 CSR (512 when
+ * b > 16), H >= 0, lambda > 0; a larger s*b is CABCD_EUNSUPPORTED.
  */
 cabcd_status cabcd_dual_bcd(const cabcd_matrix* XT, const double* y, double lambda,
                             int32_t b, int32_t s, int64_t H, uint64_t seed,

@@ -504,6 +504,10 @@ cabcd_status check_common(const Mat& M, double lambda, int b, int s, int64_t H) 
               max_rows_per_gram(M), M.csr ? "CSR" : "dense");
     return CABCD_EUNSUPPORTED;
   }
+  if (b > 16 && sb > 512) {   // the 32-lane block solves hold at most 512 rows
+    set_error("s*b = %lld with b = %d > 16 exceeds the supported maximum 512", (long long)sb, b);
+    return CABCD_EUNSUPPORTED;
+  }
   if (solve_lds_bytes((int)sb, b) > kSolveMaxLds) {
     set_error("s*b = %lld with b = %d needs more LDS than one workgroup has", (long long)sb, b);
     return CABCD_EUNSUPPORTED;

@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kBT) void batch_aux_kernel(const BProb* __restrict_
         for (int q = 0; q < pr.nslab; ++q) rr += glb(pr.objp)[q];
         const double f = rr / (2.0 * (double)pr.n) + 0.5 * pr.lambda * ww;
         st->obj = f;
-        if (!isfinite(f) && st->status == DEV_OK) st->status = DEV_NONFINITE;
+        if (!isfinite(f)) raise_status(&st->status, DEV_NONFINITE);
         st->fresh = MODE == kAuxExact ? 2 : 1;
         st->m_prev = 0;
         if ((pr.f_target > 0.0 && f <= pr.f_target) || !isfinite(f)) st->active = 0;

@@ -32,22 +32,27 @@ __device__ __forceinline__ gptr<T> glb(T* p) {
   return (gptr<T>)p;
 }
 
-// Exact decoding of the low-precision storage formats to FP64.
+// Exact decoding of BF16 storage to FP64.  (E4M3 codes are decoded by the
+// hardware conversion v_cvt_pk_f32_fp8, which reads 0x7F / 0xFF as NaN, the same
+// reading as the FP8 matrix instructions.)
 __device__ __forceinline__ double decode_bf16(uint32_t b) {
   return (double)__uint_as_float((b & 0xFFFFu) << 16);
-}
-__device__ __forceinline__ double decode_e4m3(uint32_t b) {
-  const uint32_t E = (b >> 3) & 15u, M = b & 7u;
-  const double v = E == 0 ? (double)M * 0x1p-9 : ldexp((double)(8u + M), (int)E - 10);
-  return (b & 0x80u) ? -v : v;
 }
 
 // ------------------------------------------------------------------ errors
 void set_error(const char* fmt, ...);
 void clear_error();
 
-// Device status word values written by kernels (0 = fine).
-enum DeviceStatus : int { DEV_OK = 0, DEV_NOTSPD = 1, DEV_NONFINITE = 2 };
+// Device status word values written by kernels (0 = fine).  A larger value
+// outranks a smaller one: a block that is not positive definite makes its
+// solve and every later value non-finite, and the status must name the cause.
+enum DeviceStatus : int { DEV_OK = 0, DEV_NONFINITE = 1, DEV_NOTSPD = 2 };
+
+// Records a device-detected error in the status word, keeping the highest
+// ranked one (integer atomic maximum, so concurrent writers agree).
+__device__ __forceinline__ void raise_status(int* status, int code) {
+  atomicMax(status, code);
+}
 
 // ------------------------------------------------------------------ sampler
 // Counter-based block sampler (the sampling step of Alg. 1-4): b distinct

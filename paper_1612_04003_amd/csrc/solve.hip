@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64) void invert_diag_kernel(double* G, int m, int b
   } else {
     static_assert(BP <= 16, "blocks up to 16 x 16");
   }
-  if (bad) *status = DEV_NOTSPD;
+  if (bad) raise_status(status, DEV_NOTSPD);
 }
 
 template <int BP>

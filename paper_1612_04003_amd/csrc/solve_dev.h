@@ -355,7 +355,7 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
     invert_rows16<WAVES>(Gi, s, wave, lane, bad);
   else
     invert_rounds<BP, (C::EPL == 1 ? 2 : 1), WAVES>(Gi, s, wave, lane, bad);
-  if (bad) *glb(a.status) = DEV_NOTSPD;
+  if (bad) raise_status(a.status, DEV_NOTSPD);
   lds_barrier();
 
   // ---- phase 3: the dependent chain over the s blocks.  Every thread runs all
@@ -447,7 +447,7 @@ __device__ __forceinline__ void solve_block(const SolveArgs& a, double* sm) {
   if (active) {
     dp = Dl[dslot];
     glb(a.delta)[p] = dp;
-    if (!isfinite(dp)) *glb(a.status) = DEV_NONFINITE;
+    if (!isfinite(dp)) raise_status(a.status, DEV_NONFINITE);
     h = hash_idx(ip, slots);
     for (;;) {
       const int old = atomicCAS(&hkey[h], -1, ip);

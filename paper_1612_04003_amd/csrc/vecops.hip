@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kVecThreads) void objective_final_kernel(
   if (threadIdx.x == 0) {
     const double f = c1 * red[0][0] + c2 * red[1][0];
     *out = f;
-    if (status != nullptr && !isfinite(f)) *status = DEV_NONFINITE;
+    if (status != nullptr && !isfinite(f)) raise_status(status, DEV_NONFINITE);
   }
 }
 
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kVecThreads) void norm_final_kernel(
   if (threadIdx.x == 0) {
     const double r = sqrt(red[0]);
     *out = r;
-    if (status != nullptr && !isfinite(r)) *status = DEV_NONFINITE;
+    if (status != nullptr && !isfinite(r)) raise_status(status, DEV_NONFINITE);
   }
 }
 

@@ -1,0 +1,239 @@
+"""Whole outer steps through the driver paths the benchmarks time, the b = 1
+case of the paper's headline speedups, and the solver's edge cases, against the
+CPU oracle through the C-ABI.
+
+Which driver path a run took is read from the phase launch counts that
+`opts.timing` returns:
+* one Gram per outer step (gathered rows of more than 8 MiB, or a ragged last
+  step): `gram` and `reduce` once per outer step, no `yu` pass;
+* Grams computed ahead (short rows, CSR): one `gram` launch for many outer
+  steps and a separate `yu` row-product pass per step.
+
+Tolerances:
+* FP64 iterates: 1e-10 relative (the bar of the FP64 path); where a block is
+  ill-conditioned the bound is stated from kappa u (see the test);
+* mixed precision: relative objective error 1e-6 on the dequantised problem
+  (X^, y, lambda) and an exact residual recomputation to 1e-12.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse
+import torch
+
+from oracle import bcd
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+U64 = 2.0 ** -53
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _launches(gpu_lib, t):
+    return {k: v["launches"] for k, v in gpu_lib.timing_dict(t).items()}
+
+
+def _assert_per_step(gpu_lib, t, steps):
+    n = _launches(gpu_lib, t)
+    _say("  launches", n)
+    assert n["yu"] == 0, "expected one fused Gram per outer step"
+    assert n["gram"] == steps and n["reduce"] == steps and n["solve"] == steps
+
+
+# ------------------------------------------------------------------ one Gram per step
+
+def test_primal_fp64_per_step_path_full_steps(gpu_lib):
+    """Headline path at a shard shape: b = 8, s = 32 (sb = 256), rows of
+    32768 FP64 values (64 MiB gathered per step), three full outer steps and a
+    ragged one; the spectrum of the headline matrix (1 .. 1e3)."""
+    d, n, b, s, lam, seed = 512, 32768, 8, 32, 1e-4, 2001
+    H = 3 * s + 5
+    _say("primal per-step", d, n, b, s, H)
+    X, y, _ = synth.spectral_ridge(d, n, 1001)
+    t = gpu_lib.new_timing()
+    w, r = gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), lam, b, s, H, seed, timing=t)
+    _assert_per_step(gpu_lib, t, 4)
+    trace = []
+    wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed,
+                            monitor=lambda h, w_, z_: trace.append(h))
+    assert trace == [32, 64, 96, 101]
+    e_w, e_r = _rel(w.cpu(), wo), _rel(r.cpu(), zo - y.numpy())
+    _say(f"  rel err w {e_w:.2e}, r {e_r:.2e}")
+    assert e_w <= 1e-10 and e_r <= 1e-10
+
+
+def test_dual_fp64_per_step_path_full_steps(gpu_lib):
+    """Dual on A = X^T with rows of 6000 features: 12 MiB gathered per step at
+    sb = 256, so each outer step forms its own Gram with Y w fused."""
+    d, n, b, s, lam, seed = 6000, 3000, 8, 32, 1e-3, 7
+    H = 3 * s + 5
+    _say("dual per-step", d, n, b, s, H)
+    X, y, _ = synth.gaussian_ridge(d, n, 606)
+    XT = X.t().contiguous()
+    t = gpu_lib.new_timing()
+    a, w = gpu_lib.dual_bcd(XT.to(DEV), y.to(DEV), lam, b, s, H, seed, timing=t)
+    _assert_per_step(gpu_lib, t, 4)
+    ao, wo = bcd.dual_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed)
+    e_a, e_w = _rel(a.cpu(), ao), _rel(w.cpu(), wo)
+    _say(f"  rel err alpha {e_a:.2e}, w {e_w:.2e}")
+    assert e_a <= 1e-10 and e_w <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_mixed_primal_per_step_path(gpu_lib, dtype):
+    """The mixed-precision step at sb = 256 (b = 16, s = 16) on rows of 65536
+    codes (32 MiB of BF16, 16 MiB of FP8 gathered per step), with the exact
+    residual recomputed every 4 outer steps as in the mixed workload."""
+    d, n, b, s, lam, seed = 512, 65536, 16, 16, 1e-4, 3
+    steps = 48
+    H = steps * s
+    _say("mixed per-step", dtype, d, n, b, s, H)
+    X, y, _, _ = synth.colscaled_ridge(d, n, 9)
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(X.to(DEV), code)
+    Xh = Q.dequantize().cpu().numpy()
+    yn = y.numpy()
+    wstar = bcd.ridge_closed_form(Xh, yn, lam)
+    fstar = bcd.primal_objective(Xh, yn, lam, wstar)
+    t = gpu_lib.new_timing()
+    w, r = gpu_lib.primal_bcd(Q, y.to(DEV), lam, b, s, H, seed, resid_every=4, timing=t)
+    _assert_per_step(gpu_lib, t, steps)
+    wn = w.cpu().numpy()
+    rel_obj = (bcd.primal_objective(Xh, yn, lam, wn) - fstar) / fstar
+    _say(f"  rel obj error {rel_obj:.2e}")
+    assert rel_obj <= 1e-6
+    # the last outer step recomputed r = X^ T w - y exactly (48 steps, every 4th)
+    ro = Xh.T @ wn - yn
+    bound = np.abs(Xh).T @ np.abs(wn) + np.abs(yn)
+    assert np.all(np.abs(r.cpu().numpy() - ro) <= 1e-12 * bound)
+    # the FP64 path on X^ with the same blocks (pinned to the oracle by the
+    # tests above): the distance is the FP32 Gram accumulation's, reported
+    w64, _ = gpu_lib.primal_bcd(torch.tensor(Xh, device=DEV), y.to(DEV), lam, b, s, H, seed)
+    _say(f"  ||w_mixed - w_fp64|| / ||w_fp64|| = {_rel(wn, w64.cpu()):.2e} (reported)")
+
+
+# ------------------------------------------------------------------ b = 1
+
+def _csr(M):
+    S = scipy.sparse.csr_matrix(M)
+    S.sort_indices()
+    return S
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("s,H", [(1, 300), (8, 300), (32, 101)])
+def test_primal_b1_matches_oracle(gpu_lib, kind, s, H):
+    """b = 1 (single-coordinate BCD, the regime of the paper's largest CA
+    speedups) on a matrix with a few exact zeros per row."""
+    _say("primal b=1", kind, s, H)
+    X, y, _ = synth.gaussian_ridge(64, 1024, 71)
+    X[np.abs(X.numpy()) < 0.3] = 0.0
+    lam = 1e-3
+    A = gpu_lib.CSR.from_scipy(_csr(X.numpy()), DEV) if kind == "csr" else X.to(DEV)
+    w, r = gpu_lib.primal_bcd(A, y.to(DEV), lam, 1, s, H, 5)
+    wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, 1, s, H, 5)
+    assert _rel(w.cpu(), wo) <= 1e-10
+    assert _rel(r.cpu(), zo - y.numpy()) <= 1e-10
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("s,H", [(1, 300), (8, 300), (32, 101)])
+def test_dual_b1_matches_oracle(gpu_lib, kind, s, H):
+    _say("dual b=1", kind, s, H)
+    X, y, _ = synth.gaussian_ridge(300, 200, 72)
+    X[np.abs(X.numpy()) < 0.3] = 0.0
+    lam = 1e-2
+    XT = X.t().contiguous()
+    A = gpu_lib.CSR.from_scipy(_csr(XT.numpy()), DEV) if kind == "csr" else XT.to(DEV)
+    a, w = gpu_lib.dual_bcd(A, y.to(DEV), lam, 1, s, H, 6)
+    ao, wo = bcd.dual_bcd(X.numpy(), y.numpy(), lam, 1, s, H, 6)
+    assert _rel(a.cpu(), ao) <= 1e-10
+    assert _rel(w.cpu(), wo) <= 1e-10
+
+
+# ------------------------------------------------------------------ solver edge cases
+
+@pytest.mark.parametrize("kind,s,H", [
+    ("dense", 1, 1),    # Grams computed ahead: diagonal blocks inverted ahead
+    ("dense", 4, 1),    # ragged step: the solve inverts its own blocks
+    ("dense", 4, 9),    # full steps ahead, then a ragged one
+    ("csr", 1, 1),
+    ("csr", 4, 1),
+])
+def test_not_positive_definite_block_is_reported(gpu_lib, kind, s, H):
+    """Every feature row is the same +-1 vector, so any block of b = 2 holds two
+    identical rows: Gamma = [[1, 1], [1, 1]] + lambda I with lambda = 1e-300,
+    which rounds to the singular [[1, 1], [1, 1]] (all sums exact).  The
+    oracle's Cholesky meets a zero pivot; the GPU must report
+    CABCD_ENOTSPD (not the non-finite values that follow)."""
+    _say("not SPD", kind, s, H)
+    d, n, lam = 6, 64, 1e-300
+    rng = np.random.default_rng(3)
+    row = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    X = np.tile(row, (d, 1))
+    y = rng.standard_normal(n)
+    with pytest.raises(bcd.NotSPDError):
+        bcd.primal_bcd(X, y, lam, 2, s, H, 1)
+    A = (gpu_lib.CSR.from_scipy(_csr(X), DEV) if kind == "csr"
+         else torch.tensor(X, device=DEV))
+    with pytest.raises(gpu_lib.CabcdError) as e:
+        gpu_lib.primal_bcd(A, torch.tensor(y, device=DEV), lam, 2, s, H, 1)
+    assert e.value.status == gpu_lib.ENOTSPD
+
+
+@pytest.mark.parametrize("b,s", [(4, 8), (8, 4), (16, 2)])
+def test_ill_conditioned_blocks(gpu_lib, b, s):
+    """Rows v + eps z_i (eps = 2e-3): every b x b diagonal block has
+    kappa ~ 1e6.  A solve with such a block moves its result by at most about
+    kappa u relative to the exact one, in either implementation, and block
+    coordinate descent does not amplify such perturbations from step to step
+    (each block step is an exact minimisation), so the iterates of H steps
+    agree to within H * 10 * kappa_max * u."""
+    d, n, lam, H, seed = 32, 1024, 1e-10, 64, 8
+    _say("ill-conditioned", b, s)
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(n)
+    X = v[None, :] + 2e-3 * rng.standard_normal((d, n))
+    y = X.T @ rng.standard_normal(d) + 0.1 * rng.standard_normal(n)
+    # kappa of the blocks this run factors (the oracle's Gram)
+    from oracle import sampler
+    blocks = sampler.sample_blocks(seed, 0, H, b, d)
+    kap = max(np.linalg.cond(bcd.gram(X, blk, 1.0 / n, lam)[0]) for blk in blocks)
+    _say(f"  max kappa(Gamma_j) = {kap:.2e}")
+    assert 1e5 <= kap <= 1e8
+    w, r = gpu_lib.primal_bcd(torch.tensor(X, device=DEV), torch.tensor(y, device=DEV), lam, b,
+                              s, H, seed)
+    wo, zo = bcd.primal_bcd(X, y, lam, b, s, H, seed)
+    tol = H * 10.0 * kap * U64
+    e_w, e_r = _rel(w.cpu(), wo), _rel(r.cpu(), zo - y)
+    _say(f"  rel err w {e_w:.2e}, r {e_r:.2e}, bound {tol:.2e}")
+    assert e_w <= tol and e_r <= tol
+
+
+def test_fp8_nan_codes_read_as_nan(gpu_lib):
+    """E4M3 has no infinities; 0x7F / 0xFF are NaN.  The FP64 streaming pass
+    must read them as NaN (as the matrix instructions do), never as a finite
+    value."""
+    _say("fp8 nan codes")
+    codes = torch.full((3, 40), 0x38, dtype=torch.uint8)   # 1.0
+    codes[1, 7] = 0x7F
+    codes[2, 9] = 0xFF
+    Q = gpu_lib.Quantized(codes.to(DEV), torch.ones(3, dtype=torch.float32, device=DEV),
+                          gpu_lib.FP8_E4M3)
+    w = torch.tensor([1.0, 1.0, 0.5], dtype=torch.float64, device=DEV)
+    y = torch.zeros(40, dtype=torch.float64, device=DEV)
+    f, r = gpu_lib.primal_objective(Q, y, 1.0, w)
+    rn = r.cpu().numpy()
+    assert np.isnan(rn[7]) and np.isnan(rn[9])
+    assert np.all(rn[[k for k in range(40) if k not in (7, 9)]] == 2.5)
+    assert np.isnan(f.item())
