@@ -186,6 +186,27 @@ cabcd_status cabcd_gram(const cabcd_matrix* A, const int32_t* idx, int32_t m,
                         double* Yu, void* stream);
 
 /*
+ * cabcd_gram for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same A, idx, m, scale, shift, u, G and Yu as cabcd_gram, for dense A (F64,
+ * BF16, FP8; CSR is CABCD_EUNSUPPORTED), m <= 256.  The call allocates nothing,
+ * copies nothing to the host and never synchronises: the split-K partial Grams
+ * and a checked copy of idx live in a fixed 64 MiB device array of the library
+ * (one per GPU, held from the first call on that GPU until the process ends).
+ * The column slabs are widened so that the partials fit it, so the summation
+ * order (not the result beyond rounding) may differ from cabcd_gram's.
+ *   status  optional device int32: receives CABCD_OK, or CABCD_EINVAL when an
+ *           index lies outside [0, rows) (that row is then read as row 0 and G,
+ *           Yu are meaningless), in stream order before the Gram is formed.
+ * Argument errors found on the host are returned before anything is enqueued.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ */
+cabcd_status cabcd_gram_noalloc(const cabcd_matrix* A, const int32_t* idx, int32_t m,
+                                double scale, double shift, const double* u, double* G,
+                                double* Yu, int32_t* status, void* stream);
+
+/*
  * Primal CA-BCD (Alg. 2; s = 1 is BCD, Alg. 1), H inner iterations.
  *   X      A = X, d x n (rows = features)
  *   y      n labels

@@ -97,6 +97,7 @@ def load():
         "cabcd_opts_init": (None, [OP]),
         "cabcd_sample": (I32, [U64, I64, I64, I32, I64, P, P]),
         "cabcd_gram": (I32, [MP, P, I32, D, D, P, P, P, P]),
+        "cabcd_gram_noalloc": (I32, [MP, P, I32, D, D, P, P, P, P, P]),
         "cabcd_primal_bcd": (I32, [MP, P, D, I32, I32, I64, U64, P, P, OP, P]),
         "cabcd_dual_bcd": (I32, [MP, P, D, I32, I32, I64, U64, P, P, OP, P]),
         "cabcd_primal_objective": (I32, [MP, P, D, P, P, P, P]),
@@ -126,7 +127,8 @@ def load():
 
 def exported_symbols():
     """Names of the C entry points this binding expects the library to export."""
-    return ["cabcd_opts_init", "cabcd_sample", "cabcd_gram", "cabcd_primal_bcd",
+    return ["cabcd_opts_init", "cabcd_sample", "cabcd_gram", "cabcd_gram_noalloc",
+            "cabcd_primal_bcd",
             "cabcd_dual_bcd", "cabcd_primal_objective", "cabcd_primal_objective_t",
             "cabcd_dual_to_primal", "cabcd_primal_residual", "cabcd_dual_residual",
             "cabcd_workspace_bytes", "cabcd_last_error",
@@ -329,6 +331,32 @@ def gram(A, idx, scale, shift, u=None):
     _check(load().cabcd_gram(ctypes.byref(M), _ptr(idx), m, scale, shift, _ptr(u), _ptr(G),
                              _ptr(Yu), _stream()))
     return G, Yu
+
+
+def gram_noalloc(A, idx, scale, shift, u=None, G=None, Yu=None, status=None):
+    """cabcd_gram_noalloc: the Gram of gram() for a dense A without any device
+    allocation inside the library.  G (m x m float64), Yu (m float64, with u)
+    and status (1-element int32) may be passed in; missing ones are created
+    here, outside the call.  Returns (G, Yu, status); status holds the device
+    check of the indices (OK or EINVAL) once the stream reaches it."""
+    M = describe(A)
+    _need(idx, torch.int32, "idx")
+    m = idx.numel()
+    if G is None:
+        G = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    _need(G, torch.float64, "G", m * m)
+    if u is not None:
+        _need(u, torch.float64, "u", A.shape[1])
+        if Yu is None:
+            Yu = torch.empty(m, dtype=torch.float64, device=A.device)
+        _need(Yu, torch.float64, "Yu", m)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=A.device)
+    _need(status, torch.int32, "status", 1)
+    _check(load().cabcd_gram_noalloc(ctypes.byref(M), _ptr(idx), m, scale, shift, _ptr(u),
+                                     _ptr(G), _ptr(Yu if u is not None else None), _ptr(status),
+                                     _stream()))
+    return G, Yu, status
 
 
 def primal_bcd(X, y, lam, b, s, H, seed, w=None, r=None, **opt):
