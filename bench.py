@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--b", type=int, default=8)
     ap.add_argument("--s", type=int, default=32)
     ap.add_argument("--lam", type=float, default=1e-4)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tol", action="store_true", help="skip the time-to-1e-6 runs")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra records")
@@ -67,33 +67,67 @@ def parse():
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the numerical-stability record")
     ap.add_argument("--only-stability", action="store_true",
-                    help="run only the headline and the numerical-stability record")
+                    help="run only the numerical-stability record")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per Gram launch measured by rocprofv3 counters")
     return ap.parse_args()
 
 
 def cpu_baseline(X, y, lam, b, s, steps, seed):
+    """The FP64 oracle on the host cores, with the paper's timing protocol (one
+    warm-up run and three timed runs, mean and minimum): each run is `steps`
+    outer steps of the headline problem, once with the matrix library on one
+    thread and once on every thread it has.  value is the all-thread mean."""
     from oracle import bcd
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count()
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     Xh = X.cpu().numpy()
     yh = y.cpu().numpy()
-    stamps = []
-    t0 = time.perf_counter()
-    bcd.primal_bcd(Xh, yh, lam, b, s, steps * s, seed,
-                   monitor=lambda h, w, z: stamps.append(time.perf_counter()))
     d, n = Xh.shape
     sb = s * b
-    per_step = (stamps[-1] - t0) / steps
-    flops = n * sb * (sb + 1)
-    return {"value": flops / per_step / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+    flops = n * sb * (sb + 1) * steps
+
+    def protocol(limit):
+        times = []
+        with threadpool_limits(limits=limit):
+            for _ in range(4):
+                t0 = time.perf_counter()
+                bcd.primal_bcd(Xh, yh, lam, b, s, steps * s, seed)
+                times.append(time.perf_counter() - t0)
+        return times[1:]
+
+    t_all = protocol(threads)
+    t_one = protocol(1)
+    mean_all, mean_one = sum(t_all) / 3, sum(t_one) / 3
+    log(f"cpu baseline: {threads} threads {t_all}, 1 thread {t_one}")
+    return {"value": flops / mean_all / 1e12, "unit": "TFLOP/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"{steps} outer steps (s={s}, b={b}) of the FP64 oracle on the same "
-                      f"d={d} x n={n} problem; {per_step:.3f} s per step"}
+                      f"d={d} x n={n} problem per run; 1 warm-up + 3 timed runs; "
+                      f"{mean_all / steps:.3f} s per step on {threads} threads, "
+                      f"{mean_one / steps:.3f} s on 1",
+            "runs_s": [round(t, 4) for t in t_all],
+            "best": flops / min(t_all) / 1e12,
+            "single_thread": {"value": flops / mean_one / 1e12, "cores": 1,
+                              "runs_s": [round(t, 4) for t in t_one],
+                              "best": flops / min(t_one) / 1e12}}
+
+
+def closed_form(cabcd, torch, X, y, lam):
+    """The ridge minimiser (X X^T / n + lam I) w = X y / n on the GPU (Cholesky of
+    the d x d normal matrix in FP64) and f(w*) by the library's objective.
+    Reference values outside every timed region; the GPU tests check this
+    routine against the oracle's closed form."""
+    n = X.shape[1]
+    M = X @ X.t()
+    M /= n
+    M.diagonal().add_(lam)
+    L = torch.linalg.cholesky(M)
+    del M
+    w = torch.cholesky_solve(((X @ y) / n)[:, None], L)[:, 0]
+    del L
+    f, _ = cabcd.primal_objective(X, y, lam, w)
+    return w, f.item()
 
 
 def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False, mask=0):
@@ -320,17 +354,6 @@ def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, la
                        f"exact residual + objective every {chunk} outer steps",
            "tol": tol}
 
-    def closed_form_fstar(Xh):
-        M = Xh @ Xh.t()
-        M /= n
-        M.diagonal().add_(lam)
-        L = torch.linalg.cholesky(M)
-        rhs = (Xh @ y) / n
-        w = torch.cholesky_solve(rhs[:, None], L)[:, 0]
-        del M, L
-        f, _ = cabcd.primal_objective(Xh, y, lam, w)
-        return f.item()
-
     def run(A, fstar):
         w = torch.zeros(d, dtype=torch.float64, device="cuda")
         r = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -348,7 +371,7 @@ def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, la
             err = (trace.item() - fstar) / fstar
             if err <= tol:
                 break
-        return time.perf_counter() - t0, steps, err
+        return time.perf_counter() - t0, steps, err, w
 
     def gram_rate(A, elem, steps=8):
         """The Gram kernel alone over `steps` outer steps (HIP events around the
@@ -367,20 +390,35 @@ def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, la
                 "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
                 "gram_tflops": round(n * sb * (sb + 1) / (ms * 1e-3) / 1e12, 2)}
 
+    # the optimum of the original FP64 X: the quantisation shift of each stored
+    # problem is measured against it
+    w_x, _ = closed_form(cabcd, torch, X, y, lam)
     for name, code in (("bf16", cabcd.BF16), ("fp8", cabcd.FP8_E4M3)):
         Q = cabcd.quantize(X, code)
         Xh = Q.dequantize()
-        fstar = closed_form_fstar(Xh)
-        t64, st64, e64 = run(Xh, fstar)
+        w_hat, fstar = closed_form(cabcd, torch, Xh, y, lam)
+        shift = (torch.linalg.norm(w_hat - w_x) / torch.linalg.norm(w_x)).item()
+        t64, st64, e64, w64 = run(Xh, fstar)
         g64 = gram_rate(Xh, 8)
         del Xh
         torch.cuda.empty_cache()
-        tq, stq, eq = run(Q, fstar)
+        tq, stq, eq, wq = run(Q, fstar)
         gq = gram_rate(Q, 2 if name == "bf16" else 1)
+        nrm = torch.linalg.norm(w_hat)
         res[name] = {"fp64_on_xhat_s": round(t64, 5), "fp64_outer_steps": st64,
                      "fp64_rel_err": e64,
                      "mixed_s": round(tq, 5), "mixed_outer_steps": stq, "mixed_rel_err": eq,
-                     "speedup": round(t64 / tq, 3), "gram_fp64": g64, "gram_" + name: gq}
+                     "speedup": round(t64 / tq, 3), "gram_fp64": g64, "gram_" + name: gq,
+                     # ||w^* - w*_X|| / ||w*_X||: how far storing X in this format
+                     # moves the optimum (the problem the mixed runs solve is X^)
+                     "quantisation_shift": shift,
+                     # the final iterates against the optimum of X^, and the mixed
+                     # iterate against the FP64 one (same blocks; equal only when
+                     # both stopped after the same number of outer steps)
+                     "fp64_w_rel_err": (torch.linalg.norm(w64 - w_hat) / nrm).item(),
+                     "mixed_w_rel_err": (torch.linalg.norm(wq - w_hat) / nrm).item(),
+                     "mixed_vs_fp64_w": (torch.linalg.norm(wq - w64) /
+                                         torch.linalg.norm(w64)).item()}
         log(f"time-to-tol {name}: {res[name]}")
         del Q
         torch.cuda.empty_cache()
@@ -400,14 +438,7 @@ def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, chea
     torch.cuda.synchronize()
 
     def fstar(X, y, lam):
-        n = X.shape[1]
-        M = X @ X.t()
-        M /= n
-        M.diagonal().add_(lam)
-        L = torch.linalg.cholesky(M)
-        w = torch.cholesky_solve(((X @ y) / n)[:, None], L)[:, 0]
-        f, _ = cabcd.primal_objective(X, y, lam, w)
-        return f.item()
+        return closed_form(cabcd, torch, X, y, lam)[1]
 
     res = {"workload": f"{P} Gaussian ridge problems, d log-uniform [32, 1024], n log-uniform "
                        f"[4096, 131072], lambda log-uniform [1e-6, 1e-1]; objective every "
@@ -466,11 +497,11 @@ def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, chea
         rec["stream_gb"] = round(byts / 1e9, 2)
         rec["hbm_gbs"] = round(byts / max(t2 - t1, 1e-9) / 1e9, 1)
         log(f"batched {name}: {rec}")
-        if name == "f64" and baseline:
-            # one problem at a time, same (b, s), same stopping rule
+        if baseline:
+            # one problem at a time, same storage, same (b, s), same stopping rule
             tot, steps_tot, worst = 0.0, 0, 0.0
             for p in range(P):
-                X, y = data[p]
+                X, y = mats[p], data[p][1]
                 b, s = infos[p]["b"], infos[p]["s"]
                 w = torch.zeros(ds[p], dtype=torch.float64, device="cuda")
                 r = torch.empty(ns[p], dtype=torch.float64, device="cuda")
@@ -500,83 +531,126 @@ def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, chea
             rec["one_at_a_time_outer_steps"] = steps_tot
             rec["one_at_a_time_max_rel_err"] = worst
             rec["speedup"] = round(tot / (t2 - t1), 3)
-            log(f"one-at-a-time f64: {tot:.3f} s, speedup {rec['speedup']}")
+            log(f"one-at-a-time {name}: {tot:.3f} s, speedup {rec['speedup']}")
         res[name] = rec
         del probs, mats
         torch.cuda.empty_cache()
     return res
 
 
-def stability(cabcd, torch, X, y, lam, b=8, H=4096, seed=2005):
-    """Numerical stability (Section 6) on the synthetic stand-in: the same
-    block sequence run with s = 1 ... 32 must give the same iterates up to
-    rounding (CA-BCD reproduces BCD in exact arithmetic), in FP64 and on BF16
-    storage; and the condition numbers of the s-step Gram G and of its b x b
-    diagonal blocks (the matrices actually factorised) over sampled outer
-    steps, for the primal (rows of X) and the dual (columns of X)."""
+STAB_S = (1, 2, 4, 8, 16, 32)
+
+
+def stability_curve(cabcd, torch, A, y, lam, b, s, H, points, seed, w_star, f_star,
+                    dual=False):
+    """One run of H iterations from zero, in `points` equal chunks (each a whole
+    number of outer steps, so the iterates are those of one uninterrupted run);
+    after every chunk the relative objective error of the primal iterate
+    (f(w_h) - f*) / f* (objective recomputed from A) and its relative solution
+    error ||w_h - w*|| / ||w*||, the two measures of the paper's stability
+    study.  The dual reports its maintained w.  Returns [(h, obj, sol)]."""
+    rows, cols = A.shape
+    dev = y.device
+    coord = torch.zeros(rows, dtype=torch.float64, device=dev)
+    comp = torch.empty(cols, dtype=torch.float64, device=dev)
+    run = cabcd.dual_bcd if dual else cabcd.primal_bcd
+    kw = dict(alpha=coord, w=comp) if dual else dict(w=coord, r=comp)
+    chunk = H // points
+    assert chunk * points == H and chunk % s == 0
+    run(A, y, lam, b, s, 0, seed, **kw)                # companion vector of the zero start
+    nw = torch.linalg.norm(w_star)
+    out = []
+    for k in range(points):
+        run(A, y, lam, b, s, chunk, seed, h0=k * chunk, flags=cabcd.FLAG_STATE_VALID, **kw)
+        w = comp if dual else coord
+        f = (cabcd.primal_objective_t(A, y, lam, w) if dual else
+             cabcd.primal_objective(A, y, lam, w))[0].item()
+        out.append(((k + 1) * chunk, (f - f_star) / f_star,
+                    (torch.linalg.norm(w - w_star) / nw).item()))
+    return out
+
+
+def gram_conditions(cabcd, torch, A, scale, shift, b, s, seed, steps=16):
+    """cond(G) of the s b x s b Gram and the largest cond(Gamma_j) of its b x b
+    diagonal blocks (the matrices the solves factor) over the first `steps`
+    outer steps of a run: medians and maxima."""
     import numpy as np
-    d, n = X.shape
-    log("stability: closed-form optimum")
-    M = X @ X.T
-    M /= n
-    M.diagonal().add_(lam)
-    L = torch.linalg.cholesky(M)
-    wst = torch.cholesky_solve(((X @ y) / n)[:, None], L)[:, 0]
-    del M, L
-    fst = cabcd.primal_objective(X, y, lam, wst)[0].item()
-    res = {"workload": f"the headline matrix (d={d}, n={n}, spectrum 1..1e3, lambda={lam:g}), "
-                       f"b={b}, H={H} iterations from w=0 with one block sequence",
-           "H": H, "b": b}
-    for name in ("f64", "bf16"):
-        A, fs = X, fst
-        if name == "bf16":
-            A = cabcd.quantize(X, cabcd.BF16)
-            Xh = A.dequantize()
-            M = Xh @ Xh.T
-            M /= n
-            M.diagonal().add_(lam)
-            L = torch.linalg.cholesky(M)
-            wh = torch.cholesky_solve(((Xh @ y) / n)[:, None], L)[:, 0]
-            fs = cabcd.primal_objective(Xh, y, lam, wh)[0].item()
-            del Xh, M, L, wh
-        rec, w1 = {}, None
-        for s_ in (1, 2, 4, 8, 16, 32):
-            w, _ = cabcd.primal_bcd(A, y, lam, b, s_, H, seed)
-            f = cabcd.primal_objective(A, y, lam, w)[0].item()
-            if w1 is None:
-                w1 = w.clone()
-            rec[f"s{s_}"] = {"rel_obj_err": (f - fs) / fs,
-                             "w_rel_diff_vs_s1": (torch.linalg.norm(w - w1) /
-                                                  torch.linalg.norm(w1)).item()}
-        res[name] = rec
-        log(f"stability {name}: {rec}")
-        del A
-    torch.cuda.empty_cache()
+    idx = cabcd.sample(seed, 0, steps * s, b, A.shape[0]).reshape(steps, s * b)
+    cg, cb = [], []
+    for k in range(steps):
+        G = cabcd.gram(A, idx[k].contiguous(), scale, shift)[0].cpu().numpy()
+        cg.append(float(np.linalg.cond(G)))
+        cb.append(max(float(np.linalg.cond(G[j * b:(j + 1) * b, j * b:(j + 1) * b]))
+                      for j in range(s)))
+    return {"G_median": float(np.median(cg)), "G_max": max(cg),
+            "block_median": float(np.median(cb)), "block_max": max(cb)}
 
-    def conds(gram_of_step, steps, s_, bb):
-        cg, cb = [], []
-        for k in range(steps):
-            G = gram_of_step(k).cpu().numpy()
-            cg.append(float(np.linalg.cond(G)))
-            cb.append(max(float(np.linalg.cond(G[j * bb:(j + 1) * bb, j * bb:(j + 1) * bb]))
-                          for j in range(s_)))
-        return {"G_median": float(np.median(cg)), "G_max": max(cg),
-                "diag_block_median": float(np.median(cb)), "diag_block_max": max(cb)}
 
-    cond = {}
-    for s_ in (8, 32):
-        idx = cabcd.sample(seed, 0, 16 * s_, b, d).reshape(16, s_ * b)
-        cond[f"primal_s{s_}"] = conds(
-            lambda k: cabcd.gram(X, idx[k].contiguous(), 1.0 / n, lam)[0], 16, s_, b)
-        jdx = cabcd.sample(seed, 0, 16 * s_, b, n).reshape(16, s_ * b).long()
-        ar = torch.arange(s_ * b, dtype=torch.int32, device=X.device)
+def stability(cabcd, torch, synth, seed=2005, points=32):
+    """Numerical stability of the s-step methods (Section 6, the CA-BCD and
+    CA-BDCD convergence figures) on synthetic stand-ins with the paper's
+    regularisation rule, lambda = 1000 x the smallest eigenvalue of X X^T / n:
+    relative objective and solution error against iterations for
+    s = 1 ... 32 with one block sequence, run until FP64 reaches its floor;
+    FP64 and the BF16 / FP8 storage (each against the optimum of its own
+    stored matrix); and the condition numbers of the Gram matrices per s.
+    Primal: X = U diag(sigma) V^T, d = 512, n = 32768, sigma 1..1e3, b = 16,
+    H = 65536.  Dual: the same construction with d = 256, n = 1024, b' = 16,
+    H' = 32768 (A = X^T)."""
+    dev = "cuda"
+    res = {"s": list(STAB_S), "points": points,
+           "lambda_rule": "1000 x the smallest eigenvalue of X X^T / n (sigma_min = 1)"}
+    cases = {
+        "primal": dict(d=512, n=32768, b=16, H=65536, dual=False, data_seed=1010),
+        "dual": dict(d=256, n=1024, b=16, H=32768, dual=True, data_seed=1011),
+    }
+    for meth, c in cases.items():
+        d, n, b, H, dual = c["d"], c["n"], c["b"], c["H"], c["dual"]
+        X, y, _ = synth.spectral_ridge(d, n, c["data_seed"], sigma_max=1e3, device=dev)
+        lam = 1000.0 / n
+        rec = {"workload": f"X = U diag(sigma) V^T, d={d}, n={n}, sigma 1..1e3, "
+                           f"lambda={lam:.4g}, b={b}, H={H}, from zero",
+               "lambda": lam, "b": b, "H": H}
+        for fmt in ("f64", "bf16", "fp8"):
+            if fmt == "f64":
+                Xs = X
+                store = X.t().contiguous() if dual else X
+            else:
+                code = cabcd.BF16 if fmt == "bf16" else cabcd.FP8_E4M3
+                store = cabcd.quantize(X.t().contiguous() if dual else X, code)
+                Xs = store.dequantize()
+                Xs = Xs.t().contiguous() if dual else Xs
+            w_star, f_star = closed_form(cabcd, torch, Xs, y, lam)
+            curves = {}
+            t0 = time.perf_counter()
+            for s_ in STAB_S:
+                pts = stability_curve(cabcd, torch, store, y, lam, b, s_, H, points, seed,
+                                      w_star, f_star, dual=dual)
+                curves[f"s{s_}"] = {"h": [p[0] for p in pts], "obj": [p[1] for p in pts],
+                                    "sol": [p[2] for p in pts]}
+            s1 = curves["s1"]
+            keep = list(range(points // 8 - 1, points, points // 8))   # 8 points a curve
 
-        def dual_gram(k):
-            Y = X[:, jdx[k]].t().contiguous()   # the sampled data points (rows of X^T)
-            return cabcd.gram(Y, ar, 1.0 / (lam * n * n), 1.0 / n)[0]
-        cond[f"dual_s{s_}"] = conds(dual_gram, 16, s_, b)
-    res["cond"] = cond
-    log(f"stability cond: {cond}")
+            def thin(v):
+                return [float(f"{v[i]:.3g}") for i in keep]
+            rec[fmt] = {
+                "h": [curves["s1"]["h"][i] for i in keep],
+                "obj": {k: thin(v["obj"]) for k, v in curves.items()},
+                "sol": {k: thin(v["sol"]) for k, v in curves.items()},
+                # the largest gap of each s to s = 1 over all monitor points
+                "max_sol_gap_vs_s1": {k: float(f"{max(abs(a - b_) for a, b_ in zip(v['sol'], s1['sol'])):.3g}")
+                                      for k, v in curves.items()},
+                "seconds": round(time.perf_counter() - t0, 3)}
+            log(f"stability {meth} {fmt}: sol {rec[fmt]['sol']}")
+            del store, Xs
+        A = X.t().contiguous() if dual else X
+        scale, shift = (1.0 / (lam * n * n), 1.0 / n) if dual else (1.0 / n, lam)
+        rec["cond"] = {f"s{s_}": gram_conditions(cabcd, torch, A, scale, shift, b, s_, seed)
+                       for s_ in STAB_S}
+        log(f"stability {meth} cond: {rec['cond']}")
+        res[meth] = rec
+        del X, y, A
+        torch.cuda.empty_cache()
     return res
 
 
@@ -610,10 +684,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"extra": extra_records(args, cabcd, torch, synth, X, y)}), flush=True)
         return
-    out, X, y = headline(args, cabcd, torch, synth)
     if args.only_stability:
-        print(json.dumps({"stability": stability(cabcd, torch, X, y, args.lam)}), flush=True)
+        print(json.dumps({"stability": stability(cabcd, torch, synth)}), flush=True)
         return
+    out, X, y = headline(args, cabcd, torch, synth)
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(X, y, args.lam, args.b, args.s, args.cpu_steps, 2001)
@@ -621,10 +695,10 @@ def main():
         out["cpu_baseline"] = None
     if not args.no_extra:
         out["extra"] = extra_records(args, cabcd, torch, synth, X, y)
-    if not args.no_stability:
-        out["stability"] = stability(cabcd, torch, X, y, args.lam)
     del X, y
     torch.cuda.empty_cache()
+    if not args.no_stability:
+        out["stability"] = stability(cabcd, torch, synth)
     if not args.no_tol:
         out["time_to_tol"] = time_to_tol(cabcd, torch, synth)
     if not args.no_batch:

@@ -175,7 +175,9 @@ cabcd_status cabcd_sample(uint64_t seed, int64_t h0, int64_t count, int32_t b,
  *   G  = scale * Y Y^T + shift * I     (m x m, row-major, both triangles, ld m)
  *   Yu = Y u                           (m; only if u and Yu are non-NULL)
  * Primal CA-BCD uses scale 1/n, shift lambda; dual uses 1/(lambda n^2), 1/n.
- * Dense F64 / BF16 / FP8 (m <= 256) and CSR F64 (m <= 1024).  Low-precision
+ * Dense F64 / BF16 / FP8 (m <= 512; above 256 rows the Gram is assembled from
+ * 256-row Grams of the two row halves and of pairs of their 128-row quarters,
+ * about 1.5x the matrix-core work) and CSR F64 (m <= 1024).  Low-precision
  * rows are multiplied in their storage type on the matrix cores with FP32
  * accumulation inside a workgroup's slab; the slabs are summed and the row
  * scales applied in FP64; Yu is computed in FP64 from the decoded values.
@@ -219,7 +221,7 @@ cabcd_status cabcd_gram_noalloc(const cabcd_matrix* A, const int32_t* idx, int32
  * X may be dense F64, dense BF16 / FP8 (mixed precision: the Gram on the
  * stored codes with FP32 accumulation, everything else in FP64 on X^; set
  * opts->resid_every to recompute r exactly every few outer steps) or CSR F64.
- * 1 <= b <= min(d, 32), s >= 1, s*b <= 256 dense / 1024 CSR (512 when
+ * 1 <= b <= min(d, 32), s >= 1, s*b <= 512 dense / 1024 CSR (512 when
  * b > 16), H >= 0, lambda > 0; a larger s*b is CABCD_EUNSUPPORTED.
  */
 cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lambda,
@@ -237,7 +239,7 @@ cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lam
  * X^T may be dense F64, dense BF16 / FP8 (mixed precision as for the primal:
  * the Gram on the stored codes with FP32 accumulation, everything else in
  * FP64 on the dequantised X^; one row scale per data point) or CSR F64.
- * 1 <= b <= min(n, 32), s >= 1, s*b <= 256 dense / 1024 CSR (512 when
+ * 1 <= b <= min(n, 32), s >= 1, s*b <= 512 dense / 1024 CSR (512 when
  * b > 16), H >= 0, lambda > 0; a larger s*b is CABCD_EUNSUPPORTED.
  */
 cabcd_status cabcd_dual_bcd(const cabcd_matrix* XT, const double* y, double lambda,
@@ -330,8 +332,10 @@ typedef struct cabcd_problem {
                                 type per batch                                     */
   const double* y;           /* n labels                                           */
   double lambda;             /* > 0                                                */
-  int32_t b;                 /* block size, 1..16; 0: chosen by the autotuner      */
-  int32_t s;                 /* unrolling, s*b <= 256; 0: chosen by the autotuner  */
+  int32_t b;                 /* block size, 1..16; 0: chosen by the autotuner
+                                (4, 8 or 16; fewer only when d is smaller)         */
+  int32_t s;                 /* unrolling, s*b <= 256; 0: chosen by the autotuner
+                                (4 <= s <= 32 within s*b <= 256)                   */
   uint64_t seed;             /* sampler seed (blocks over [0, d))                  */
   int64_t H;                 /* inner-iteration budget; <= 0: unlimited            */
   double f_target;           /* > 0: retire at the first monitor point with

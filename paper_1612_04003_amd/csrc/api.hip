@@ -33,7 +33,8 @@ void clear_error() { g_err.clear(); }
 
 namespace {
 
-constexpr int kMaxSBDense = 256;            // s*b of one dense FP64 Gram launch
+constexpr int kMaxSBDense = 512;            // s*b of a dense Gram (above 256: four-part form)
+constexpr int kGramRows = 256;              // rows of one dense Gram launch
 constexpr int64_t kIdxChunkSteps = 4096;    // outer steps whose indices are drawn at once
 constexpr int kCsrAhead = 64;               // CSR: outer-step Grams computed per launch (max)
 constexpr int kDenseAhead = 32;             // dense: the same, when one Gram is too small
@@ -188,8 +189,17 @@ cabcd_status check_csr_device(const Mat& M, int* flag_dev, hipStream_t st) {
 
 int max_rows_per_gram(const Mat& M) { return M.csr ? kCsrMaxRows : kMaxSBDense; }
 
+// Plan of one dense Gram launch of m rows (at most kGramRows: larger Grams
+// are assembled from launches of kGramRows rows).
 GramPlan plan_for(const Mat& M, int m) {
+  m = std::min(m, kGramRows);
   return M.lowp() ? plan_gram_lp(m, M.cols, M.dtype) : plan_gram_f64(m, M.cols);
+}
+
+// A Gram of more than kGramRows rows: six partial sets of the 256-row plan
+// (two diagonal blocks, up to four cross blocks) and the two index lists.
+size_t big_partials(const Mat& M) {
+  return 6 * gram_partial_doubles(plan_for(M, kGramRows)) + (512 + 4 * 256) / 2;
 }
 
 size_t max_partials(const Mat& M, int sb_max) {
@@ -199,6 +209,7 @@ size_t max_partials(const Mat& M, int sb_max) {
     best = std::max(best, gram_partial_doubles(plan_for(M, std::min(m, sb_max))));
     if (m >= sb_max) break;
   }
+  if (sb_max > kGramRows) best = std::max(best, big_partials(M));
   return best;
 }
 
@@ -372,6 +383,37 @@ hipError_t mat_gram(const Mat& M, const int32_t* idx, int m, const double* u, do
     auto f = [&] { return launch_csr_gram(M.C, idx, m, u, scale, shift, overlap, G, Yu, st); };
     return timer ? timer->run(CABCD_PHASE_GRAM, f) : f();
   }
+  if (m > kGramRows) {
+    // rows [0, 256) and [256, m): the two diagonal blocks as two 256-row
+    // Grams (with Y u), the cross block from the 256-row Grams of pairs of
+    // 128-row halves (their off-diagonal quarter)
+    const GramPlan plan = plan_for(M, kGramRows);
+    const size_t set = gram_partial_doubles(plan);
+    int32_t* ia = reinterpret_cast<int32_t*>(partials + 6 * set);
+    int32_t* ib = ia + 512;
+    const int nc = big_cross_steps(m);
+    auto g = [&]() -> hipError_t {
+      hipError_t e = launch_big_index(idx, m, ia, ib, st);
+      if (e != hipSuccess) return e;
+      if (M.lowp()) {
+        e = launch_gram_lp(plan, M.dtype, M.Q, M.ld, M.cols, ia, kGramRows, u, partials, st, 2);
+        if (e != hipSuccess) return e;
+        return launch_gram_lp(plan, M.dtype, M.Q, M.ld, M.cols, ib, kGramRows, nullptr,
+                              partials + 2 * set, st, nc);
+      }
+      e = launch_gram_f64(plan, M.X, M.ld, M.cols, ia, kGramRows, u, partials, st, 2);
+      if (e != hipSuccess) return e;
+      return launch_gram_f64(plan, M.X, M.ld, M.cols, ib, kGramRows, nullptr, partials + 2 * set,
+                             st, nc);
+    };
+    auto r = [&] {
+      return launch_gram_reduce_big(plan, partials, idx, m, scale, shift, overlap, G, Yu, st,
+                                    partial_layout(M, plan), M.lowp() ? M.rs : nullptr);
+    };
+    hipError_t e = timer ? timer->run(CABCD_PHASE_GRAM, g) : g();
+    if (e != hipSuccess) return e;
+    return timer ? timer->run(CABCD_PHASE_REDUCE, r) : r();
+  }
   const GramPlan plan = plan_for(M, m);
   auto g = [&] {
     return M.lowp() ? launch_gram_lp(plan, M.dtype, M.Q, M.ld, M.cols, idx, m, u, partials, st)
@@ -396,7 +438,7 @@ int gram_slots(const Mat& M, int64_t sb) {
   if (M.csr)
     return (int)std::max<int64_t>(1, std::min<int64_t>(kCsrAhead, kAheadDoubles / (sb * sb)));
   const int64_t elem = M.dtype == CABCD_F64 ? 8 : (M.dtype == CABCD_BF16 ? 2 : 1);
-  if (sb * M.cols * elem > kAheadRowBytes) return 1;
+  if (sb > kGramRows || sb * M.cols * elem > kAheadRowBytes) return 1;
   const GramPlan p = plan_for(M, (int)sb);
   if (p.nsplit >= kDenseFill) return 1;
   const int64_t per = (int64_t)gram_partial_doubles(p) + sb * sb;   // partials and G

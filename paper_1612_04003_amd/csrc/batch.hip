@@ -577,10 +577,15 @@ double slab_work(int sb, int64_t cols, int dtype) {
   return std::max(flops / (dtype == CABCD_F64 ? kCuF64 : kCuLp), bytes / kCuBw);
 }
 
+// The tuner's block sizes are b in {4, 8, 16} (smaller only when d is) and its
+// unrollings s in [4, 32]: s < 4 would be (nearly) classical BCD, which the
+// s-step form exists to replace.
+constexpr int kTuneMinS = 4;
+
 int auto_b(int64_t d) {
   if (d >= 64) return 16;
   if (d >= 16) return 8;
-  if (d >= 8) return 4;
+  if (d >= 4) return 4;
   return (int)std::max<int64_t>(1, d);
 }
 
@@ -606,7 +611,7 @@ double plan_candidate(const std::vector<cabcd_problem>& pb, double rp, int cus,
     if (s == 0) {
       const int smax = std::min(32, kBMaxRows / b);
       s = (int)std::ceil((double)d / (b * rp));
-      s = std::max(1, std::min(s, smax));
+      s = std::max(std::min(kTuneMinS, smax), std::min(s, smax));
     }
     out[p].b = b;
     out[p].s = s;

@@ -12,8 +12,8 @@ namespace {
 
 using namespace gdev;
 
-// Several outer steps per launch: step blockIdx.y reads idx + step * m and
-// writes its partials at partials + step * pstride (u is NULL then).
+// Several row lists per launch: step blockIdx.y reads idx + step * m and
+// writes its partials (and its Y u, when u is given) at partials + step * pstride.
 template <int NB, int RPW>
 __global__ __launch_bounds__((Cfg<NB, RPW>::THREADS)) void gram_f64_kernel(
     const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
@@ -60,8 +60,49 @@ __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
 constexpr int kRedElems = 64;    // partial entries per reduction workgroup
 constexpr int kRedGroups = 16;   // split groups per entry (one wave each)
 
-// Step blockIdx.y: partials + step * nsplit * pstride, idx + step * m,
-// G + step * m * m (Yu is NULL for several steps).
+// Where the reduced entry e of step `step` of a Gram of more than 256 rows
+// goes (m in (256, 512], assembled from 256-row Grams; see
+// launch_big_index): set 0 holds the two diagonal 256 x 256 blocks (step k:
+// rows and columns 256 k + local) and Y u; set 1 holds the cross blocks, step
+// t giving rows 256 + 128 (t / 2) + (local row - 128) and columns
+// 128 (t % 2) + local column from the local block rows 8..15 x columns 0..7.
+__device__ __forceinline__ void store_entry_big(int64_t e, double t, int set, int step,
+                                                const int32_t* idx, int m, double scale,
+                                                double shift, int overlap,
+                                                double* __restrict__ G, double* __restrict__ Yu,
+                                                int layout, const float* __restrict__ rs) {
+  constexpr int kNblk = 136;
+  if (e >= (int64_t)kNblk * 256) {          // the Y u entries follow the blocks
+    const int p = 256 * step + (int)(e - (int64_t)kNblk * 256);
+    if (set == 0 && Yu != nullptr && p < m) glb(Yu)[p] = rs ? (double)glb(rs)[idx[p]] * t : t;
+    return;
+  }
+  int row, col;
+  bool lower;
+  entry_rc(e, layout, row, col, lower);
+  if (!lower) return;
+  int gr, gc;
+  if (set == 0) {
+    gr = 256 * step + row;
+    gc = 256 * step + col;
+  } else {
+    if (row < 128 || col >= 128) return;
+    gr = 256 + 128 * (step >> 1) + (row - 128);
+    gc = 128 * (step & 1) + col;
+  }
+  if (gr >= m || gc >= m) return;
+  const bool on = overlap ? (idx[gr] == idx[gc]) : (gr == gc);
+  const double sc = rs ? scale * (double)glb(rs)[idx[gr]] * (double)glb(rs)[idx[gc]] : scale;
+  const double v = sc * t + (on ? shift : 0.0);
+  glb(G)[(int64_t)gr * m + gc] = v;
+  glb(G)[(int64_t)gc * m + gr] = v;
+}
+
+// Step blockIdx.y: partials + step * nsplit * pstride.  MODE 0: the Gram of
+// step blockIdx.y (idx + step * m, G + step * m * m; Yu is NULL for several
+// steps).  MODE 1 / 2: sets 0 / 1 of a Gram of m in (256, 512] rows
+// (store_entry_big; idx is its m indices).
+template <int MODE>
 __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
     const double* __restrict__ partials, int nsplit, int nb, const int32_t* __restrict__ idx,
     int m, double scale, double shift, int overlap, double* __restrict__ G,
@@ -70,8 +111,10 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
   const int nblk = nb * (nb + 1) / 2;
   const int64_t pstride = (int64_t)nblk * 256 + 16 * nb;
   partials += (int64_t)blockIdx.y * nsplit * pstride;
-  idx += (int64_t)blockIdx.y * m;
-  G += (int64_t)blockIdx.y * m * m;
+  if constexpr (MODE == 0) {
+    idx += (int64_t)blockIdx.y * m;
+    G += (int64_t)blockIdx.y * m * m;
+  }
   const int el = threadIdx.x % kRedElems;
   const int grp = threadIdx.x / kRedElems;
   const int64_t e = (int64_t)blockIdx.x * kRedElems + el;
@@ -111,7 +154,39 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
   double t = red[0][el];
 #pragma unroll
   for (int g = 1; g < kRedGroups; ++g) t += red[g][el];
-  store_entry(e, t, nblk, idx, m, scale, shift, overlap, G, Yu, layout, rs);
+  if constexpr (MODE == 0)
+    store_entry(e, t, nblk, idx, m, scale, shift, overlap, G, Yu, layout, rs);
+  else
+    store_entry_big(e, t, MODE - 1, (int)blockIdx.y, idx, m, scale, shift, overlap, G, Yu,
+                    layout, rs);
+}
+
+// Index lists of a Gram of m in (256, 512] rows (one workgroup of 512):
+// ia = the m indices padded to 512 with idx[0] (two 256-row Grams: the
+// diagonal blocks); ib[t] (t < 4) = idx[128 x .. 128 x + 128) followed by
+// ia[256 + 128 y .. 256 + 128 y + 128), x = t % 2, y = t / 2, whose 256-row
+// Gram holds the cross block of rows 256 + 128 y.. and columns 128 x.. .
+// Padding rows are multiplied and never stored.
+__global__ __launch_bounds__(512) void big_index_kernel(const int32_t* __restrict__ idx, int m,
+                                                        int32_t* __restrict__ ia,
+                                                        int32_t* __restrict__ ib) {
+  const int t = threadIdx.x;
+  ia[t] = idx[t < m ? t : 0];
+  const int i0 = idx[0];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int slot = t + 512 * q;             // 0 .. 1023
+    const int list = slot >> 8, pos = slot & 255;
+    const int x = list & 1, y = list >> 1;
+    int v;
+    if (pos < 128) {
+      v = idx[128 * x + pos];
+    } else {
+      const int r = 256 + 128 * y + (pos - 128);
+      v = r < m ? idx[r] : i0;
+    }
+    ib[slot] = v;
+  }
 }
 
 template <int NB, int RPW>
@@ -210,7 +285,7 @@ size_t gram_partial_doubles(const GramPlan& p) {
 hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
                            const int32_t* idx, int m, const double* u, double* partials,
                            hipStream_t st, int nsteps) {
-  if (nsteps < 1 || nsteps > 65535 || (nsteps > 1 && u != nullptr)) return hipErrorInvalidValue;
+  if (nsteps < 1 || nsteps > 65535) return hipErrorInvalidValue;
   switch (p.nb) {
     case 1: return launch_nb<1, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
     case 2: return launch_nb<2, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
@@ -228,9 +303,35 @@ hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const i
   if (nsteps < 1 || nsteps > 65535 || (nsteps > 1 && Yu != nullptr)) return hipErrorInvalidValue;
   const int64_t entries = (int64_t)p.nblk * 256 + 16 * p.nb;
   const int64_t blocks = (entries + kRedElems - 1) / kRedElems;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks, (unsigned)nsteps),
+  hipLaunchKernelGGL(gram_reduce_kernel<0>, dim3((unsigned)blocks, (unsigned)nsteps),
                      dim3(kRedElems * kRedGroups), 0, st, partials, p.nsplit, p.nb, idx, m, scale,
                      shift, overlap ? 1 : 0, G, Yu, layout, rs);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_index(const int32_t* idx, int m, int32_t* ia, int32_t* ib, hipStream_t st) {
+  if (m <= 256 || m > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(big_index_kernel, dim3(1), dim3(512), 0, st, idx, m, ia, ib);
+  return hipGetLastError();
+}
+
+int big_cross_steps(int m) { return m - 256 > 128 ? 4 : 2; }
+
+hipError_t launch_gram_reduce_big(const GramPlan& p, const double* partials, const int32_t* idx,
+                                  int m, double scale, double shift, bool overlap, double* G,
+                                  double* Yu, hipStream_t st, int layout, const float* rs) {
+  if (p.nb != 16 || m <= 256 || m > 512) return hipErrorInvalidValue;
+  const int64_t entries = (int64_t)p.nblk * 256 + 16 * p.nb;
+  const int64_t blocks = (entries + kRedElems - 1) / kRedElems;
+  const size_t set = gram_partial_doubles(p);
+  hipLaunchKernelGGL(gram_reduce_kernel<1>, dim3((unsigned)blocks, 2u),
+                     dim3(kRedElems * kRedGroups), 0, st, partials, p.nsplit, p.nb, idx, m, scale,
+                     shift, overlap ? 1 : 0, G, Yu, layout, rs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_reduce_kernel<2>, dim3((unsigned)blocks, (unsigned)big_cross_steps(m)),
+                     dim3(kRedElems * kRedGroups), 0, st, partials + 2 * set, p.nsplit, p.nb, idx,
+                     m, scale, shift, overlap ? 1 : 0, G, nullptr, layout, rs);
   return hipGetLastError();
 }
 

@@ -120,8 +120,9 @@ struct GramPlan {
 GramPlan plan_gram_f64(int m, int64_t cols);
 size_t gram_partial_doubles(const GramPlan& p);   // partial G + partial Yu
 // partials: nsplit * (nblk*256 + 16*nb) doubles.
-// nsteps > 1: the Grams of nsteps outer steps in one launch (step k reads
-// idx + k m, writes partials + k gram_partial_doubles(p); u must be NULL).
+// nsteps > 1: the Grams of nsteps row lists in one launch (step k reads
+// idx + k m, writes partials + k gram_partial_doubles(p), its Y u with the
+// same u).
 hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
                            const int32_t* idx, int m, const double* u, double* partials,
                            hipStream_t st, int nsteps = 1);
@@ -138,6 +139,18 @@ hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const i
                               int m, double scale, double shift, bool overlap, double* G,
                               double* Yu, hipStream_t st, int layout = 0,
                               const float* rs = nullptr, int nsteps = 1);
+// Grams of m in (256, 512] rows from 256-row Grams (plan p of 256 rows, nb 16):
+// launch_big_index builds the index lists ia (512: the rows padded with
+// idx[0]) and ib (4 x 256: half-bands [rows 128 x.. ; rows 256 + 128 y..]);
+// the Gram launches then write 2 + big_cross_steps(m) partial sets of
+// gram_partial_doubles(p) each (ia as 2 steps with Y u, then ib), which
+// launch_gram_reduce_big sums into G (m x m) and Y u.
+hipError_t launch_big_index(const int32_t* idx, int m, int32_t* ia, int32_t* ib, hipStream_t st);
+int big_cross_steps(int m);
+hipError_t launch_gram_reduce_big(const GramPlan& p, const double* partials, const int32_t* idx,
+                                  int m, double scale, double shift, bool overlap, double* G,
+                                  double* Yu, hipStream_t st, int layout = 0,
+                                  const float* rs = nullptr);
 
 // ------------------------------------------------------------------ fused solve
 // One outer step's s block solves through the unrolled recurrence, followed by

@@ -552,7 +552,7 @@ int gram_lp_partial_layout(const GramPlan& p, int dtype, const void* A, int64_t 
 hipError_t launch_gram_lp(const GramPlan& p, int dtype, const void* A, int64_t ld, int64_t cols,
                           const int32_t* idx, int m, const double* u, double* partials,
                           hipStream_t st, int nsteps) {
-  if (nsteps < 1 || nsteps > 65535 || (nsteps > 1 && u != nullptr)) return hipErrorInvalidValue;
+  if (nsteps < 1 || nsteps > 65535) return hipErrorInvalidValue;
   if (dtype == CABCD_BF16)
     return launch_lp_fmt<CABCD_BF16>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
   return launch_lp_fmt<CABCD_FP8_E4M3>(p, A, ld, cols, idx, m, nsteps, u, partials, st);

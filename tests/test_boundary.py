@@ -54,7 +54,7 @@ def _fake_matrix(rows, cols, kind=cabcd.DENSE, dtype=cabcd.F64):
     (dict(s=0), cabcd.EINVAL),
     (dict(H=-1), cabcd.EINVAL),
     (dict(b=33), cabcd.EUNSUPPORTED),
-    (dict(b=16, s=17), cabcd.EUNSUPPORTED),
+    (dict(b=16, s=33), cabcd.EUNSUPPORTED),   # s b = 528 > 512 dense
 ])
 def test_primal_argument_errors(kw, status):
     lib = cabcd.load()
@@ -66,6 +66,18 @@ def test_primal_argument_errors(kw, status):
                               ctypes.c_void_p(0x4000), None, None)
     assert st == status
     assert lib.cabcd_last_error().decode() != ""
+
+
+def test_csr_large_blocks_limit():
+    # blocks of b > 16 take the 32-lane solves, which hold at most 512 rows
+    lib = cabcd.load()
+    M = _fake_matrix(20000, 1 << 20, kind=cabcd.CSR_KIND)
+    M.rowptr, M.colidx, M.vals, M.nnz = 0x1000, 0x2000, 0x3000, 10
+    for fn in (lib.cabcd_primal_bcd, lib.cabcd_dual_bcd):
+        st = fn(ctypes.byref(M), ctypes.c_void_p(0x2000), 1e-3, 32, 17, 10, 1,
+                ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), None, None)
+        assert st == cabcd.EUNSUPPORTED
+        assert "512" in lib.cabcd_last_error().decode()
 
 
 def test_matrix_errors():
@@ -88,7 +100,10 @@ def test_workspace_bytes_grows_with_problem():
     a = lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(64, 1024)), 4, 8)
     b = lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(2048, 262144)), 8, 32)
     assert 0 < a < b
-    assert lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(64, 1024)), 16, 17) == 0
+    assert lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(64, 1024)), 16, 33) == 0
+    # s b in (256, 512]: the four-part dense Gram needs more partials than s b = 256
+    c = lib.cabcd_workspace_bytes(ctypes.byref(_fake_matrix(2048, 262144)), 16, 32)
+    assert c > b
 
 
 def test_batch_struct_layout_matches_header():

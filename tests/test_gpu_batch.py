@@ -133,7 +133,9 @@ def test_batch_autotuned_reaches_1e6(gpu_lib):
          f"at 3 of 4 monitor points)")
     assert act == 0
     for q, fst, inf, d in zip(probs, fstars, infos, ds):
-        assert 1 <= inf["b"] <= 16 and inf["b"] <= d and inf["b"] * inf["s"] <= 256
+        # the tuner's range: b in {4, 8, 16}, 4 <= s <= 32, s b <= 256
+        assert inf["b"] in (4, 8, 16) and inf["b"] <= d and inf["b"] * inf["s"] <= 256
+        assert 4 <= inf["s"] <= 32
         w = q["w"].cpu().numpy()
         rel = (bcd.primal_objective(q["Xc"], q["yc"], q["lam"], w) - fst) / fst
         assert rel <= 1e-6 * (1 + 1e-6)

@@ -237,3 +237,94 @@ def test_fp8_nan_codes_read_as_nan(gpu_lib):
     assert np.isnan(rn[7]) and np.isnan(rn[9])
     assert np.all(rn[[k for k in range(40) if k not in (7, 9)]] == 2.5)
     assert np.isnan(f.item())
+
+
+# ------------------------------------------------------------------ s b in (256, 512]
+
+@pytest.mark.parametrize("m,cols", [(257, 1000), (300, 4098), (384, 20000), (385, 777),
+                                    (512, 32768), (512, 65), (511, 5001)])
+def test_big_gram_matches_oracle(gpu_lib, m, cols):
+    """Gram of 257..512 gathered rows (assembled from 256-row Grams), with
+    repeated indices, against the oracle's definition."""
+    _say("big gram", m, cols)
+    rows = m + 40
+    g = torch.Generator().manual_seed(m * 7 + cols)
+    A = torch.randn(rows, cols, generator=g, dtype=torch.float64)
+    u = torch.randn(cols, generator=g, dtype=torch.float64)
+    idx = torch.randint(0, rows, (m,), generator=g, dtype=torch.int32)
+    scale, shift = 1.0 / cols, 0.37
+    G, Yu = gpu_lib.gram(A.to(DEV), idx.to(DEV), scale, shift, u.to(DEV))
+    Go, Yo = bcd.gram(A.numpy(), idx.numpy(), scale, shift, u.numpy())
+    Y = np.abs(A.numpy()[idx.numpy()])
+    assert np.all(np.abs(G.cpu().numpy() - Go) <= 1e-12 * scale * (Y @ Y.T) + 1e-300)
+    assert torch.equal(G, G.t())
+    assert np.all(np.abs(Yu.cpu().numpy() - Yo) <= 1e-12 * (Y @ np.abs(u.numpy())) + 1e-300)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("m,cols", [(300, 4096), (512, 20000), (400, 4099)])
+def test_big_lowp_gram_matches_oracle(gpu_lib, dtype, m, cols):
+    _say("big lowp gram", dtype, m, cols)
+    rows = m + 9
+    rng = np.random.default_rng(m + cols)
+    X = rng.standard_normal((rows, cols)) * np.exp(rng.standard_normal(rows))[:, None]
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(torch.tensor(X, device=DEV), code)
+    Xh = Q.dequantize().cpu().numpy()
+    idx = rng.integers(0, rows, size=m).astype(np.int32)
+    u = rng.standard_normal(cols)
+    scale, shift = 1.0 / cols, 0.5
+    G, Yu = gpu_lib.gram(Q, torch.tensor(idx, device=DEV), scale, shift,
+                         torch.tensor(u, device=DEV))
+    Go, Yo = bcd.gram(Xh, idx, scale, shift, u)
+    Y = np.abs(Xh[idx])
+    # FP32 accumulation bound of the mixed-precision Gram (as for 256 rows)
+    rel_bound = cols * 2.0 ** -24 + (0.0 if dtype == "bf16" else 2.0 ** -12)
+    assert np.all(np.abs(G.cpu().numpy() - Go) <= rel_bound * scale * (Y @ Y.T) + 1e-300)
+    assert np.all(np.abs(Yu.cpu().numpy() - Yo) <= 1e-12 * (Y @ np.abs(u)) + 1e-300)
+
+
+@pytest.mark.parametrize("d,n,b,s,H", [
+    (1024, 8192, 16, 32, 2 * 32 + 7),   # s b = 512: b = 16, s = 32
+    (700, 3001, 8, 64, 150),            # s b = 512 with b = 8 (odd n: unaligned rows)
+    (600, 4000, 12, 40, 90),            # s b = 480, b not a power of two
+    (300, 2048, 16, 20, 50),            # s b = 320: half of the cross blocks
+])
+def test_primal_big_sb_matches_oracle(gpu_lib, d, n, b, s, H):
+    _say("primal big sb", d, n, b, s, H)
+    X, y, _ = synth.gaussian_ridge(d, n, 500 + d)
+    t = gpu_lib.new_timing()
+    w, r = gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), 1e-3, b, s, H, 21, timing=t)
+    steps = -(-H // s)
+    _assert_per_step(gpu_lib, t, steps)
+    wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), 1e-3, b, s, H, 21)
+    assert _rel(w.cpu(), wo) <= 1e-10
+    assert _rel(r.cpu(), zo - y.numpy()) <= 1e-10
+
+
+def test_dual_big_sb_matches_oracle(gpu_lib):
+    d, n, b, s, H = 3000, 2048, 16, 32, 70
+    _say("dual big sb", d, n, b, s, H)
+    X, y, _ = synth.gaussian_ridge(d, n, 808)
+    a, w = gpu_lib.dual_bcd(X.t().contiguous().to(DEV), y.to(DEV), 1e-2, b, s, H, 22)
+    ao, wo = bcd.dual_bcd(X.numpy(), y.numpy(), 1e-2, b, s, H, 22)
+    assert _rel(a.cpu(), ao) <= 1e-10
+    assert _rel(w.cpu(), wo) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_mixed_primal_big_sb_reaches_1e6(gpu_lib, dtype):
+    d, n, b, s, lam = 512, 16384, 16, 32, 1e-4
+    H = 40 * s
+    _say("mixed big sb", dtype, d, n, b, s, H)
+    X, y, _, _ = synth.colscaled_ridge(d, n, 19)
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(X.to(DEV), code)
+    Xh = Q.dequantize().cpu().numpy()
+    yn = y.numpy()
+    fstar = bcd.primal_objective(Xh, yn, lam, bcd.ridge_closed_form(Xh, yn, lam))
+    w, r = gpu_lib.primal_bcd(Q, y.to(DEV), lam, b, s, H, 4, resid_every=4)
+    wn = w.cpu().numpy()
+    rel_obj = (bcd.primal_objective(Xh, yn, lam, wn) - fstar) / fstar
+    _say(f"  rel obj error {rel_obj:.2e}")
+    assert rel_obj <= 1e-6
