@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--s", type=int, default=32)
     ap.add_argument("--lam", type=float, default=1e-4)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--settle", type=float, default=0.1,
+                    help="seconds of untimed outer steps before the warm-up (clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tol", action="store_true", help="skip the time-to-1e-6 runs")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra records")
@@ -130,10 +132,15 @@ def closed_form(cabcd, torch, X, y, lam):
     return w, f.item()
 
 
-def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False, mask=0):
+def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False, mask=0,
+                 settle_s=0.0):
     """Warm up, then time `steps` outer steps; returns (elapsed s, phase dict).
     `mask` selects the phases bracketed by HIP events (0: all); every event
-    pair costs GPU time, so the timed headline run brackets the Gram only."""
+    pair costs GPU time, so the timed headline run brackets the Gram only.
+    settle_s > 0: before the `warmup` steps, untimed outer steps run until the
+    GPU has been busy that long: coming out of idle, the GPU's clocks take
+    some 20 ms of load to ramp up (the first 20 steps of the headline run 15 %
+    slower than the steady state of a long solve)."""
     rows, cols = X.shape
     coord = torch.zeros(rows, dtype=torch.float64, device=y.device)
     comp = torch.empty(cols, dtype=torch.float64, device=y.device)
@@ -142,6 +149,12 @@ def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False,
         kw0 = dict(alpha=coord, w=comp)
     else:
         kw0 = dict(w=coord, r=comp)
+    if settle_s > 0.0:
+        t_end = time.perf_counter() + settle_s
+        while time.perf_counter() < t_end:
+            run(X, y, lam, b, s, 10 * s, seed, **kw0)
+            torch.cuda.synchronize()
+        coord.zero_()
     run(X, y, lam, b, s, warmup * s, seed, **kw0)
     torch.cuda.synchronize()
     tm = cabcd.new_timing()
@@ -180,7 +193,7 @@ def headline(args, cabcd, torch, synth):
     log(f"timing {args.steps} steps")
     gram_only = 1 << cabcd.PHASES.index("gram")
     elapsed, ph = timed_primal(cabcd, torch, X, y, lam, b, s, args.steps, args.warmup, 2001,
-                               mask=gram_only)
+                               mask=gram_only, settle_s=args.settle)
     log("phase breakdown run (every phase bracketed by events)")
     _, ph_all = timed_primal(cabcd, torch, X, y, lam, b, s, min(args.steps, 10), 1, 2001)
     gram_flops = n * sb * (sb + 1)

@@ -139,7 +139,7 @@ typedef struct cabcd_opts {
 #define CABCD_PHASE_SAMPLE 0    /* block sampler                                   */
 #define CABCD_PHASE_GRAM 1      /* gathered-row Gram (with Y u when fused)         */
 #define CABCD_PHASE_REDUCE 2    /* sum of the Gram partials, scale and overlap     */
-#define CABCD_PHASE_SOLVE 3     /* s Cholesky solves + recurrence + x[idx] += d;   */
+#define CABCD_PHASE_SOLVE 3     /* s block solves + recurrence + x[idx] += d;      */
                                 /* also the launches that invert the diagonal     */
                                 /* blocks of Grams computed ahead                 */
 #define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta                 */

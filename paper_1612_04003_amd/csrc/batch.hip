@@ -13,7 +13,8 @@
 //      one-problem Gram kernel);
 //   4. counts its arrival; the workgroup that completes the problem's set of
 //      slabs sums the partials in slab order (deterministic), runs the fused
-//      solve of the s blocks (Cholesky/recurrence, w[idx] += delta) and records
+//      solve of the s blocks (Gauss-Jordan block inverses, recurrence,
+//      w[idx] += delta) and records
 //      the step.  No workgroup ever waits for another.
 // A second persistent kernel evaluates f(w) every few rounds, either
 // recomputing r = X^T w - y exactly from X (the periodic full residual of the

@@ -546,14 +546,17 @@ __device__ __forceinline__ void gram_slab_dma(const double* __restrict__ A, int6
 // end.  Needs A 16-byte aligned with an even ld; chunks that cross the end of
 // the slab are written with ordinary LDS stores (zero-filled).
 struct D16 {
-  static constexpr int NB = 16, SBP = 256, NBLK = 136, KT = 16, CH = 8;
+  static constexpr int NB = 16, SBP = 256, NBLK = 136, KT = 16, CH = KT / 2;
+  static constexpr int PP = KT / 8;                  // 128-bit fragment reads per tile
   static constexpr int THREADS = 512;
   static constexpr int TILE = SBP * KT + KT;         // doubles per buffer: rows, then u
   static constexpr int DMA_PER_WAVE = SBP * CH / THREADS;   // 4 instructions
   static constexpr int LDS = 2 * TILE;
 };
 
-__device__ __forceinline__ int d16_swz(int r) { return (r >> 1) & 7; }
+// Chunk swizzle of row r: the sixteen rows of a fragment read land on
+// distinct banks (8 chunks a row: (r >> 1) & 7; 16 chunks a row: r & 15).
+__device__ __forceinline__ int d16_swz(int r) { return D16::CH == 8 ? (r >> 1) & 7 : r & 15; }
 
 // The whole slab for wave W (block rows W and 15 - W); gram_slab_dma16 picks
 // the instantiation once, so each wave's tile loop is one straight-line path
@@ -578,8 +581,8 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
 #pragma unroll
   for (int i = 0; i < C::DMA_PER_WAVE; ++i) {
     const int q = (C::DMA_PER_WAVE * W + i) * 64 + lane;
-    const int r = q >> 3;
-    cofs[i] = 2 * ((q & 7) ^ d16_swz(r));
+    const int r = q / C::CH;
+    cofs[i] = 2 * ((q % C::CH) ^ d16_swz(r));
     src[i] = Ag + (int64_t)idx[r < m ? r : 0] * ld;   // rows past m: any valid row
   }
   const bool want_u = u != nullptr;
@@ -601,7 +604,7 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
         *reinterpret_cast<double2*>(dst + 2 * lane) = v;
       }
     }
-    // the tile's 16 entries of u (zeros without u): lanes 0..7 of wave 7
+    // the tile's KT entries of u (zeros without u): lanes 0..CH-1 of wave 7
     if (W == 7 && lane < C::CH) {
       double* dst = T + C::SBP * C::KT;
       const int64_t k = k0 + 2 * lane;
@@ -620,8 +623,9 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
   // lane & 15 of every block row, chunk 4 pp + lane / 16, swizzled.
   const int g = lane >> 4;
   const int rl = lane & 15;
-  const int lane_off[2] = {rl * C::KT + 2 * ((0 + g) ^ d16_swz(rl)),
-                           rl * C::KT + 2 * ((4 + g) ^ d16_swz(rl))};
+  int lane_off[C::PP];
+#pragma unroll
+  for (int pp = 0; pp < C::PP; ++pp) lane_off[pp] = rl * C::KT + 2 * ((4 * pp + g) ^ d16_swz(rl));
 
   d4 acc[17];
 #pragma unroll
@@ -635,7 +639,7 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
     if (t + 1 < ntiles) issue(t + 1, (t + 1) & 1);
     const double* tile = lds + (t & 1) * C::TILE;
 #pragma unroll
-    for (int pp = 0; pp < 2; ++pp) {
+    for (int pp = 0; pp < C::PP; ++pp) {
       const double* base = tile + lane_off[pp];
       auto frag = [&](int r) {   // rows 16 r .. 16 r + 15, this lane's chunk of pair pp
         return *reinterpret_cast<const double2*>(base + r * 16 * C::KT);
