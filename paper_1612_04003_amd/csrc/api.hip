@@ -41,6 +41,11 @@ constexpr int kDenseAhead = 32;             // dense: the same, when one Gram is
 constexpr int kDenseFill = 512;             // workgroups that fill the GPU (two per CU)
 constexpr int64_t kAheadRowBytes = 8 << 20; // dense: gathered rows small enough to read twice
 constexpr int64_t kAheadDoubles = (int64_t)8 << 20;   // their buffers (64 MiB at most)
+constexpr int kSplitMinRows = 256;          // CSR: the split Gram from this many rows a step
+constexpr int kSplitMaxRows = 512;
+constexpr int kSplitAhead = 16;             // steps per split Gram launch (at most)
+constexpr size_t kSplitBudget = (size_t)512 << 20;   // its scratch (bytes, at most)
+constexpr int64_t kSplitMaxCols = (int64_t)1 << 22;   // its per-step tables index columns
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
 
@@ -50,17 +55,17 @@ struct Pool {
   size_t cap = 0;
 };
 std::mutex g_pool_mu;
-std::vector<Pool> g_pools;
+std::vector<Pool> g_pools[2];   // [0]: step buffers, [1]: the split sparse Gram's scratch
 
-cabcd_status pool_get(size_t bytes, void** out) {
+cabcd_status pool_get(size_t bytes, void** out, int which = 0) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     set_error("hipGetDevice failed");
     return CABCD_EHIP;
   }
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1);
-  Pool& p = g_pools[dev];
+  if ((int)g_pools[which].size() <= dev) g_pools[which].resize(dev + 1);
+  Pool& p = g_pools[which][dev];
   if (p.cap < bytes) {
     if (p.ptr != nullptr) {
       (void)hipDeviceSynchronize();
@@ -471,7 +476,15 @@ hipError_t mat_gram_steps(const Mat& M, const int32_t* idx, int m, int nsteps, d
   });
 }
 
+// CSR steps of kSplitMinRows..kSplitMaxRows rows whose Grams are computed
+// ahead take the split Gram (heavy columns dense, light ones by column lists).
+bool use_split(const Mat& M, int64_t sb) {
+  return M.csr && sb >= kSplitMinRows && sb <= kSplitMaxRows && M.cols <= kSplitMaxCols &&
+         gram_slots(M, sb) > 1;
+}
+
 struct StepBuffers {
+  int* split_prep;   // the split Gram's per-matrix numbering of heavy columns
   int* status;
   int32_t* idx;      // kIdxChunkSteps * s * b
   double* G;         // gram_slots x sb x sb
@@ -489,6 +502,7 @@ struct StepBuffers {
 size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp_len,
               bool checks) {
   const int sb = s * b;
+  B.split_prep = c.take<int>(use_split(M, sb) ? csr_split_prepare_ints(M.C) : 1);
   B.status = c.take<int>(1);
   B.idx = c.take<int32_t>((size_t)kIdxChunkSteps * sb);
   B.G = c.take<double>((size_t)gram_slots(M, sb) * sb * sb);
@@ -618,6 +632,51 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   e = check_csr_device(M, B.status, st);
   if (e != CABCD_OK) return e;
 
+  // The split sparse Gram: heavy columns numbered once for this matrix, its
+  // data-dependent scratch from the second pool (or from a caller workspace
+  // that has room for it beyond `need`; otherwise the Grams stay on the
+  // row-pair kernel).
+  const int64_t sb_full = (int64_t)s * b;
+  bool split = use_split(M, sb_full);
+  CsrSplitInfo sinfo{};
+  int ksplit = 0;
+  double* split_d = nullptr;
+  int* split_i = nullptr;
+  if (split) {
+    HIP_TRY(csr_split_prepare(M.C, B.split_prep, &sinfo, st));
+    ksplit = std::min(gram_slots(M, sb_full), kSplitAhead);
+    // a launch takes 1..ksplit steps; its doubles, then its ints, must fit
+    size_t dmax = 0, imax = 0;
+    auto bytes_of = [&](int k) {
+      dmax = imax = 0;
+      for (int j = 1; j <= k; ++j) {
+        const SplitLayout L = csr_split_layout(sinfo, M.cols, (int)sb_full, j);
+        dmax = std::max(dmax, L.doubles);
+        imax = std::max(imax, L.ints);
+      }
+      return dmax * sizeof(double) + imax * sizeof(int) + 512;
+    };
+    while (ksplit > 1 && bytes_of(ksplit) > kSplitBudget) ksplit /= 2;
+    const size_t sbytes = bytes_of(ksplit);
+    void* sp = nullptr;
+    if (sbytes > kSplitBudget) {
+      split = false;   // rows too long for the per-step entry tables
+    } else if (o.workspace != nullptr) {
+      // the split scratch starts at the first 256-byte boundary past `need`
+      const uintptr_t w0 = reinterpret_cast<uintptr_t>(o.workspace);
+      const uintptr_t s0 = (w0 + need + 255) & ~(uintptr_t)255;
+      if (s0 + sbytes <= w0 + o.workspace_bytes) sp = reinterpret_cast<void*>(s0);
+      split = sp != nullptr;
+    } else {
+      e = pool_get(sbytes, &sp, 1);
+      if (e != CABCD_OK) return e;
+    }
+    if (split) {
+      split_d = static_cast<double*>(sp);
+      split_i = reinterpret_cast<int*>(split_d + dmax);
+    }
+  }
+
   hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, B.status, 0);
   HIP_TRY(hipGetLastError());
 
@@ -693,8 +752,15 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
         // the Grams of the next full outer steps whose indices are at hand
         int64_t avail = (H - h) / s;
         if (o.explicit_idx == nullptr) avail = std::min(avail, (chunk_end - h) / s);
-        const int nst = (int)std::min<int64_t>(K, std::max<int64_t>(avail, 1));
-        HIP_TRY(mat_gram_steps(M, idx, m, nst, scale, shift, B.G, B.partials, st, &timer));
+        const int nst =
+            (int)std::min<int64_t>(split ? ksplit : K, std::max<int64_t>(avail, 1));
+        if (split)
+          HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
+            return launch_csr_gram_split(M.C, sinfo, idx, m, nst, scale, shift, true, B.G,
+                                         split_d, split_i, st);
+          }));
+        else
+          HIP_TRY(mat_gram_steps(M, idx, m, nst, scale, shift, B.G, B.partials, st, &timer));
         // their diagonal blocks inverted together, off the solves' chains
         if (pre_inv)
           HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] {

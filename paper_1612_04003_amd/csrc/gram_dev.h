@@ -724,11 +724,14 @@ __device__ __forceinline__ void entry_rc(int64_t e, int layout, int& row, int& c
   lower = r != cb || row >= col;
 }
 
-// Writes the reduced entry e (sum t of its partials) to Gov / Yu.
+// Writes the reduced entry e (sum t of its partials) to Gov / Yu.  add (may be
+// NULL): an m x m row-major term added to the sum before scaling, read at
+// (row, col) with row >= col (the light-column part of a split sparse Gram).
 __device__ __forceinline__ void store_entry(int64_t e, double t, int nblk, const int32_t* idx,
                                             int m, double scale, double shift, int overlap,
                                             double* __restrict__ G, double* __restrict__ Yu,
-                                            int layout, const float* __restrict__ rs) {
+                                            int layout, const float* __restrict__ rs,
+                                            const double* __restrict__ add = nullptr) {
   if (e >= (int64_t)nblk * 256) {          // the Y u entries follow the blocks
     const int p = (int)(e - (int64_t)nblk * 256);
     if (Yu != nullptr && p < m) glb(Yu)[p] = rs ? (double)glb(rs)[idx[p]] * t : t;
@@ -741,6 +744,7 @@ __device__ __forceinline__ void store_entry(int64_t e, double t, int nblk, const
     const bool on = overlap ? (idx[row] == idx[col]) : (row == col);
     const double sc =
         rs ? scale * (double)glb(rs)[idx[row]] * (double)glb(rs)[idx[col]] : scale;
+    if (add != nullptr) t += glb(add)[(int64_t)row * m + col];
     const double v = sc * t + (on ? shift : 0.0);
     glb(G)[(int64_t)row * m + col] = v;
     glb(G)[(int64_t)col * m + row] = v;

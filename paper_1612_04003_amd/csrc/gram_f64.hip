@@ -57,8 +57,11 @@ __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
                   partials + (int64_t)blockIdx.x * (D16::NBLK * 256 + D16::SBP), lds);
 }
 
-constexpr int kRedElems = 64;    // partial entries per reduction workgroup
-constexpr int kRedGroups = 16;   // split groups per entry (one wave each)
+// A reduction workgroup has 1024 threads: GROUPS split groups (a wave or more
+// each) for 1024 / GROUPS entries.  Many splits take 16 groups of 64 entries;
+// a few splits take one group, each thread summing all of its entry's splits.
+constexpr int kRedThreads = 1024;
+int red_groups(int nsplit) { return nsplit <= 4 ? 1 : 16; }
 
 // Where the reduced entry e of step `step` of a Gram of more than 256 rows
 // goes (m in (256, 512], assembled from 256-row Grams; see
@@ -70,7 +73,8 @@ __device__ __forceinline__ void store_entry_big(int64_t e, double t, int set, in
                                                 const int32_t* idx, int m, double scale,
                                                 double shift, int overlap,
                                                 double* __restrict__ G, double* __restrict__ Yu,
-                                                int layout, const float* __restrict__ rs) {
+                                                int layout, const float* __restrict__ rs,
+                                                const double* __restrict__ add) {
   constexpr int kNblk = 136;
   if (e >= (int64_t)kNblk * 256) {          // the Y u entries follow the blocks
     const int p = 256 * step + (int)(e - (int64_t)kNblk * 256);
@@ -93,36 +97,43 @@ __device__ __forceinline__ void store_entry_big(int64_t e, double t, int set, in
   if (gr >= m || gc >= m) return;
   const bool on = overlap ? (idx[gr] == idx[gc]) : (gr == gc);
   const double sc = rs ? scale * (double)glb(rs)[idx[gr]] * (double)glb(rs)[idx[gc]] : scale;
+  if (add != nullptr) t += glb(add)[(int64_t)gr * m + gc];
   const double v = sc * t + (on ? shift : 0.0);
   glb(G)[(int64_t)gr * m + gc] = v;
   glb(G)[(int64_t)gc * m + gr] = v;
 }
 
-// Step blockIdx.y: partials + step * nsplit * pstride.  MODE 0: the Gram of
-// step blockIdx.y (idx + step * m, G + step * m * m; Yu is NULL for several
-// steps).  MODE 1 / 2: sets 0 / 1 of a Gram of m in (256, 512] rows
-// (store_entry_big; idx is its m indices).
-template <int MODE>
-__global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
+// Partial set blockIdx.y: partials + set * nsplit * pstride.  MODE 0: the
+// Gram of step blockIdx.y (idx + step * m, G and add + step * m * m; Yu is
+// NULL for several steps).  MODE 1 / 2: sets 0 / 1 of Grams of m in
+// (256, 512] rows (store_entry_big): `per` partial sets per Gram (2 diagonal /
+// big_cross_steps(m) cross), so set q belongs to Gram q / per, whose indices,
+// G and add are at step offsets as in MODE 0 (Yu only with a single Gram).
+template <int MODE, int GROUPS>
+__global__ __launch_bounds__(kRedThreads) void gram_reduce_kernel(
     const double* __restrict__ partials, int nsplit, int nb, const int32_t* __restrict__ idx,
     int m, double scale, double shift, int overlap, double* __restrict__ G,
-    double* __restrict__ Yu, int layout, const float* __restrict__ rs) {
+    double* __restrict__ Yu, int layout, const float* __restrict__ rs,
+    const double* __restrict__ add, int per) {
+  constexpr int kRedElems = kRedThreads / GROUPS;
+  constexpr int kRedGroups = GROUPS;
   __shared__ double red[kRedGroups][kRedElems];
   const int nblk = nb * (nb + 1) / 2;
   const int64_t pstride = (int64_t)nblk * 256 + 16 * nb;
   partials += (int64_t)blockIdx.y * nsplit * pstride;
-  if constexpr (MODE == 0) {
-    idx += (int64_t)blockIdx.y * m;
-    G += (int64_t)blockIdx.y * m * m;
-  }
+  const int gram = MODE == 0 ? (int)blockIdx.y : (int)blockIdx.y / per;
+  const int part = MODE == 0 ? 0 : (int)blockIdx.y % per;
+  idx += (int64_t)gram * m;
+  G += (int64_t)gram * m * m;
+  if (add != nullptr) add += (int64_t)gram * m * m;
   const int el = threadIdx.x % kRedElems;
   const int grp = threadIdx.x / kRedElems;
   const int64_t e = (int64_t)blockIdx.x * kRedElems + el;
   // Each wave sums a contiguous range of splits for 64 consecutive entries;
   // the ranges are then added in group order, so the result is deterministic.
-  const int per = (nsplit + kRedGroups - 1) / kRedGroups;
-  const int sp0 = grp * per;
-  const int sp1 = min(nsplit, sp0 + per);
+  const int spg = (nsplit + kRedGroups - 1) / kRedGroups;   // splits per group
+  const int sp0 = grp * spg;
+  const int sp1 = min(nsplit, sp0 + spg);
   double s = 0.0;
   if (layout == 2 && e < (int64_t)nblk * 256) {   // FP32 block entries
     const float* p = reinterpret_cast<const float*>(partials) + e;
@@ -155,10 +166,10 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
 #pragma unroll
   for (int g = 1; g < kRedGroups; ++g) t += red[g][el];
   if constexpr (MODE == 0)
-    store_entry(e, t, nblk, idx, m, scale, shift, overlap, G, Yu, layout, rs);
+    store_entry(e, t, nblk, idx, m, scale, shift, overlap, G, Yu, layout, rs, add);
   else
-    store_entry_big(e, t, MODE - 1, (int)blockIdx.y, idx, m, scale, shift, overlap, G, Yu,
-                    layout, rs);
+    store_entry_big(e, t, MODE - 1, part, idx, m, scale, shift, overlap, G, Yu, layout, rs,
+                    add);
 }
 
 // Index lists of a Gram of m in (256, 512] rows (one workgroup of 512):
@@ -167,16 +178,23 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void gram_reduce_kernel(
 // ia[256 + 128 y .. 256 + 128 y + 128), x = t % 2, y = t / 2, whose 256-row
 // Gram holds the cross block of rows 256 + 128 y.. and columns 128 x.. .
 // Padding rows are multiplied and never stored.
+// Workgroup k builds the lists of Gram k (indices idx + k m) at ia + 512 k and
+// ib + 256 nc k, nc = big_cross_steps(m) lists.
 __global__ __launch_bounds__(512) void big_index_kernel(const int32_t* __restrict__ idx, int m,
                                                         int32_t* __restrict__ ia,
                                                         int32_t* __restrict__ ib) {
   const int t = threadIdx.x;
+  const int nc = m - 256 > 128 ? 4 : 2;
+  idx += (int64_t)blockIdx.x * m;
+  ia += (int64_t)blockIdx.x * 512;
+  ib += (int64_t)blockIdx.x * 256 * nc;
   ia[t] = idx[t < m ? t : 0];
   const int i0 = idx[0];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int slot = t + 512 * q;             // 0 .. 1023
     const int list = slot >> 8, pos = slot & 255;
+    if (list >= nc) break;
     const int x = list & 1, y = list >> 1;
     int v;
     if (pos < 128) {
@@ -296,22 +314,36 @@ hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64
   }
 }
 
+template <int MODE>
+void launch_reduce(int groups, dim3 grid, hipStream_t st, const double* partials, int nsplit,
+                   int nb, const int32_t* idx, int m, double scale, double shift, int overlap,
+                   double* G, double* Yu, int layout, const float* rs, const double* add,
+                   int per) {
+  if (groups == 1)
+    hipLaunchKernelGGL((gram_reduce_kernel<MODE, 1>), grid, dim3(kRedThreads), 0, st, partials,
+                       nsplit, nb, idx, m, scale, shift, overlap, G, Yu, layout, rs, add, per);
+  else
+    hipLaunchKernelGGL((gram_reduce_kernel<MODE, 16>), grid, dim3(kRedThreads), 0, st, partials,
+                       nsplit, nb, idx, m, scale, shift, overlap, G, Yu, layout, rs, add, per);
+}
+
 hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const int32_t* idx,
                               int m, double scale, double shift, bool overlap, double* G,
                               double* Yu, hipStream_t st, int layout, const float* rs,
-                              int nsteps) {
+                              int nsteps, const double* add) {
   if (nsteps < 1 || nsteps > 65535 || (nsteps > 1 && Yu != nullptr)) return hipErrorInvalidValue;
   const int64_t entries = (int64_t)p.nblk * 256 + 16 * p.nb;
-  const int64_t blocks = (entries + kRedElems - 1) / kRedElems;
-  hipLaunchKernelGGL(gram_reduce_kernel<0>, dim3((unsigned)blocks, (unsigned)nsteps),
-                     dim3(kRedElems * kRedGroups), 0, st, partials, p.nsplit, p.nb, idx, m, scale,
-                     shift, overlap ? 1 : 0, G, Yu, layout, rs);
+  const int groups = red_groups(p.nsplit);
+  const int64_t blocks = (entries + kRedThreads / groups - 1) / (kRedThreads / groups);
+  launch_reduce<0>(groups, dim3((unsigned)blocks, (unsigned)nsteps), st, partials, p.nsplit, p.nb,
+                   idx, m, scale, shift, overlap ? 1 : 0, G, Yu, layout, rs, add, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_big_index(const int32_t* idx, int m, int32_t* ia, int32_t* ib, hipStream_t st) {
-  if (m <= 256 || m > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(big_index_kernel, dim3(1), dim3(512), 0, st, idx, m, ia, ib);
+hipError_t launch_big_index(const int32_t* idx, int m, int32_t* ia, int32_t* ib, hipStream_t st,
+                            int ngram) {
+  if (m <= 256 || m > 512 || ngram < 1 || ngram > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(big_index_kernel, dim3((unsigned)ngram), dim3(512), 0, st, idx, m, ia, ib);
   return hipGetLastError();
 }
 
@@ -319,19 +351,22 @@ int big_cross_steps(int m) { return m - 256 > 128 ? 4 : 2; }
 
 hipError_t launch_gram_reduce_big(const GramPlan& p, const double* partials, const int32_t* idx,
                                   int m, double scale, double shift, bool overlap, double* G,
-                                  double* Yu, hipStream_t st, int layout, const float* rs) {
-  if (p.nb != 16 || m <= 256 || m > 512) return hipErrorInvalidValue;
+                                  double* Yu, hipStream_t st, int layout, const float* rs,
+                                  int ngram, const double* add) {
+  if (p.nb != 16 || m <= 256 || m > 512 || ngram < 1 || (ngram > 1 && Yu != nullptr))
+    return hipErrorInvalidValue;
   const int64_t entries = (int64_t)p.nblk * 256 + 16 * p.nb;
-  const int64_t blocks = (entries + kRedElems - 1) / kRedElems;
+  const int groups = red_groups(p.nsplit);
+  const int64_t blocks = (entries + kRedThreads / groups - 1) / (kRedThreads / groups);
   const size_t set = gram_partial_doubles(p);
-  hipLaunchKernelGGL(gram_reduce_kernel<1>, dim3((unsigned)blocks, 2u),
-                     dim3(kRedElems * kRedGroups), 0, st, partials, p.nsplit, p.nb, idx, m, scale,
-                     shift, overlap ? 1 : 0, G, Yu, layout, rs);
+  const int nc = big_cross_steps(m);
+  launch_reduce<1>(groups, dim3((unsigned)blocks, (unsigned)(2 * ngram)), st, partials, p.nsplit,
+                   p.nb, idx, m, scale, shift, overlap ? 1 : 0, G, Yu, layout, rs, add, 2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_reduce_kernel<2>, dim3((unsigned)blocks, (unsigned)big_cross_steps(m)),
-                     dim3(kRedElems * kRedGroups), 0, st, partials + 2 * set, p.nsplit, p.nb, idx,
-                     m, scale, shift, overlap ? 1 : 0, G, nullptr, layout, rs);
+  launch_reduce<2>(groups, dim3((unsigned)blocks, (unsigned)(nc * ngram)), st,
+                   partials + 2 * ngram * set, p.nsplit, p.nb, idx, m, scale, shift,
+                   overlap ? 1 : 0, G, nullptr, layout, rs, add, nc);
   return hipGetLastError();
 }
 

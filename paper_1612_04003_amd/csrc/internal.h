@@ -135,22 +135,29 @@ hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64
 // rs[idx_p] rs[idx_q] to G and rs[idx_p] to Y u.
 // nsteps > 1: step k reduces partials + k gram_partial_doubles(p) into
 // G + k m^2 (Yu must be NULL).
+// add (may be NULL): nsteps m x m row-major terms (read at row >= col) added
+// to the partial sums before scaling.
 hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, const int32_t* idx,
                               int m, double scale, double shift, bool overlap, double* G,
                               double* Yu, hipStream_t st, int layout = 0,
-                              const float* rs = nullptr, int nsteps = 1);
-// Grams of m in (256, 512] rows from 256-row Grams (plan p of 256 rows, nb 16):
-// launch_big_index builds the index lists ia (512: the rows padded with
-// idx[0]) and ib (4 x 256: half-bands [rows 128 x.. ; rows 256 + 128 y..]);
-// the Gram launches then write 2 + big_cross_steps(m) partial sets of
-// gram_partial_doubles(p) each (ia as 2 steps with Y u, then ib), which
-// launch_gram_reduce_big sums into G (m x m) and Y u.
-hipError_t launch_big_index(const int32_t* idx, int m, int32_t* ia, int32_t* ib, hipStream_t st);
+                              const float* rs = nullptr, int nsteps = 1,
+                              const double* add = nullptr);
+// Grams of m in (256, 512] rows from 256-row Grams (plan p of 256 rows, nb 16),
+// for ngram row lists idx + k m: launch_big_index builds per Gram the index
+// lists ia (512: the rows padded with the first) and ib (nc = big_cross_steps(m)
+// lists of 256: half-bands [rows 128 x.. ; rows 256 + 128 y..]); the Gram
+// launches then write 2 ngram partial sets (ia as 2 ngram steps, with Y u for
+// a single Gram) followed by nc ngram sets (ib), each of
+// gram_partial_doubles(p), which launch_gram_reduce_big sums into G + k m^2
+// (adding add + k m^2 when given) and Y u.
+hipError_t launch_big_index(const int32_t* idx, int m, int32_t* ia, int32_t* ib, hipStream_t st,
+                            int ngram = 1);
 int big_cross_steps(int m);
 hipError_t launch_gram_reduce_big(const GramPlan& p, const double* partials, const int32_t* idx,
                                   int m, double scale, double shift, bool overlap, double* G,
                                   double* Yu, hipStream_t st, int layout = 0,
-                                  const float* rs = nullptr);
+                                  const float* rs = nullptr, int ngram = 1,
+                                  const double* add = nullptr);
 
 // ------------------------------------------------------------------ fused solve
 // One outer step's s block solves through the unrolled recurrence, followed by
@@ -224,6 +231,32 @@ hipError_t launch_csr_gram_steps(const CsrView& A, const int32_t* idx, int m, in
 // launch_csr_gram_steps).
 hipError_t launch_csr_rowdot_rows(const CsrView& A, const int32_t* idx, int64_t m,
                                   const double* v, double* out, hipStream_t st);
+// The Grams of nsteps outer steps computed ahead, split by column popularity
+// (csr_split.hip): the heavy columns (at most 512 of the most popular) through
+// a dense panel on the matrix cores, the light ones through per-step column
+// lists (per-step tables indexed by column: scratch grows with cols).  csr_split_prepare numbers the heavy columns (once per matrix; ws
+// holds csr_split_prepare_ints(A) ints) and reads the statistics the layout
+// needs back to the host.  m <= 512.
+struct CsrSplitInfo {
+  const int* hmap;   // per column: heavy slot (column order) or -1
+  int heavy;         // heavy columns
+  int maxrow;        // longest row
+  int maxlight;      // most light entries in one row
+};
+struct SplitLayout {
+  int hp;            // panel width (heavy rounded up to 16; 0 without heavy columns)
+  int nblk;          // scan workgroups over the columns
+  int64_t cs;        // per-step column-table stride (nblk whole scan workgroups)
+  int64_t lcap;      // light list capacity per step
+  GramPlan plan;     // the panel Gram's plan
+  size_t doubles, ints;   // scratch of one launch
+};
+size_t csr_split_prepare_ints(const CsrView& A);
+hipError_t csr_split_prepare(const CsrView& A, int* ws, CsrSplitInfo* info, hipStream_t st);
+SplitLayout csr_split_layout(const CsrSplitInfo& info, int64_t cols, int m, int nsteps);
+hipError_t launch_csr_gram_split(const CsrView& A, const CsrSplitInfo& info, const int32_t* idx,
+                                 int m, int nsteps, double scale, double shift, bool overlap,
+                                 double* G, double* dws, int* iws, hipStream_t st);
 hipError_t launch_csr_scatter(const CsrView& A, const int32_t* idx, int64_t m, const double* v,
                               double gamma, double* out, hipStream_t st);
 // out[p] = A[p] . v + beta * base[p] for every row.

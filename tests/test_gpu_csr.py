@@ -82,6 +82,23 @@ def test_csr_long_rows_tile_chunks(gpu_lib):
     assert _rel(w.cpu(), wo) <= 1e-10
 
 
+def test_csr_split_gram_power_law_columns(gpu_lib):
+    """The split path on power-law column popularity (the text-classification
+    structure): a few hundred columns in most rows go to the dense panel, the
+    long tail to the column lists; 256 and 512 gathered rows an outer step."""
+    rows, cols = 3000, 20000
+    rowptr, colidx, vals, y, _ = synth.zipf_csr_ridge(rows, cols, 60, 77)
+    S = scipy.sparse.csr_matrix((vals, colidx, rowptr), shape=(rows, cols))
+    XT = gpu_lib.CSR.from_scipy(S, DEV)
+    for s in (16, 32):
+        _say("csr split gram power law", s)
+        H = 6 * s + 5
+        a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), 1e-3, 16, s, H, 21)
+        ao, wo = bcd.dual_bcd(S.T.tocsc(), y, 1e-3, 16, s, H, 21)
+        assert _rel(a.cpu(), ao) <= 1e-10
+        assert _rel(w.cpu(), wo) <= 1e-10
+
+
 @pytest.mark.parametrize("s", [1, 8, 32])
 def test_csr_dual_matches_oracle(gpu_lib, zipf_small, s):
     _say("csr dual", s)
@@ -181,5 +198,22 @@ def test_csr_steps_cross_index_chunks(gpu_lib):
     H = 2 * 4096 + 2 * 50 + 1         # s = 2: 4146 full outer steps, then a ragged one
     a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), 1e-2, 2, 2, H, 13)
     ao, wo = bcd.dual_bcd(S.T.tocsc(), y, 1e-2, 2, 2, H, 13)
+    assert _rel(a.cpu(), ao) <= 1e-10
+    assert _rel(w.cpu(), wo) <= 1e-10
+
+
+@pytest.mark.parametrize("density,s", [(0.01, 32), (0.2, 32), (0.05, 40), (0.05, 64)])
+def test_csr_split_gram_without_and_with_heavy_columns(gpu_lib, density, s):
+    """Grams computed ahead by the split path: a uniform sparse matrix whose
+    columns all stay below the heavy threshold (light lists only), and a denser
+    one where the 512 most frequent columns go to the dense panel."""
+    _say("csr split gram", density, s)
+    S = _random_csr(2000, 4000, density, 31, long_rows=(5,), empty_rows=(9,))
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(2000)
+    XT = gpu_lib.CSR.from_scipy(S, DEV)
+    lam, b, H, seed = 1e-2, 8, 10 * s + 3, 14
+    a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), lam, b, s, H, seed)
+    ao, wo = bcd.dual_bcd(S.T.tocsc(), y, lam, b, s, H, seed)
     assert _rel(a.cpu(), ao) <= 1e-10
     assert _rel(w.cpu(), wo) <= 1e-10
