@@ -339,31 +339,33 @@ __global__ void fill_kernel(double* __restrict__ out, int64_t n, const double* _
 
 // Structure check: rowptr[0] = 0, non-decreasing, rowptr[rows] = nnz; columns
 // strictly increasing inside a row and in [0, cols).  Any violation sets *bad.
-__global__ void csr_check_kernel(const int64_t* __restrict__ rowptr,
-                                 const int32_t* __restrict__ colidx, int64_t rows, int64_t cols,
-                                 int64_t nnz, int* __restrict__ bad) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per row (wave `rows` checks the end), each lane comparing its
+// entries with their predecessors.
+constexpr int kCheckT = 256;
+__global__ __launch_bounds__(kCheckT) void csr_check_kernel(const int64_t* __restrict__ rowptr,
+                                                            const int32_t* __restrict__ colidx,
+                                                            int64_t rows, int64_t cols,
+                                                            int64_t nnz, int* __restrict__ bad) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = ((int64_t)blockIdx.x * kCheckT + threadIdx.x) >> 6;
   if (r > rows) return;
   const int64_t a = rowptr[r];
-  if (r == 0 && a != 0) *bad = 1;
+  int wrong = 0;
   if (r == rows) {
-    if (a != nnz) *bad = 1;
-    return;
-  }
-  const int64_t e = rowptr[r + 1];
-  if (e < a || e > nnz || a < 0) {
-    *bad = 1;
-    return;
-  }
-  int prev = -1;
-  for (int64_t k = a; k < e; ++k) {
-    const int c = colidx[k];
-    if (c <= prev || c >= cols) {
-      *bad = 1;
-      return;
+    wrong = a != nnz;
+  } else {
+    const int64_t e = rowptr[r + 1];
+    if (e < a || e > nnz || a < 0 || (r == 0 && a != 0)) {
+      wrong = 1;
+    } else {
+      for (int64_t k = a + lane; k < e; k += 64) {
+        const int c = colidx[k];
+        const int prev = k > a ? colidx[k - 1] : -1;
+        if (c <= prev || c >= cols) wrong = 1;
+      }
     }
-    prev = c;
   }
+  if (wrong) *bad = 1;
 }
 
 }  // namespace
@@ -428,8 +430,9 @@ hipError_t launch_fill(double* out, int64_t n, const double* base, double beta, 
 }
 
 hipError_t launch_csr_check(const CsrView& A, int* bad, hipStream_t st) {
-  hipLaunchKernelGGL(csr_check_kernel, dim3((unsigned)((A.rows + 1 + 255) / 256)), dim3(256), 0,
-                     st, A.rowptr, A.colidx, A.rows, A.cols, A.nnz, bad);
+  const int64_t threads = (A.rows + 1) * 64;
+  hipLaunchKernelGGL(csr_check_kernel, dim3((unsigned)((threads + kCheckT - 1) / kCheckT)),
+                     dim3(kCheckT), 0, st, A.rowptr, A.colidx, A.rows, A.cols, A.nnz, bad);
   return hipGetLastError();
 }
 

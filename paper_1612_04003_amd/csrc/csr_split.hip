@@ -36,9 +36,9 @@ namespace {
 
 constexpr int kT = 256;               // threads of the helper kernels
 constexpr int kHeavyMax = 512;        // panel columns at most
-constexpr int kHist = 65536;          // column-count histogram bins (counts capped)
+constexpr int kHist = 8192;           // column-count histogram bins (counts capped)
 constexpr int kScanChunk = 1024;      // columns per workgroup of the slot numbering
-constexpr int64_t kSampleRows = 4096; // rows whose columns estimate the popularity
+constexpr int64_t kSampleRows = 2048; // rows whose columns estimate the popularity
 
 __global__ __launch_bounds__(kT) void zero_ints_kernel(int* __restrict__ p, int64_t n, int v) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
@@ -76,48 +76,75 @@ __global__ __launch_bounds__(kT) void count_hist_kernel(const int* __restrict__ 
   }
 }
 
-// One workgroup of 1024 threads: the smallest count T >= tmin such that at
-// most kHeavyMax columns have a count >= T (kHist means none).  stats[0] = T.
-__global__ __launch_bounds__(1024) void heavy_threshold_kernel(const int* __restrict__ hist,
-                                                               int tmin, int* __restrict__ stats) {
-  __shared__ int part[1024];
-  constexpr int per = kHist / 1024;
-  const int t = threadIdx.x;
-  int s = 0;   // columns with a count in this thread's bins
-  for (int v = t * per; v < (t + 1) * per; ++v) s += hist[v];
-  part[t] = s;
+// One workgroup of 1024 threads, 8 bins each: the smallest count T >= tmin
+// such that at most kHeavyMax columns have a count >= T (stats[0] = T), and
+// the number of those columns (stats[3]).  The thread whose bins hold the
+// crossing finds it from its suffix sum (the columns in higher bins).
+constexpr int kThrT = 1024;
+constexpr int kThrPer = kHist / kThrT;
+__global__ __launch_bounds__(kThrT) void heavy_threshold_kernel(const int* __restrict__ hist,
+                                                                int tmin, int* __restrict__ stats) {
+  __shared__ int sh[kThrT / 64];
+  __shared__ int res[2];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int h[kThrPer];
+  int mine = 0;
+#pragma unroll
+  for (int q = 0; q < kThrPer; ++q) {
+    h[q] = hist[t * kThrPer + q];
+    mine += h[q];
+  }
+  // above = sum of `mine` over the threads t' > t (inclusive scan from the top)
+  int x = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_down(x, o, 64);
+    if (lane + o < 64) x += v;
+  }
+  if (lane == 0) sh[wave] = x;
+  if (t == 0) res[0] = 0;   // no crossing: every qualifying column is heavy
+  __syncthreads();
+  int above = x - mine;
+  for (int w = wave + 1; w < kThrT / 64; ++w) above += sh[w];
+  if (above <= kHeavyMax && above + mine > kHeavyMax) {
+    int acc = above, T = 0;
+    for (int q = kThrPer - 1; q >= 0; --q) {
+      if (acc + h[q] > kHeavyMax) {
+        T = t * kThrPer + q + 1;
+        break;
+      }
+      acc += h[q];
+    }
+    res[0] = T;   // exactly one thread holds the crossing
+  }
+  __syncthreads();
+  const int T = max(res[0], tmin);
+  // heavy columns: those in bins >= T
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < kThrPer; ++q) c += t * kThrPer + q >= T ? h[q] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  __syncthreads();
+  if (lane == 0) sh[wave] = c;
   __syncthreads();
   if (t == 0) {
-    // suffix sums from the highest bins down; the crossing bin is then
-    // searched inside its thread range
-    int acc = 0, T = kHist;
-    for (int q = 1023; q >= 0 && T == kHist; --q) {
-      if (acc + part[q] <= kHeavyMax) {
-        acc += part[q];
-        continue;
-      }
-      for (int v = (q + 1) * per - 1; v >= q * per; --v) {
-        if (acc + hist[v] > kHeavyMax) {
-          T = v + 1;
-          break;
-        }
-        acc += hist[v];
-      }
-    }
-    if (T == kHist) T = 0;       // every column fits: all counts qualify
-    stats[0] = max(T, tmin);
+    int tot = 0;
+    for (int w = 0; w < kThrT / 64; ++w) tot += sh[w];
+    stats[0] = T;
+    stats[3] = tot;
   }
 }
 
 // Heavy columns of workgroup chunk blockIdx.x: block counts (pass 0), then slot
-// numbers in column order (pass 1, with the exclusive scan of the block counts).
+// numbers in column order (pass 1, with the sum of the earlier block counts).
 __global__ __launch_bounds__(kScanChunk) void heavy_slots_kernel(const int* __restrict__ cnt,
                                                                  int64_t cols,
                                                                  const int* __restrict__ stats,
                                                                  int* __restrict__ blk,
                                                                  int* __restrict__ hmap, int pass) {
   __shared__ int wsum[kScanChunk / 64];
-  __shared__ int base;
+  __shared__ int bsum[kScanChunk / 64];
   const int T = stats[0];
   const int64_t c = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
   const bool heavy = c < cols && cnt[c] >= T;
@@ -133,33 +160,28 @@ __global__ __launch_bounds__(kScanChunk) void heavy_slots_kernel(const int* __re
     }
     return;
   }
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int b = 0; b < (int)blockIdx.x; ++b) s += blk[b];   // at most kHeavyMax in total
-    base = s;
-  }
+  // the earlier blocks' counts, summed by the workgroup
+  int e = 0;
+  for (int q = threadIdx.x; q < (int)blockIdx.x; q += kScanChunk) e += blk[q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+  if (lane == 0) bsum[wave] = e;
   __syncthreads();
-  int off = base;
+  int off = 0;
+  for (int w = 0; w < kScanChunk / 64; ++w) off += bsum[w];
   for (int w = 0; w < wave; ++w) off += wsum[w];
   const int below = __popcll(mask & ((1ull << lane) - 1ull));
   if (c < cols) hmap[c] = heavy ? off + below : -1;
 }
 
-// stats[1] = longest row (the bound of a row's light entries too), stats[3]
-// = heavy columns (slots).
+// stats[1] = longest row (the bound of a row's light entries too).
 __global__ __launch_bounds__(kT) void split_stats_kernel(const int64_t* __restrict__ rowptr,
-                                                         int64_t rows, const int* __restrict__ blk,
-                                                         int nblk, int* __restrict__ stats) {
+                                                         int64_t rows, int* __restrict__ stats) {
   int mx = 0;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kT)
     mx = max(mx, (int)(rowptr[i + 1] - rowptr[i]));
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(&stats[1], mx);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    int s = 0;
-    for (int q = 0; q < nblk; ++q) s += blk[q];
-    stats[3] = s;
-  }
 }
 
 // ----------------------------------------------------------------- per launch
@@ -314,17 +336,25 @@ __global__ __launch_bounds__(kT) void split_fill_kernel(
 
 // One wave per (step k, gathered row p): row p of the light part,
 // Gl[k][p][q] = sum over the light columns c of row p, in the row's column
-// order, of v_pc v_qc for q <= p.  The row's entries are taken 64 at a time:
-// their slots, values and list extents are loaded by the lanes together, the
-// lists are staged into LDS (each lane copies its entry's list), and the
-// entries are then applied one after the other from LDS.  A column's list
-// holds a gathered row at most once, so the lanes of one entry add to
-// distinct q and the order of every sum is the row's column order, whatever
-// order the lists were filled in.  The row is accumulated in LDS and written
-// whole (zeros where no light column is shared).
+// order, of v_pc v_qc for q <= p.  The row's entries are taken 64 at a time
+// (the next batch's columns and values are loaded while one is applied):
+// their list extents are loaded by the lanes together, runs of lists that
+// fit the stage are copied into LDS by the whole wave (one staged element a
+// lane and load, eight loads in flight), and the entries are then applied one
+// after the other from LDS.  A column's list holds a gathered row at most
+// once, so the lanes of one entry add to distinct q and the order of every
+// sum is the row's column order, whatever order the lists were filled in.
+// The row is accumulated in LDS and written whole (zeros where no light
+// column is shared).
 constexpr int kSplitMaxRows = 512;
 constexpr int kStage = 512;                 // staged list elements per wave
+constexpr int kCopyUnroll = kStage / 64;    // loads in flight a lane while staging
 constexpr int kLightWaves = kT / 64;
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __global__ __launch_bounds__(kT) void split_light_kernel(
     const int64_t* __restrict__ rowptr, const double* __restrict__ vals,
     const int32_t* __restrict__ idx, int m, int nsteps, const int* __restrict__ cnt,
@@ -341,6 +371,7 @@ __global__ __launch_bounds__(kT) void split_light_kernel(
   double* bv = sv[wave];
   int* bq = sq[wave];
   for (int q = lane; q < m; q += 64) ar[q] = 0.0;
+  wave_sync_lds();
   const int k = (int)(wv / m), p = (int)(wv % m);
   cnt += (int64_t)k * cs;
   off += (int64_t)k * cs;
@@ -352,15 +383,18 @@ __global__ __launch_bounds__(kT) void split_light_kernel(
   // light columns no other gathered row shares give only p's own product:
   // each lane sums those of its entries (in row order), added at the end
   double self = 0.0;
+  int c = a + lane < b ? erow[lane] : -1;
+  double vp = c >= 0 ? vals[a + lane] : 0.0;
   for (int64_t e0 = a; e0 < b; e0 += 64) {
-    // this batch's entries: column, value, list extent (lanes together)
-    const int64_t j = e0 + lane;
-    const int c = j < b ? erow[j - a] : -1;
-    const double vp = c >= 0 ? vals[j] : 0.0;
+    // this batch's list extents; the next batch's columns and values
     const int nc = c >= 0 ? cnt[c] : 0;
+    const int oc = c >= 0 ? off[c] : 0;
+    const int64_t jn = e0 + 64 + lane;
+    const int cn = jn < b ? erow[jn - a] : -1;
+    const double vn = cn >= 0 ? vals[jn] : 0.0;
     if (nc == 1) self = fma(vp, vp, self);
     const int n = nc >= 2 ? nc : 0;
-    const int s0 = n > 0 ? off[c] - n : 0;
+    const int s0 = oc - n;
     // staging positions: exclusive prefix of the list lengths
     int pre = n;
 #pragma unroll
@@ -386,17 +420,39 @@ __global__ __launch_bounds__(kT) void split_light_kernel(
         }
       }
       const bool staged = run != 0ull;
-      if (!staged) run = 1ull << first;
-      if (staged && ((run >> lane) & 1ull)) {
-        for (int t = 0; t < n; ++t) {
-          bq[pre - base + t] = lq[s0 + t];
-          bv[pre - base + t] = lv[s0 + t];
+      if (staged) {
+        // each entry writes its elements' global positions into the stage,
+        // then every lane copies staged elements lane, lane + 64, ...
+        const int last = 63 - __clzll((long long)run);
+        const int total = __shfl(pre, last, 64) + __shfl(n, last, 64) - base;
+        if ((run >> lane) & 1ull)
+          for (int t = 0; t < n; ++t) bq[pre - base + t] = s0 + t;
+        wave_sync_lds();
+        int g[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+          const int jj = u * 64 + lane;
+          g[u] = jj < total ? bq[jj] : -1;
         }
+        int qv[kCopyUnroll];
+        double vv[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+          qv[u] = g[u] >= 0 ? lq[g[u]] : 0;
+          vv[u] = g[u] >= 0 ? lv[g[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+          const int jj = u * 64 + lane;
+          if (jj < total) {
+            bq[jj] = qv[u];
+            bv[jj] = vv[u];
+          }
+        }
+        wave_sync_lds();
+      } else {
+        run = 1ull << first;
       }
-      // the wave's LDS writes stay ahead of the other lanes' reads
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       todo &= ~run;
       while (run != 0ull) {
         const int e = __ffsll((long long)run) - 1;
@@ -409,16 +465,17 @@ __global__ __launch_bounds__(kT) void split_light_kernel(
           const int q = t < ne ? (staged ? bq[pe + t] : lq[se + t]) : INT_MAX;
           if (q <= p) ar[q] += ve * (staged ? bv[pe + t] : lv[se + t]);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_lds();
       }
     }
+    c = cn;
+    vp = vn;
   }
   // the lanes' own products in a fixed tree order
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) self += __shfl_xor(self, o, 64);
   if (lane == 0) ar[p] += self;
+  wave_sync_lds();
   double* grow = Gl + wv * (int64_t)m;
   for (int q = lane; q <= p; q += 64) grow[q] = ar[q];
 }
@@ -468,8 +525,9 @@ hipError_t csr_split_prepare(const CsrView& A, int* ws, CsrSplitInfo* info, hipS
   hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_for(kHist)), dim3(kT), 0, st, hist,
                      (int64_t)kHist, 0);
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(kT), 0, st, stats, (int64_t)8, 0);
-  // popularity from every stride-th row (about kSampleRows rows); a heavy
-  // column appears in at least 1/64 of the sampled rows (and twice)
+  // popularity from every stride-th row (kSampleRows to 2 kSampleRows - 1
+  // rows); a heavy column appears in at least 1/64 of the sampled rows (and
+  // twice)
   const int64_t stride = std::max<int64_t>(1, A.rows / kSampleRows);
   const int64_t nsample = (A.rows + stride - 1) / stride;
   const int tmin = (int)std::max<int64_t>(2, nsample / 64);
@@ -478,13 +536,13 @@ hipError_t csr_split_prepare(const CsrView& A, int* ws, CsrSplitInfo* info, hipS
                        A.colidx, A.rows, stride, cnt);
   hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(A.cols)), dim3(kT), 0, st, cnt,
                      (int64_t)A.cols, tmin, hist);
-  hipLaunchKernelGGL(heavy_threshold_kernel, dim3(1), dim3(1024), 0, st, hist, tmin, stats);
+  hipLaunchKernelGGL(heavy_threshold_kernel, dim3(1), dim3(kThrT), 0, st, hist, tmin, stats);
   hipLaunchKernelGGL(heavy_slots_kernel, dim3(nblk), dim3(kScanChunk), 0, st, cnt,
                      (int64_t)A.cols, stats, blk, hmap, 0);
   hipLaunchKernelGGL(heavy_slots_kernel, dim3(nblk), dim3(kScanChunk), 0, st, cnt,
                      (int64_t)A.cols, stats, blk, hmap, 1);
   hipLaunchKernelGGL(split_stats_kernel, dim3(grid_for(A.rows)), dim3(kT), 0, st, A.rowptr,
-                     A.rows, blk, nblk, stats);
+                     A.rows, stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int h[4] = {0, 0, 0, 0};
