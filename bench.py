@@ -296,7 +296,50 @@ def extra_records(args, cabcd, torch, synth, X, y):
             "gram_gbs": round(np.mean(by) / (g * 1e-3) / 1e9, 2)}
         log(f"sparse dual s={s}: {rec[f'sparse_dual_s{s}']}")
     rec.update(resid_tol_records(cabcd, torch, X, y, lam, args.b, args.s, A, yd))
+    rec["graph_small_steps"] = graph_records(cabcd, torch, X, y, lam)
     return rec
+
+
+def graph_records(cabcd, torch, X, y, lam, steps=64):
+    """Small outer steps with and without HIP graph capture: one call of
+    `steps` outer steps timed as issued (launches from the host), against the
+    same call captured once into a graph (caller workspace, no synchronisation
+    inside the call) and replayed.  Each replay repeats the captured
+    iterations from the state it finds; both rates are per outer step on the
+    headline matrix."""
+    out = {}
+    d, n = X.shape
+    for (b, s) in ((8, 1), (1, 1), (1, 8), (8, 4)):
+        ws = torch.empty(cabcd.workspace_bytes(X, b, s), dtype=torch.uint8, device="cuda")
+        w = torch.zeros(d, dtype=torch.float64, device="cuda")
+        r = torch.empty(n, dtype=torch.float64, device="cuda")
+        H = steps * s
+        kw = dict(w=w, r=r, workspace=ws)
+        cabcd.primal_bcd(X, y, lam, b, s, H, 77, **kw)
+        flags = cabcd.FLAG_STATE_VALID | cabcd.FLAG_ASYNC
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            cabcd.primal_bcd(X, y, lam, b, s, H, 77, h0=H, flags=flags, **kw)
+        torch.cuda.synchronize()
+        direct = (time.perf_counter() - t0) / (3 * steps)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            cabcd.primal_bcd(X, y, lam, b, s, H, 77, h0=H, flags=flags, **kw)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        graph = (time.perf_counter() - t0) / (3 * steps)
+        out[f"b{b}s{s}"] = {"direct_us_per_step": round(direct * 1e6, 2),
+                            "graph_us_per_step": round(graph * 1e6, 2),
+                            "direct_us_per_iteration": round(direct * 1e6 / s, 2),
+                            "graph_us_per_iteration": round(graph * 1e6 / s, 2)}
+        log(f"graph b={b} s={s}: {out[f'b{b}s{s}']}")
+        del g, ws
+    return out
 
 
 def resid_tol_records(cabcd, torch, X, y, lam, b, s, A, yd, every=8):

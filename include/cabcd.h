@@ -320,7 +320,8 @@ cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha,
  * monitor_every rounds a second persistent launch evaluates the objective f(w)
  * (recomputing r = X^T w - y exactly, or from the maintained residual, see
  * cheap_monitors) and retires problems that reached f_target.  The launches
- * are captured once into hipGraphs and replayed.
+ * of one monitor period are captured once into hipGraphs and replayed (when
+ * monitor_every is at most 64; longer periods launch directly).
  *
  * Per problem, the iterates are those of cabcd_primal_bcd with the same X, y,
  * lambda, b, s, seed and H (the same blocks), up to rounding order.

@@ -561,6 +561,7 @@ constexpr double kCuBw = 5.0e12 / 256;
 constexpr double kWgBw = 60e9;
 constexpr double kSolveBlock = 1.5e-6;
 constexpr double kRoundFixed = 10e-6;
+constexpr int kGraphMaxRounds = 64;   // rounds of one captured monitor period, at most
 
 int elem_bytes(int dtype) { return dtype == CABCD_F64 ? 8 : dtype == CABCD_BF16 ? 2 : 1; }
 
@@ -964,8 +965,10 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   if (rc != CABCD_OK) return rc;
 
   // Capture one monitor period (or one round without monitoring): one graph
-  // ending in a maintained-residual monitor, one ending in an exact one.
-  if ((B->flags & CABCD_BATCH_NO_GRAPH) == 0) {
+  // ending in a maintained-residual monitor, one ending in an exact one.  A
+  // period longer than kGraphMaxRounds rounds runs as direct launches (the
+  // graph would hold one node per round).
+  if ((B->flags & CABCD_BATCH_NO_GRAPH) == 0 && B->monitor_every <= kGraphMaxRounds) {
     BATCH_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     const int R = B->monitor_every > 0 ? B->monitor_every : 1;
     for (int g = 0; g < (B->monitor_every > 0 ? 2 : 1); ++g) {

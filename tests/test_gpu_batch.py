@@ -96,6 +96,22 @@ def test_batch_graph_direct_and_split_runs_are_identical(gpu_lib, cheap):
             assert np.array_equal(r0, r1)
 
 
+def test_batch_long_monitor_period_runs_without_graph(gpu_lib):
+    """A monitor period longer than the 64 rounds a graph may hold launches
+    directly: same iterates as a plan with graphs switched off."""
+    _say("batch, monitor_every = 100")
+    cases = CASES[:4]
+    runs = []
+    for graph in (True, False):
+        probs = _problems(cases)
+        with gpu_lib.Batch(probs, monitor_every=100, graph=graph) as B:
+            B.run(150)
+        torch.cuda.synchronize()
+        runs.append([(q["w"].cpu().numpy(), q["r"].cpu().numpy()) for q in probs])
+    for (w0, r0), (w1, r1) in zip(*runs):
+        assert np.array_equal(w0, w1) and np.array_equal(r0, r1)
+
+
 def test_batch_without_monitoring(gpu_lib):
     _say("batch, monitor_every = 0")
     cases = CASES[:4]

@@ -328,3 +328,41 @@ def test_mixed_primal_big_sb_reaches_1e6(gpu_lib, dtype):
     rel_obj = (bcd.primal_objective(Xh, yn, lam, wn) - fstar) / fstar
     _say(f"  rel obj error {rel_obj:.2e}")
     assert rel_obj <= 1e-6
+
+
+@pytest.mark.parametrize("b,s,n", [(8, 1, 300000), (1, 8, 300000), (4, 4, 300000),
+                                   (8, 4, 20000)])
+def test_graph_captured_call_equals_direct_call(gpu_lib, b, s, n):
+    """A one-problem call captured into a HIP graph (caller workspace, no
+    synchronisation inside the call) and replayed gives bitwise the iterates of
+    the same call issued directly, on every replay from the same state.  n =
+    300000: one Gram per step (gathered rows above 8 MiB); n = 20000: Grams of
+    future steps computed ahead."""
+    _say("graph capture", b, s, n)
+    d = 64
+    X, y, _ = synth.gaussian_ridge(d, n, 90, device=DEV)
+    lam, H, seed = 1e-3, 6 * s, 12
+    ws = torch.empty(gpu_lib.workspace_bytes(X, b, s), dtype=torch.uint8, device=DEV)
+    w = torch.zeros(d, dtype=torch.float64, device=DEV)
+    r = torch.empty(n, dtype=torch.float64, device=DEV)
+    gpu_lib.primal_bcd(X, y, lam, b, s, H, seed, w=w, r=r, workspace=ws)
+    w0, r0 = w.clone(), r.clone()
+    flags = gpu_lib.FLAG_STATE_VALID | gpu_lib.FLAG_ASYNC
+    gpu_lib.primal_bcd(X, y, lam, b, s, H, seed, w=w, r=r, h0=H, flags=flags, workspace=ws)
+    torch.cuda.synchronize()
+    w1, r1 = w.clone(), r.clone()
+    wo, ro = bcd.primal_bcd(X.cpu().numpy(), y.cpu().numpy(), lam, b, s, 2 * H, seed)
+    assert _rel(w1.cpu().numpy(), wo) <= 1e-10
+    w.copy_(w0)
+    r.copy_(r0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpu_lib.primal_bcd(X, y, lam, b, s, H, seed, w=w, r=r, h0=H, flags=flags, workspace=ws)
+    for rep in range(3):
+        w.copy_(w0)
+        r.copy_(r0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(w, w1) and torch.equal(r, r1), f"replay {rep}"
