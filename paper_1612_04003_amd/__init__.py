@@ -230,20 +230,25 @@ class Quantized:
 
 
 def quantize(A, dtype):
-    """Store the FP64 matrix A (rows x cols) as BF16 or FP8-E4M3 codes."""
+    """Store the FP64 matrix A (rows x cols) as BF16 or FP8-E4M3 codes.  The
+    codes' rows start on 16-byte boundaries (leading dimension padded with
+    zero codes), which is what the 16-byte loads and the LDS-DMA paths of the
+    kernels need; `codes` is the rows x cols view."""
     _need(A, torch.float64, "A")
     rows, cols = A.shape
     if dtype == BF16:
-        codes = torch.empty((rows, cols), dtype=torch.int16, device=A.device)
+        ldq = -(-cols // 8) * 8
+        buf = torch.zeros((rows, ldq), dtype=torch.int16, device=A.device)
         scales = None
     elif dtype == FP8_E4M3:
-        codes = torch.empty((rows, cols), dtype=torch.uint8, device=A.device)
+        ldq = -(-cols // 16) * 16
+        buf = torch.zeros((rows, ldq), dtype=torch.uint8, device=A.device)
         scales = torch.empty(rows, dtype=torch.float32, device=A.device)
     else:
         raise ValueError("dtype must be BF16 or FP8_E4M3")
-    _check(load().cabcd_quantize(_ptr(A), rows, cols, A.stride(0), dtype, _ptr(codes), cols,
+    _check(load().cabcd_quantize(_ptr(A), rows, cols, A.stride(0), dtype, _ptr(buf), ldq,
                                  _ptr(scales), _stream()))
-    return Quantized(codes, scales, dtype)
+    return Quantized(buf[:, :cols], scales, dtype)
 
 
 def describe(A):

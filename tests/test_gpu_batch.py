@@ -191,6 +191,8 @@ def test_batch_lowp_reaches_1e6_on_dequantised(gpu_lib, dtype):
     for p in range(P):
         X, y, _ = synth.gaussian_ridge(ds[p], ns[p], 1200 + p)
         Q = gpu_lib.quantize(X.to(DEV), code)
+        if p % 2:   # every other problem with rows starting at any byte
+            Q = gpu_lib.Quantized(Q.codes.contiguous(), Q.scales, Q.dtype)
         Xh = Q.dequantize().cpu().numpy()
         yc = y.numpy()
         fst = bcd.primal_objective(Xh, yc, lams[p], bcd.ridge_closed_form(Xh, yc, lams[p]))

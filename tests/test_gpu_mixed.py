@@ -26,6 +26,16 @@ def _say(*a):
     print(*a, flush=True)
 
 
+def _layouts(gpu_lib, Q):
+    """The binding's storage (rows padded to 16-byte boundaries) and, when the
+    padding is not empty, a contiguous copy whose rows start at any byte (the
+    kernels' unaligned paths)."""
+    out = [("padded", Q)]
+    if Q.codes.stride(0) != Q.codes.shape[1]:
+        out.append(("contiguous", gpu_lib.Quantized(Q.codes.contiguous(), Q.scales, Q.dtype)))
+    return out
+
+
 def _matrix(rows, cols, seed):
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((rows, cols)) * np.exp(2.0 * rng.standard_normal(rows))[:, None]
@@ -69,8 +79,6 @@ def test_lowp_gram_against_fp64_gram_of_dequantised(gpu_lib, dtype, m, cols):
     idx = rng.integers(0, rows, size=m).astype(np.int32)
     u = rng.standard_normal(cols)
     scale, shift = 1.0 / cols, 0.5
-    G, Yu = gpu_lib.gram(Q, torch.tensor(idx, device=DEV), scale, shift,
-                         torch.tensor(u, device=DEV))
     Go, Yo = bcd.gram(Xh, idx, scale, shift, u)
     Y = np.abs(Xh[idx])
     # BF16: Higham's bound for a K-term FP32 dot product.  FP8: the E4M3 matrix
@@ -79,11 +87,14 @@ def test_lowp_gram_against_fp64_gram_of_dequantised(gpu_lib, dtype, m, cols):
     # its bound carries an extra 2^-12 relative term.
     rel_bound = cols * 2.0 ** -24 + (0.0 if dtype == "bf16" else 2.0 ** -12)
     bound = rel_bound * scale * (Y @ Y.T) + 1e-300
-    err = np.abs(G.cpu().numpy() - Go)
-    assert np.all(err <= bound)
-    rel = (err / np.maximum(scale * (Y @ Y.T), 1e-300)).max()
-    _say(f"  max |dG| / (scale |Y||Y|^T) = {rel:.2e}")
-    assert np.all(np.abs(Yu.cpu().numpy() - Yo) <= 1e-12 * (Y @ np.abs(u)) + 1e-300)
+    for name, Qv in _layouts(gpu_lib, Q):
+        G, Yu = gpu_lib.gram(Qv, torch.tensor(idx, device=DEV), scale, shift,
+                             torch.tensor(u, device=DEV))
+        err = np.abs(G.cpu().numpy() - Go)
+        assert np.all(err <= bound), name
+        rel = (err / np.maximum(scale * (Y @ Y.T), 1e-300)).max()
+        _say(f"  {name}: max |dG| / (scale |Y||Y|^T) = {rel:.2e}")
+        assert np.all(np.abs(Yu.cpu().numpy() - Yo) <= 1e-12 * (Y @ np.abs(u)) + 1e-300), name
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
@@ -100,11 +111,12 @@ def test_lowp_companion_pass_entrywise(gpu_lib, dtype, d, n):
     code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
     Q = gpu_lib.quantize(torch.tensor(X, device=DEV), code)
     Xh = Q.dequantize().cpu().numpy()
-    _, r = gpu_lib.primal_bcd(Q, torch.tensor(y, device=DEV), 1e-3, 1, 1, 0, 1,
-                              w=torch.tensor(w, device=DEV))
     ro = Xh.T @ w - y
     bound = np.abs(Xh).T @ np.abs(w) + np.abs(y)
-    assert np.all(np.abs(r.cpu().numpy() - ro) <= 1e-12 * bound)
+    for name, Qv in _layouts(gpu_lib, Q):
+        _, r = gpu_lib.primal_bcd(Qv, torch.tensor(y, device=DEV), 1e-3, 1, 1, 0, 1,
+                                  w=torch.tensor(w, device=DEV))
+        assert np.all(np.abs(r.cpu().numpy() - ro) <= 1e-12 * bound), name
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
@@ -147,6 +159,8 @@ def test_mixed_dual_reaches_1e6_on_dequantised_problem(gpu_lib, dtype, d):
     X, y, _ = synth.gaussian_ridge(d, n, 17)
     code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
     Q = gpu_lib.quantize(X.t().contiguous().to(DEV), code)
+    if d % 16:   # rows of the stored X^T starting at any byte
+        Q = gpu_lib.Quantized(Q.codes.contiguous(), Q.scales, Q.dtype)
     Xh = Q.dequantize().cpu().numpy().T            # d x n
     yn = y.numpy()
     ws = bcd.ridge_closed_form(Xh, yn, lam)
