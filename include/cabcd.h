@@ -321,7 +321,14 @@ cabcd_status cabcd_dual_to_primal(const cabcd_matrix* XT, const double* alpha,
  * (recomputing r = X^T w - y exactly, or from the maintained residual, see
  * cheap_monitors) and retires problems that reached f_target.  The launches
  * of one monitor period are captured once into hipGraphs and replayed (when
- * monitor_every is at most 64; longer periods launch directly).
+ * monitor_every is at most 64; longer periods launch directly).  Every 32 or
+ * so rounds (a multiple of monitor_every) cabcd_batch_run synchronises its
+ * stream, and once the active problems have halved since the slabs were last
+ * cut, it cuts the active problems' slabs again for them alone (same b and s,
+ * more and shorter slabs) and captures the graphs again, so that the GPU stays
+ * filled as problems retire; this changes only the rounding order of the Gram
+ * sums, and happens at the same rounds however the rounds are split between
+ * calls.
  *
  * Per problem, the iterates are those of cabcd_primal_bcd with the same X, y,
  * lambda, b, s, seed and H (the same blocks), up to rounding order.

@@ -234,7 +234,10 @@ def quantize(A, dtype):
     codes' rows start on 16-byte boundaries (leading dimension padded with
     zero codes), which is what the 16-byte loads and the LDS-DMA paths of the
     kernels need; `codes` is the rows x cols view."""
-    _need(A, torch.float64, "A")
+    if not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.float64:
+        raise TypeError("A must be a float64 CUDA (HIP) tensor")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be 2-D with unit column stride")
     rows, cols = A.shape
     if dtype == BF16:
         ldq = -(-cols // 8) * 8

@@ -562,6 +562,7 @@ constexpr double kWgBw = 60e9;
 constexpr double kSolveBlock = 1.5e-6;
 constexpr double kRoundFixed = 10e-6;
 constexpr int kGraphMaxRounds = 64;   // rounds of one captured monitor period, at most
+constexpr int kReplanRounds = 32;     // rounds between checks for re-slicing, about
 
 int elem_bytes(int dtype) { return dtype == CABCD_F64 ? 8 : dtype == CABCD_BF16 ? 2 : 1; }
 
@@ -597,6 +598,19 @@ struct Pick {
   double crit;
 };
 
+// Slabs of a problem with `wp` CU-seconds of slab work per round for a target
+// of `target` per slab: at most kBMaxSlabs, at least one tile each, widths a
+// multiple of the tile.
+void slice(double wp, double target, int64_t n, int kt, int64_t& chunk_out, int& nslab_out) {
+  int64_t nslab = (int64_t)std::ceil(wp / target);
+  nslab = std::max<int64_t>(1, std::min<int64_t>(nslab, kBMaxSlabs));
+  nslab = std::min<int64_t>(nslab, (n + kt - 1) / kt);
+  int64_t chunk = (n + nslab - 1) / nslab;
+  chunk = (chunk + kt - 1) / kt * kt;
+  chunk_out = chunk;
+  nslab_out = (int)((n + chunk - 1) / chunk);
+}
+
 // (b, s) of every problem for a target of `rp` rounds per pass over the
 // coordinates, slabs sized so a round has about four items per CU, and the
 // predicted time of one pass (rounds per pass x round time).
@@ -624,17 +638,10 @@ double plan_candidate(const std::vector<cabcd_problem>& pb, double rp, int cus,
   for (size_t p = 0; p < P; ++p) {
     const int sb = out[p].b * out[p].s;
     const int nb = nb_of(sb);
-    const int kt = tile_cols(nb, pb[p].X.dtype);
     const int64_t n = pb[p].X.cols;
     const double wp = slab_work(sb, n, pb[p].X.dtype);
-    int64_t nslab = (int64_t)std::ceil(wp / target);
-    nslab = std::max<int64_t>(1, std::min<int64_t>(nslab, kBMaxSlabs));
-    nslab = std::min<int64_t>(nslab, (n + kt - 1) / kt);
-    int64_t chunk = (n + nslab - 1) / nslab;
-    chunk = (chunk + kt - 1) / kt * kt;
-    nslab = (n + chunk - 1) / chunk;
-    out[p].chunk = chunk;
-    out[p].nslab = (int)nslab;
+    slice(wp, target, n, tile_cols(nb, pb[p].X.dtype), out[p].chunk, out[p].nslab);
+    const int64_t nslab = out[p].nslab;
     out[p].crit = wp / nslab + nslab * pstride_of(nb) * 8.0 / kWgBw + out[p].s * kSolveBlock;
     crit = std::max(crit, out[p].crit);
     passes = std::max(passes, (double)pb[p].X.rows / sb);
@@ -684,6 +691,13 @@ struct cabcd_batch_plan {
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   int graph_rounds = 0;
   int dtype = CABCD_F64;   // storage type shared by every problem of the plan
+  // re-slicing of the slabs as problems retire
+  int cus = 1, occ_step = 1, occ_aux = 1;
+  int items_cap = 0;       // capacity of dI
+  double* pool = nullptr;  // partials and objective partials of re-sliced plans
+  size_t pool_doubles = 0;
+  int plan_active = 0;     // active problems when the slabs were last sliced
+  int64_t replan_period = 0;
 };
 
 namespace cabcd {
@@ -824,6 +838,8 @@ void release(cabcd_batch_plan* B) {
   delete B;
 }
 
+cabcd_status capture(cabcd_batch_plan* B);
+
 cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* opts,
                     hipStream_t st, cabcd_batch_plan* B) {
   BATCH_HIP(hipGetDevice(&B->device));
@@ -858,15 +874,20 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   for (int p : order)
     for (int q = 0; q < best[p].nslab; ++q) items.push_back(BItem{p, q});
   B->nitems = (int)items.size();
+  B->cus = cus;
+  B->items_cap = std::max(B->nitems, 4 * cus + 2 * P);
 
-  // Workspace and device copies.
+  // Workspace and device copies.  The pool holds the partials of re-sliced
+  // plans: as much as the first plan's, plus the largest slab set of one
+  // problem.
   size_t bytes = 0;
   auto add = [&](size_t n) { bytes = ((bytes + 255) & ~(size_t)255) + n; };
   add(sizeof(BProb) * P);
   add(sizeof(BState) * P);
-  add(sizeof(BItem) * items.size());
+  add(sizeof(BItem) * B->items_cap);
   add(sizeof(BQueue));
   int area = 0;
+  size_t pool = 0;
   for (int p = 0; p < P; ++p) {
     const int sb = best[p].b * best[p].s;
     const int nb = nb_of(sb);
@@ -876,7 +897,11 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
     add(sizeof(double) * sb);
     add(sizeof(double) * best[p].nslab);
     area = std::max<int>(area, (int)((solve_lds_bytes(sb, best[p].b) + 7) / 8));
+    pool += (size_t)best[p].nslab * (pstride_of(nb) + 1) + 64;
   }
+  pool += (size_t)kBMaxSlabs * (pstride_of(16) + 1) + 64;
+  B->pool_doubles = pool;
+  add(sizeof(double) * pool);
   if (B->dtype == CABCD_F64) {
     area = std::max<int>(area, gdev::Cfg<16, 2>::LDS);
     area = std::max<int>(area, gdev::Cfg<1, 2>::LDS);
@@ -901,8 +926,9 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   Workspace ws{static_cast<char*>(B->mem)};
   B->dP = ws.take<BProb>(P);
   B->dS = ws.take<BState>(P);
-  B->dI = ws.take<BItem>(items.size());
+  B->dI = ws.take<BItem>(B->items_cap);
   B->dQ = ws.take<BQueue>(1);
+  B->pool = ws.take<double>(B->pool_doubles);
   B->probs.resize(P);
   std::vector<BState> S(P);
   for (int p = 0; p < P; ++p) {
@@ -954,22 +980,40 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   int occ = 0;
   BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_kernel_ptr(B->dtype), kBT,
                                                          B->step_lds));
-  B->grid_step = std::max(1, std::min(B->nitems, std::max(occ, 1) * cus));
+  B->occ_step = std::max(occ, 1);
+  B->grid_step = std::max(1, std::min(B->nitems, B->occ_step * cus));
   BATCH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &occ, reinterpret_cast<const void*>(batch_aux_kernel<0, CABCD_F64>), kBT, 0));
-  B->grid_aux = std::max(1, std::min(B->nitems, std::max(occ, 1) * cus));
+  B->occ_aux = std::max(occ, 1);
+  B->grid_aux = std::max(1, std::min(B->nitems, B->occ_aux * cus));
+  B->plan_active = P;
 
   // r_0 = X^T w_0 - y and f(w_0).
   BATCH_HIP(launch_aux(B, kAuxExact, st));
   cabcd_status rc = sync_status(B, st, nullptr);
   if (rc != CABCD_OK) return rc;
 
-  // Capture one monitor period (or one round without monitoring): one graph
-  // ending in a maintained-residual monitor, one ending in an exact one.  A
-  // period longer than kGraphMaxRounds rounds runs as direct launches (the
-  // graph would hold one node per round).
+  {
+    const int R = B->monitor_every > 0 ? B->monitor_every : 1;
+    B->replan_period = (int64_t)R * ((kReplanRounds + R - 1) / R);
+  }
+  return capture(B);
+}
+
+// Capture one monitor period (or one round without monitoring): one graph
+// ending in a maintained-residual monitor, one ending in an exact one.  A
+// period longer than kGraphMaxRounds rounds runs as direct launches (the graph
+// would hold one node per round).  Replaces the graphs of an earlier plan.
+cabcd_status capture(cabcd_batch_plan* B) {
+  for (int g = 0; g < 2; ++g) {
+    if (B->exec[g] != nullptr) BATCH_HIP(hipGraphExecDestroy(B->exec[g]));
+    if (B->graph[g] != nullptr) BATCH_HIP(hipGraphDestroy(B->graph[g]));
+    B->exec[g] = nullptr;
+    B->graph[g] = nullptr;
+  }
+  B->graph_rounds = 0;
   if ((B->flags & CABCD_BATCH_NO_GRAPH) == 0 && B->monitor_every <= kGraphMaxRounds) {
-    BATCH_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    if (B->cap == nullptr) BATCH_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     const int R = B->monitor_every > 0 ? B->monitor_every : 1;
     for (int g = 0; g < (B->monitor_every > 0 ? 2 : 1); ++g) {
       BATCH_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
@@ -990,6 +1034,67 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
     B->graph_rounds = R;
   }
   return CABCD_OK;
+}
+
+// Re-slicing: once the active problems have halved since the slabs were last
+// cut, their slabs are cut again for the active problems alone (same (b, s),
+// the slab target recomputed from their work), so the GPU stays filled as
+// problems retire.  Runs between launches; the partials and objective
+// partials live only within a launch, so they move to the pool freely.  Only
+// the rounding order of the Gram sums changes (more, shorter slabs).
+cabcd_status replan(cabcd_batch_plan* B, hipStream_t st) {
+  std::vector<BState> S(B->P);
+  BATCH_HIP(hipMemcpyAsync(S.data(), B->dS, sizeof(BState) * B->P, hipMemcpyDeviceToHost, st));
+  BATCH_HIP(hipStreamSynchronize(st));
+  std::vector<int> act;
+  for (int p = 0; p < B->P; ++p)
+    if (S[p].active) act.push_back(p);
+  if (act.empty() || 2 * (int)act.size() > B->plan_active) return CABCD_OK;
+  double W = 0.0;
+  std::vector<double> wp(act.size());
+  for (size_t i = 0; i < act.size(); ++i) {
+    const BProb& o = B->probs[act[i]];
+    wp[i] = slab_work(o.b * o.s, o.n, B->dtype);
+    W += wp[i];
+  }
+  std::vector<int64_t> chunk(act.size());
+  std::vector<int> nslab(act.size());
+  for (double target = std::max(W / (4.0 * B->cus), 20e-6);; target *= 2.0) {
+    size_t items = 0, doubles = 0;
+    for (size_t i = 0; i < act.size(); ++i) {
+      const BProb& o = B->probs[act[i]];
+      slice(wp[i], target, o.n, tile_cols(o.nb, B->dtype), chunk[i], nslab[i]);
+      items += nslab[i];
+      doubles += (size_t)nslab[i] * (pstride_of(o.nb) + 1) + 64;
+    }
+    if (items <= (size_t)B->items_cap && doubles <= B->pool_doubles) break;
+  }
+  // pool offsets, problems with the longest slab first
+  std::vector<int> order(act.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return wp[a] / nslab[a] > wp[b] / nslab[b];
+  });
+  Workspace ws{reinterpret_cast<char*>(B->pool)};
+  std::vector<BItem> items;
+  for (int i : order) {
+    BProb& o = B->probs[act[i]];
+    o.chunk = chunk[i];
+    o.nslab = nslab[i];
+    o.partials = ws.take<double>((size_t)o.nslab * pstride_of(o.nb));
+    o.objp = ws.take<double>(o.nslab);
+    for (int q = 0; q < o.nslab; ++q) items.push_back(BItem{act[i], q});
+  }
+  B->nitems = (int)items.size();
+  B->grid_step = std::max(1, std::min(B->nitems, B->occ_step * B->cus));
+  B->grid_aux = std::max(1, std::min(B->nitems, B->occ_aux * B->cus));
+  B->plan_active = (int)act.size();
+  BATCH_HIP(hipMemcpyAsync(B->dP, B->probs.data(), sizeof(BProb) * B->P, hipMemcpyHostToDevice,
+                           st));
+  BATCH_HIP(hipMemcpyAsync(B->dI, items.data(), sizeof(BItem) * items.size(),
+                           hipMemcpyHostToDevice, st));
+  BATCH_HIP(hipStreamSynchronize(st));
+  return capture(B);
 }
 
 }  // namespace
@@ -1055,16 +1160,20 @@ cabcd_status cabcd_batch_run(cabcd_batch B, int64_t rounds, void* stream, int32_
       B->rounds_done += B->graph_rounds;
       if (M > 0) ++B->monitors_done;
       B->pending = M == 0;
-      continue;
+    } else {
+      BATCH_HIP(launch_step(B, st));
+      ++done;
+      ++B->rounds_done;
+      B->pending = true;
+      if (M > 0 && B->rounds_done % M == 0) {
+        BATCH_HIP(launch_aux(B, next_exact() ? kAuxExact : kAuxMonitor, st));
+        ++B->monitors_done;
+        B->pending = false;
+      }
     }
-    BATCH_HIP(launch_step(B, st));
-    ++done;
-    ++B->rounds_done;
-    B->pending = true;
-    if (M > 0 && B->rounds_done % M == 0) {
-      BATCH_HIP(launch_aux(B, next_exact() ? kAuxExact : kAuxMonitor, st));
-      ++B->monitors_done;
-      B->pending = false;
+    if (B->rounds_done % B->replan_period == 0) {
+      const cabcd_status rc = replan(B, st);
+      if (rc != CABCD_OK) return rc;
     }
   }
   if (B->pending) {

@@ -96,6 +96,34 @@ def test_batch_graph_direct_and_split_runs_are_identical(gpu_lib, cheap):
             assert np.array_equal(r0, r1)
 
 
+def test_batch_reslicing_runs_are_identical_and_match_oracle(gpu_lib):
+    """Problems retiring at different rounds (their budgets H) make the plan
+    re-cut the remaining problems' slabs at the checks every 32 rounds (here at
+    round 64, when 2 of 9 remain: a new work list, slabs and partials in the
+    pool, graphs captured again): graph, direct and unevenly split runs stay
+    bitwise identical and each problem matches the oracle."""
+    _say("batch re-slicing")
+    cases = [(64, 20000, 8, 4, 4 * H, 1e-3, 40 + H) for H in (8, 12, 20, 28, 36, 44, 60, 200)]
+    cases += [(96, 30001, 16, 2, 400, 1e-3, 90)]
+    runs = []
+    for graph, chunks in ((True, [120]), (False, [120]), (True, [5, 27, 32, 1, 55])):
+        probs = _problems(cases)
+        with gpu_lib.Batch(probs, monitor_every=4, graph=graph) as B:
+            for c in chunks:
+                B.run(c)
+            infos = [B.info(p) for p in range(len(probs))]
+        torch.cuda.synchronize()
+        runs.append([(q["w"].cpu().numpy(), q["r"].cpu().numpy()) for q in probs])
+    for other in runs[1:]:
+        for (w0, r0), (w1, r1) in zip(runs[0], other):
+            assert np.array_equal(w0, w1) and np.array_equal(r0, r1)
+    for (d, n, b, s, H, lam, seed), inf, q in zip(cases, infos, probs):
+        assert inf["h"] == min(H, 120 * s)
+        wo, _ = bcd.primal_bcd(q["Xc"], q["yc"], lam, b, s, inf["h"], seed)
+        w = q["w"].cpu().numpy()
+        assert np.linalg.norm(w - wo) <= 1e-10 * np.linalg.norm(wo)
+
+
 def test_batch_long_monitor_period_runs_without_graph(gpu_lib):
     """A monitor period longer than the 64 rounds a graph may hold launches
     directly: same iterates as a plan with graphs switched off."""
