@@ -68,8 +68,13 @@ def parse():
                     help="run only the extra records (s sweep, dual, sparse, residual stops)")
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the numerical-stability record")
+    ap.add_argument("--only-sparse", action="store_true",
+                    help="run only the sparse dual records (CSR, s = 1, 8, 32)")
     ap.add_argument("--only-stability", action="store_true",
                     help="run only the numerical-stability record")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB of FP64 three times (the reference kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per Gram launch measured by rocprofv3 counters")
     return ap.parse_args()
@@ -242,9 +247,10 @@ def headline(args, cabcd, torch, synth):
 
 
 def extra_records(args, cabcd, torch, synth, X, y):
-    """Other shapes of the path (events bracket the Gram only, so the step
-    times carry no timing overhead); per_iteration_us = step time / s, the cost
-    of one b-coordinate iteration, shows what the s-step form saves."""
+    """Other shapes of the path (events bracket the Gram only; the event pair
+    costs a few microseconds per step, which shows at s = 1: graph_small_steps
+    has the small steps without events); per_iteration_us = step time / s, the
+    cost of one b-coordinate iteration, shows what the s-step form saves."""
     rec = {}
     gram_only = 1 << cabcd.PHASES.index("gram")
     d, n, lam = args.d, args.n, args.lam
@@ -267,23 +273,35 @@ def extra_records(args, cabcd, torch, synth, X, y):
                        "gram_tflops": round(d * sb * (sb + 1) / (g * 1e-3) / 1e12, 3)}
     log(f"dual: {rec['dual_s32']}")
     del XT
-    # sparse dual: A = X^T in CSR, 20000 rows x 2^20 columns, 315 Zipf(1.1) features per row
+    sp, A, yd = sparse_records(cabcd, torch, synth)
+    rec.update(sp)
+    rec.update(resid_tol_records(cabcd, torch, X, y, lam, args.b, args.s, A, yd))
+    rec["graph_small_steps"] = graph_records(cabcd, torch, X, y, lam)
+    return rec
+
+
+def sparse_records(cabcd, torch, synth):
+    """Sparse dual on A = X^T in CSR, 20000 rows x 2^20 columns, 315 Zipf(1.1)
+    features per row, b = 16, s = 1, 8, 32."""
     import numpy as np
+    rec = {}
+    gram_only = 1 << cabcd.PHASES.index("gram")
     log("generating the sparse problem (CSR, 20000 x 2^20)")
     rowptr, colidx, vals, ys, _ = synth.zipf_csr_ridge(20000, 1 << 20, 315, 1002)
     A = cabcd.CSR(torch.tensor(rowptr, device="cuda"), torch.tensor(colidx, device="cuda"),
                   torch.tensor(vals, device="cuda"), (20000, 1 << 20))
     yd = torch.tensor(ys, device="cuda")
+    steps = 32   # two whole launches of the split Gram (16 steps each) at s b >= 256
     for s in (1, 8, 32):
         b = 16
-        el, ph = timed_primal(cabcd, torch, A, yd, 1e-5, b, s, 20, 2, 2002, dual=True,
+        el, ph = timed_primal(cabcd, torch, A, yd, 1e-5, b, s, steps, 2, 2002, dual=True,
                               mask=gram_only)
         # per outer step: the Grams of several future steps come from one launch,
         # the Y u of each step from its own
-        g = ph["gram"]["ms"] / 20
+        g = ph["gram"]["ms"] / steps
         # algorithmic Gram work of the sampled rows: 2 sum_c nnz_c(I)^2 flops over the
         # nnz of the gathered rows (12 bytes each), averaged over the timed steps
-        idx = cabcd.sample(2002, 2 * s, 20 * s, b, 20000).cpu().numpy().reshape(20, s * b)
+        idx = cabcd.sample(2002, 2 * s, steps * s, b, 20000).cpu().numpy().reshape(steps, s * b)
         fl, by = [], []
         for blk in idx:
             cols = np.concatenate([colidx[rowptr[i]:rowptr[i + 1]] for i in blk])
@@ -291,13 +309,11 @@ def extra_records(args, cabcd, torch, synth, X, y):
             fl.append(2.0 * float((cnt.astype(np.float64) ** 2).sum()))
             by.append(12.0 * len(cols))
         rec[f"sparse_dual_s{s}"] = {
-            "ms_per_step": round(el / 20 * 1e3, 4), "gram_ms": round(g, 4),
+            "ms_per_step": round(el / steps * 1e3, 4), "gram_ms": round(g, 4),
             "gram_gflops": round(np.mean(fl) / (g * 1e-3) / 1e9, 2),
             "gram_gbs": round(np.mean(by) / (g * 1e-3) / 1e9, 2)}
         log(f"sparse dual s={s}: {rec[f'sparse_dual_s{s}']}")
-    rec.update(resid_tol_records(cabcd, torch, X, y, lam, args.b, args.s, A, yd))
-    rec["graph_small_steps"] = graph_records(cabcd, torch, X, y, lam)
-    return rec
+    return rec, A, yd
 
 
 def graph_records(cabcd, torch, X, y, lam, steps=64):
@@ -725,6 +741,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 1 GiB three times")
+        return
     cabcd.load()
     if args.only_batch:
         print(json.dumps({"batched_tol": batched_tol(cabcd, torch, synth,
@@ -739,6 +763,9 @@ def main():
         X, y, _ = synth.spectral_ridge(args.d, args.n, 1001, device="cuda:0")
         torch.cuda.synchronize()
         print(json.dumps({"extra": extra_records(args, cabcd, torch, synth, X, y)}), flush=True)
+        return
+    if args.only_sparse:
+        print(json.dumps({"sparse": sparse_records(cabcd, torch, synth)[0]}), flush=True)
         return
     if args.only_stability:
         print(json.dumps({"stability": stability(cabcd, torch, synth)}), flush=True)
