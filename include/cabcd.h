@@ -342,8 +342,11 @@ typedef struct cabcd_problem {
   double lambda;             /* > 0                                                */
   int32_t b;                 /* block size, 1..16; 0: chosen by the autotuner
                                 (4, 8 or 16; fewer only when d is smaller)         */
-  int32_t s;                 /* unrolling, s*b <= 256; 0: chosen by the autotuner
-                                (4 <= s <= 32 within s*b <= 256)                   */
+  int32_t s;                 /* unrolling, s*b <= 512 and s times b rounded up to
+                                a power of two <= 512 (above 256 rows the Gram is
+                                assembled from 256-row Grams, as for the one-
+                                problem path); 0: chosen by the autotuner
+                                (4 <= s <= 32 within s*b <= 512)                   */
   uint64_t seed;             /* sampler seed (blocks over [0, d))                  */
   int64_t H;                 /* inner-iteration budget; <= 0: unlimited            */
   double f_target;           /* > 0: retire at the first monitor point with

@@ -37,7 +37,7 @@ namespace cabcd {
 namespace {
 
 constexpr int kBT = 512;           // threads of the batched kernels (8 waves)
-constexpr int kBMaxRows = 256;     // s*b of one problem (Gram classes nb <= 16)
+constexpr int kBMaxRows = 512;     // s*b of one problem (above 256: assembled Gram)
 constexpr int kBMaxB = 16;
 constexpr int kBMaxSlabs = 64;
 
@@ -55,7 +55,8 @@ struct BProb {                     // constant per problem (device copy)
   int64_t chunk;                   // columns per slab
   int b, s, bp, nb;
   int nslab, aligned;
-  double* partials;                // nslab x (nblk*256 + 16 nb)
+  int sets, pad;                   // partial sets per slab (1; above 256 rows 4 or 6)
+  double* partials;                // nslab x sets x (nblk*256 + 16 nb)
   double* G;                       // (s b)^2
   double* Yu;                      // s b
   double* delta;                   // s b: the last step's delta
@@ -400,6 +401,8 @@ __global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict
   int32_t* iprev = icur + kBMaxRows;
   double* dprev = reinterpret_cast<double*>(iprev + kBMaxRows);
   int* ctl = reinterpret_cast<int*>(dprev + kBMaxRows);
+  int32_t* ia = ctl + 4;           // index lists of a Gram above 256 rows
+  int32_t* ib = ia + 512;
   const int tid = threadIdx.x;
 
   for (int it = next_item(Q, ctl); it < nitems; it = next_item(Q, ctl)) do {
@@ -427,14 +430,32 @@ __global__ __launch_bounds__(kBT) void batch_step_kernel(const BProb* __restrict
       __syncthreads();   // the Gram below reads these r values back
     }
     const int64_t pstride = (int64_t)(pr.nb * (pr.nb + 1) / 2) * 256 + 16 * pr.nb;
-    gram_any<FMT>(pr.nb, pr.A, pr.ld, k0, k1, icur, m, pr.r, pr.partials + item.slab * pstride,
-                  pr.aligned);
+    const int sets = uni(pr.sets);
+    // a problem above 256 rows: the Gram of every step assembled from 256-row
+    // Grams (the two diagonal blocks, then 2 or 4 cross-block Grams)
+    const int nsets = sets == 1 ? 1 : 2 + (m - 256 > 128 ? 4 : 2);
+    if (sets == 1) {
+      gram_any<FMT>(pr.nb, pr.A, pr.ld, k0, k1, icur, m, pr.r, pr.partials + item.slab * pstride,
+                    pr.aligned);
+    } else {
+      gdev::big_lists(icur, m, ia, ib, tid, kBT);
+      __syncthreads();
+      double* part = pr.partials + (int64_t)item.slab * sets * pstride;
+      for (int g = 0; g < nsets; ++g)
+        gram_any<FMT>(16, pr.A, pr.ld, k0, k1, g < 2 ? ia + 256 * g : ib + 256 * (g - 2), 256,
+                      g < 2 ? pr.r : nullptr, part + g * pstride, pr.aligned);
+    }
     if (!arrive_last(st, pr.nslab, ctl + 1)) break;
 
     // Last slab of this problem: Gov (overlap-augmented, Alg. 2 scale 1/n and
     // shift lambda), then the fused solve and w[idx] += delta.
-    gdev::reduce_wg<kBT>(pr.partials, pr.nslab, pr.nb, icur, m, 1.0 / (double)pr.n, pr.lambda,
-                         pr.G, pr.Yu, FMT == CABCD_F64 ? 0 : 1, pr.rs);
+    if (sets == 1)
+      gdev::reduce_wg<kBT>(pr.partials, pr.nslab, pr.nb, icur, m, 1.0 / (double)pr.n, pr.lambda,
+                           pr.G, pr.Yu, FMT == CABCD_F64 ? 0 : 1, pr.rs);
+    else
+      gdev::reduce_wg_big<kBT>(pr.partials, pr.nslab, sets * pstride, nsets, icur, m,
+                               1.0 / (double)pr.n, pr.lambda, pr.G, pr.Yu,
+                               FMT == CABCD_F64 ? 0 : 1, pr.rs);
     __syncthreads();
     SolveArgs a;
     a.G = pr.G;
@@ -545,11 +566,16 @@ int pow2_at_least(int b) {
 
 int nb_of(int sb) {
   int nb = 1;
-  while (16 * nb < sb) nb *= 2;
+  while (16 * nb < sb && nb < 16) nb *= 2;
   return nb;
 }
 
+// Partial sets of one slab: one Gram, or above 256 rows the 2 diagonal and
+// 2 or 4 cross-block 256-row Grams.
+int sets_of(int sb) { return sb <= 256 ? 1 : 2 + (sb - 256 > 128 ? 4 : 2); }
+
 int64_t pstride_of(int nb) { return (int64_t)(nb * (nb + 1) / 2) * 256 + 16 * nb; }
+int64_t slab_doubles(int sb) { return sets_of(sb) * pstride_of(nb_of(sb)); }
 
 // Cost model of one round (seconds), with rates measured on MI355X with the
 // one-problem kernels: the FP64 Gram at sb = 256 ran at 48 TFLOP/s over 256
@@ -575,7 +601,7 @@ int tile_cols(int nb, int dtype) {
 // the two passes over the gathered rows: Gram and deferred update).
 double slab_work(int sb, int64_t cols, int dtype) {
   const int sbp = 16 * nb_of(sb);
-  const double flops = (double)cols * sbp * (sbp + 1);
+  const double flops = (double)cols * sbp * (sbp + 1) * sets_of(sb);
   const double bytes = 2.0 * elem_bytes(dtype) * (double)cols * sb;
   return std::max(flops / (dtype == CABCD_F64 ? kCuF64 : kCuLp), bytes / kCuBw);
 }
@@ -642,7 +668,7 @@ double plan_candidate(const std::vector<cabcd_problem>& pb, double rp, int cus,
     const double wp = slab_work(sb, n, pb[p].X.dtype);
     slice(wp, target, n, tile_cols(nb, pb[p].X.dtype), out[p].chunk, out[p].nslab);
     const int64_t nslab = out[p].nslab;
-    out[p].crit = wp / nslab + nslab * pstride_of(nb) * 8.0 / kWgBw + out[p].s * kSolveBlock;
+    out[p].crit = wp / nslab + nslab * slab_doubles(sb) * 8.0 / kWgBw + out[p].s * kSolveBlock;
     crit = std::max(crit, out[p].crit);
     passes = std::max(passes, (double)pb[p].X.rows / sb);
   }
@@ -802,6 +828,11 @@ cabcd_status check_problem(const cabcd_problem& q, int p) {
               kBMaxRows, q.b, q.s);
     return CABCD_EINVAL;
   }
+  if (q.b > 0 && q.s > 0 && q.s * pow2_at_least(q.b) > kBT) {
+    set_error("problem %d: s times b rounded up to a power of two must be <= %d (b=%d s=%d)", p,
+              kBT, q.b, q.s);
+    return CABCD_EUNSUPPORTED;
+  }
   return CABCD_OK;
 }
 
@@ -891,15 +922,15 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   for (int p = 0; p < P; ++p) {
     const int sb = best[p].b * best[p].s;
     const int nb = nb_of(sb);
-    add(sizeof(double) * best[p].nslab * pstride_of(nb));
+    add(sizeof(double) * best[p].nslab * slab_doubles(sb));
     add(sizeof(double) * sb * sb);
     add(sizeof(double) * sb);
     add(sizeof(double) * sb);
     add(sizeof(double) * best[p].nslab);
     area = std::max<int>(area, (int)((solve_lds_bytes(sb, best[p].b) + 7) / 8));
-    pool += (size_t)best[p].nslab * (pstride_of(nb) + 1) + 64;
+    pool += (size_t)best[p].nslab * (slab_doubles(sb) + 1) + 64;
   }
-  pool += (size_t)kBMaxSlabs * (pstride_of(16) + 1) + 64;
+  pool += (size_t)kBMaxSlabs * (slab_doubles(kBMaxRows) + 1) + 64;
   B->pool_doubles = pool;
   add(sizeof(double) * pool);
   if (B->dtype == CABCD_F64) {
@@ -917,7 +948,7 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
   }
   B->area = (area + 1) & ~1;
   B->step_lds = sizeof(double) * B->area + kBMaxRows * 2 * sizeof(int32_t) +
-                kBMaxRows * sizeof(double) + 4 * sizeof(int);
+                kBMaxRows * sizeof(double) + 4 * sizeof(int) + (512 + 1024) * sizeof(int32_t);
   if (hipMalloc(&B->mem, bytes + 256) != hipSuccess) {
     B->mem = nullptr;
     set_error("hipMalloc of %zu bytes for the batch plan failed", bytes);
@@ -952,12 +983,14 @@ cabcd_status create(const cabcd_problem* pb, int32_t P, const cabcd_batch_opts* 
     o.s = best[p].s;
     o.bp = pow2_at_least(o.b);
     o.nb = nb_of(sb);
+    o.sets = sets_of(sb);
+    o.pad = 0;
     o.nslab = best[p].nslab;
     o.aligned = ((reinterpret_cast<uintptr_t>(o.A) & 15) == 0 &&
                  ((o.ld * elem_bytes(B->dtype)) & 15) == 0)
                     ? 1
                     : 0;
-    o.partials = ws.take<double>((size_t)o.nslab * pstride_of(o.nb));
+    o.partials = ws.take<double>((size_t)o.nslab * slab_doubles(sb));
     o.G = ws.take<double>((size_t)sb * sb);
     o.Yu = ws.take<double>(sb);
     o.delta = ws.take<double>(sb);
@@ -1065,7 +1098,7 @@ cabcd_status replan(cabcd_batch_plan* B, hipStream_t st) {
       const BProb& o = B->probs[act[i]];
       slice(wp[i], target, o.n, tile_cols(o.nb, B->dtype), chunk[i], nslab[i]);
       items += nslab[i];
-      doubles += (size_t)nslab[i] * (pstride_of(o.nb) + 1) + 64;
+      doubles += (size_t)nslab[i] * (slab_doubles(o.b * o.s) + 1) + 64;
     }
     if (items <= (size_t)B->items_cap && doubles <= B->pool_doubles) break;
   }
@@ -1081,7 +1114,7 @@ cabcd_status replan(cabcd_batch_plan* B, hipStream_t st) {
     BProb& o = B->probs[act[i]];
     o.chunk = chunk[i];
     o.nslab = nslab[i];
-    o.partials = ws.take<double>((size_t)o.nslab * pstride_of(o.nb));
+    o.partials = ws.take<double>((size_t)o.nslab * slab_doubles(o.b * o.s));
     o.objp = ws.take<double>(o.nslab);
     for (int q = 0; q < o.nslab; ++q) items.push_back(BItem{act[i], q});
   }

@@ -751,6 +751,71 @@ __device__ __forceinline__ void store_entry(int64_t e, double t, int nblk, const
   }
 }
 
+// Index lists of a Gram of m in (256, 512] rows: ia = the m indices padded to
+// 512 with idx[0] (two 256-row Grams: the diagonal blocks); ib[t] (t < nc,
+// nc = 4 when m > 384, else 2) = idx[128 x .. 128 x + 128) followed by
+// ia[256 + 128 y .. 256 + 128 y + 128), x = t % 2, y = t / 2, whose 256-row
+// Gram holds the cross block of rows 256 + 128 y.. and columns 128 x.. .
+// Padding rows are multiplied and never stored.  Thread t of nthreads.
+__device__ __forceinline__ void big_lists(const int32_t* idx, int m, int32_t* ia, int32_t* ib,
+                                          int t, int nthreads) {
+  const int nc = m - 256 > 128 ? 4 : 2;
+  const int i0 = idx[0];
+  for (int q = t; q < 512; q += nthreads) ia[q] = idx[q < m ? q : 0];
+  for (int slot = t; slot < 256 * nc; slot += nthreads) {
+    const int list = slot >> 8, pos = slot & 255;
+    const int x = list & 1, y = list >> 1;
+    int v;
+    if (pos < 128) {
+      v = idx[128 * x + pos];
+    } else {
+      const int r = 256 + 128 * y + (pos - 128);
+      v = r < m ? idx[r] : i0;
+    }
+    ib[slot] = v;
+  }
+}
+
+// Where the reduced entry e of step `step` of a Gram of more than 256 rows
+// goes (m in (256, 512], assembled from 256-row Grams; see
+// launch_big_index): set 0 holds the two diagonal 256 x 256 blocks (step k:
+// rows and columns 256 k + local) and Y u; set 1 holds the cross blocks, step
+// t giving rows 256 + 128 (t / 2) + (local row - 128) and columns
+// 128 (t % 2) + local column from the local block rows 8..15 x columns 0..7.
+__device__ __forceinline__ void store_entry_big(int64_t e, double t, int set, int step,
+                                                const int32_t* idx, int m, double scale,
+                                                double shift, int overlap,
+                                                double* __restrict__ G, double* __restrict__ Yu,
+                                                int layout, const float* __restrict__ rs,
+                                                const double* __restrict__ add) {
+  constexpr int kNblk = 136;
+  if (e >= (int64_t)kNblk * 256) {          // the Y u entries follow the blocks
+    const int p = 256 * step + (int)(e - (int64_t)kNblk * 256);
+    if (set == 0 && Yu != nullptr && p < m) glb(Yu)[p] = rs ? (double)glb(rs)[idx[p]] * t : t;
+    return;
+  }
+  int row, col;
+  bool lower;
+  entry_rc(e, layout, row, col, lower);
+  if (!lower) return;
+  int gr, gc;
+  if (set == 0) {
+    gr = 256 * step + row;
+    gc = 256 * step + col;
+  } else {
+    if (row < 128 || col >= 128) return;
+    gr = 256 + 128 * (step >> 1) + (row - 128);
+    gc = 128 * (step & 1) + col;
+  }
+  if (gr >= m || gc >= m) return;
+  const bool on = overlap ? (idx[gr] == idx[gc]) : (gr == gc);
+  const double sc = rs ? scale * (double)glb(rs)[idx[gr]] * (double)glb(rs)[idx[gc]] : scale;
+  if (add != nullptr) t += glb(add)[(int64_t)gr * m + gc];
+  const double v = sc * t + (on ? shift : 0.0);
+  glb(G)[(int64_t)gr * m + gc] = v;
+  glb(G)[(int64_t)gc * m + gr] = v;
+}
+
 // The whole reduction by one workgroup of T threads: partial sets 0..nsplit-1
 // (stride nblk*256 + 16 nb) are added in set order for every entry.
 template <int T>
@@ -773,6 +838,37 @@ __device__ __forceinline__ void reduce_wg(const double* __restrict__ partials, i
     }
     for (; sp < nsplit; ++sp) s += p[(int64_t)sp * pstride];
     store_entry(e, s, nblk, idx, m, scale, shift, 1, G, Yu, layout, rs);
+  }
+}
+
+// The reduction of a Gram of m <= 512 rows assembled from 256-row Grams, by
+// one workgroup of T threads: slab q's partial set g (g < 2: the diagonal
+// blocks, then the cross blocks; nsets = 2 + big_cross_steps(m)) is at
+// partials + q sstride + g pstride16; every entry sums its slabs in slab order
+// and is stored once (store_entry_big).
+template <int T>
+__device__ __forceinline__ void reduce_wg_big(const double* __restrict__ partials, int nslab,
+                                              int64_t sstride, int nsets, const int32_t* idx,
+                                              int m, double scale, double shift,
+                                              double* __restrict__ G, double* __restrict__ Yu,
+                                              int layout, const float* __restrict__ rs) {
+  constexpr int64_t pstride = (int64_t)136 * 256 + 16 * 16;
+  for (int g = 0; g < nsets; ++g) {
+    const int cls = g < 2 ? 0 : 1, step = g < 2 ? g : g - 2;
+    for (int64_t e = threadIdx.x; e < pstride; e += T) {
+      const gptr<const double> p = glb(partials) + (int64_t)g * pstride + e;
+      double s = 0.0;
+      int q = 0;
+      for (; q + 8 <= nslab; q += 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p[(int64_t)(q + j) * sstride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+      }
+      for (; q < nslab; ++q) s += p[(int64_t)q * sstride];
+      store_entry_big(e, s, cls, step, idx, m, scale, shift, 1, G, Yu, layout, rs, nullptr);
+    }
   }
 }
 

@@ -63,46 +63,6 @@ __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
 constexpr int kRedThreads = 1024;
 int red_groups(int nsplit) { return nsplit <= 4 ? 1 : 16; }
 
-// Where the reduced entry e of step `step` of a Gram of more than 256 rows
-// goes (m in (256, 512], assembled from 256-row Grams; see
-// launch_big_index): set 0 holds the two diagonal 256 x 256 blocks (step k:
-// rows and columns 256 k + local) and Y u; set 1 holds the cross blocks, step
-// t giving rows 256 + 128 (t / 2) + (local row - 128) and columns
-// 128 (t % 2) + local column from the local block rows 8..15 x columns 0..7.
-__device__ __forceinline__ void store_entry_big(int64_t e, double t, int set, int step,
-                                                const int32_t* idx, int m, double scale,
-                                                double shift, int overlap,
-                                                double* __restrict__ G, double* __restrict__ Yu,
-                                                int layout, const float* __restrict__ rs,
-                                                const double* __restrict__ add) {
-  constexpr int kNblk = 136;
-  if (e >= (int64_t)kNblk * 256) {          // the Y u entries follow the blocks
-    const int p = 256 * step + (int)(e - (int64_t)kNblk * 256);
-    if (set == 0 && Yu != nullptr && p < m) glb(Yu)[p] = rs ? (double)glb(rs)[idx[p]] * t : t;
-    return;
-  }
-  int row, col;
-  bool lower;
-  entry_rc(e, layout, row, col, lower);
-  if (!lower) return;
-  int gr, gc;
-  if (set == 0) {
-    gr = 256 * step + row;
-    gc = 256 * step + col;
-  } else {
-    if (row < 128 || col >= 128) return;
-    gr = 256 + 128 * (step >> 1) + (row - 128);
-    gc = 128 * (step & 1) + col;
-  }
-  if (gr >= m || gc >= m) return;
-  const bool on = overlap ? (idx[gr] == idx[gc]) : (gr == gc);
-  const double sc = rs ? scale * (double)glb(rs)[idx[gr]] * (double)glb(rs)[idx[gc]] : scale;
-  if (add != nullptr) t += glb(add)[(int64_t)gr * m + gc];
-  const double v = sc * t + (on ? shift : 0.0);
-  glb(G)[(int64_t)gr * m + gc] = v;
-  glb(G)[(int64_t)gc * m + gr] = v;
-}
-
 // Partial set blockIdx.y: partials + set * nsplit * pstride.  MODE 0: the
 // Gram of step blockIdx.y (idx + step * m, G and add + step * m * m; Yu is
 // NULL for several steps).  MODE 1 / 2: sets 0 / 1 of Grams of m in
@@ -168,43 +128,18 @@ __global__ __launch_bounds__(kRedThreads) void gram_reduce_kernel(
   if constexpr (MODE == 0)
     store_entry(e, t, nblk, idx, m, scale, shift, overlap, G, Yu, layout, rs, add);
   else
-    store_entry_big(e, t, MODE - 1, part, idx, m, scale, shift, overlap, G, Yu, layout, rs,
-                    add);
+    gdev::store_entry_big(e, t, MODE - 1, part, idx, m, scale, shift, overlap, G, Yu, layout,
+                          rs, add);
 }
 
-// Index lists of a Gram of m in (256, 512] rows (one workgroup of 512):
-// ia = the m indices padded to 512 with idx[0] (two 256-row Grams: the
-// diagonal blocks); ib[t] (t < 4) = idx[128 x .. 128 x + 128) followed by
-// ia[256 + 128 y .. 256 + 128 y + 128), x = t % 2, y = t / 2, whose 256-row
-// Gram holds the cross block of rows 256 + 128 y.. and columns 128 x.. .
-// Padding rows are multiplied and never stored.
-// Workgroup k builds the lists of Gram k (indices idx + k m) at ia + 512 k and
-// ib + 256 nc k, nc = big_cross_steps(m) lists.
+// Workgroup k builds the index lists (gdev::big_lists) of Gram k (indices
+// idx + k m) at ia + 512 k and ib + 256 nc k, nc = big_cross_steps(m) lists.
 __global__ __launch_bounds__(512) void big_index_kernel(const int32_t* __restrict__ idx, int m,
                                                         int32_t* __restrict__ ia,
                                                         int32_t* __restrict__ ib) {
-  const int t = threadIdx.x;
   const int nc = m - 256 > 128 ? 4 : 2;
-  idx += (int64_t)blockIdx.x * m;
-  ia += (int64_t)blockIdx.x * 512;
-  ib += (int64_t)blockIdx.x * 256 * nc;
-  ia[t] = idx[t < m ? t : 0];
-  const int i0 = idx[0];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int slot = t + 512 * q;             // 0 .. 1023
-    const int list = slot >> 8, pos = slot & 255;
-    if (list >= nc) break;
-    const int x = list & 1, y = list >> 1;
-    int v;
-    if (pos < 128) {
-      v = idx[128 * x + pos];
-    } else {
-      const int r = 256 + 128 * y + (pos - 128);
-      v = r < m ? idx[r] : i0;
-    }
-    ib[slot] = v;
-  }
+  gdev::big_lists(idx + (int64_t)blockIdx.x * m, m, ia + (int64_t)blockIdx.x * 512,
+                  ib + (int64_t)blockIdx.x * 256 * nc, threadIdx.x, 512);
 }
 
 template <int NB, int RPW>

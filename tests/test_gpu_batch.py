@@ -124,6 +124,38 @@ def test_batch_reslicing_runs_are_identical_and_match_oracle(gpu_lib):
         assert np.linalg.norm(w - wo) <= 1e-10 * np.linalg.norm(wo)
 
 
+BIG_CASES = [
+    (400, 6000, 16, 32, 3 * 32 * 16 + 5 * 16, 1e-3, 61),   # s b = 512, ragged last step (80 rows)
+    (300, 4097, 16, 20, 7 * 20 * 16, 1e-3, 62),            # 320 rows: 2 cross-block Grams
+    (200, 3001, 12, 30, 5 * 30 * 12 + 7, 1e-2, 63),        # 360 rows, b not a power of two
+    (64, 2000, 8, 4, 120, 1e-3, 64),                       # a small problem beside them
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_batch_grams_above_256_rows(gpu_lib, dtype):
+    """s b in (256, 512]: every step's Gram assembled from 256-row Grams inside
+    the persistent kernel.  FP64: each problem matches the oracle (1e-10).
+    BF16: each matches the oracle on the dequantised matrix within 1e-3 (the
+    Gram is accumulated in FP32: up to n u_32 ~ 4e-4 relative per entry at
+    n = 6000; a misplaced or missing block moves the iterates by O(1))."""
+    _say("batch above 256 rows", dtype)
+    probs = _problems(BIG_CASES)
+    if dtype == "bf16":
+        for q in probs:
+            Q = gpu_lib.quantize(q["X"], gpu_lib.BF16)
+            q["X"], q["Xc"] = Q, Q.dequantize().cpu().numpy()
+    act, infos = _run(gpu_lib, probs, [200])
+    assert act == 0
+    for q, (d, n, b, s, H, lam, seed), inf in zip(probs, BIG_CASES, infos):
+        assert inf["b"] == b and inf["s"] == s and inf["h"] == H
+        wo, _ = bcd.primal_bcd(q["Xc"], q["yc"], lam, b, s, H, seed)
+        w = q["w"].cpu().numpy()
+        err = np.linalg.norm(w - wo) / np.linalg.norm(wo)
+        _say(f"  d={d} n={n} b={b} s={s}: rel err {err:.2e}")
+        assert err <= (1e-10 if dtype == "f64" else 1e-3)
+
+
 def test_batch_long_monitor_period_runs_without_graph(gpu_lib):
     """A monitor period longer than the 64 rounds a graph may hold launches
     directly: same iterates as a plan with graphs switched off."""
