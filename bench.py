@@ -265,13 +265,16 @@ def extra_records(args, cabcd, torch, synth, X, y):
                                "gram_gbs": round(sb * n * 8 / (g * 1e-3) / 1e9, 1)}
         log(f"primal s={s}: {rec[f'primal_s{s}']}")
     XT = X.t().contiguous()
-    el, ph = timed_primal(cabcd, torch, XT, y, lam, args.b, args.s, 20, 2, 2001, dual=True,
-                          mask=gram_only)
-    g = ph["gram"]["ms"] / 20
-    sb = args.s * args.b
-    rec["dual_s32"] = {"ms_per_step": round(el / 20 * 1e3, 4), "gram_ms": round(g, 4),
-                       "gram_tflops": round(d * sb * (sb + 1) / (g * 1e-3) / 1e12, 3)}
-    log(f"dual: {rec['dual_s32']}")
+    for s in (1, 4, 16, 32):
+        el, ph = timed_primal(cabcd, torch, XT, y, lam, args.b, s, 20, 2, 2001, dual=True,
+                              mask=gram_only)
+        g = ph["gram"]["ms"] / 20
+        sb = s * args.b
+        rec[f"dual_s{s}"] = {"ms_per_step": round(el / 20 * 1e3, 4),
+                             "per_iteration_us": round(el / 20 / s * 1e6, 2),
+                             "gram_ms": round(g, 4),
+                             "gram_tflops": round(d * sb * (sb + 1) / (g * 1e-3) / 1e12, 3)}
+        log(f"dual s={s}: {rec[f'dual_s{s}']}")
     del XT
     sp, A, yd = sparse_records(cabcd, torch, synth)
     rec.update(sp)
