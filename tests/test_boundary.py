@@ -128,7 +128,8 @@ def _fake_problem(**kw):
     (dict(b=-1), cabcd.EINVAL),
     (dict(b=17), cabcd.EINVAL),           # above the batched block limit
     (dict(b=65, d=64), cabcd.EINVAL),     # b > d
-    (dict(b=16, s=17), cabcd.EINVAL),     # s*b > 256
+    (dict(b=16, s=33), cabcd.EINVAL),     # s*b > 512
+    (dict(b=9, s=40), cabcd.EUNSUPPORTED),  # s*b = 360, but s*16 > 512 solve lanes
     (dict(s=-2), cabcd.EINVAL),
     (dict(y=0), cabcd.EINVAL),
     (dict(w=0), cabcd.EINVAL),
