@@ -199,8 +199,11 @@ __device__ __forceinline__ bool chunk_of(int64_t wv, int m, int nchunk, int nste
 }
 
 // Heavy entries into the dense panel row; light entries counted in the step's
-// per-column counts (the column itself indexes the table); ent[k][p][e] =
-// the light column of entry e, or -1 for a heavy one.
+// per-column counts (the column itself indexes the table).  ent[k][p][e] =
+// -1 for a heavy entry, else the light column shifted up by kRankBits with
+// the entry's rank in its column's list (the count before it) below: columns
+// are < 2^22 and ranks < 512 rows, so the pair fits 31 bits.
+constexpr int kRankBits = 9;
 __global__ __launch_bounds__(kT) void split_scatter_kernel(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
     const double* __restrict__ vals, const int32_t* __restrict__ idx, int m, int nsteps,
@@ -217,12 +220,12 @@ __global__ __launch_bounds__(kT) void split_scatter_kernel(
   if (j >= b) return;
   const int c = colidx[j];
   const int hs = hmap[c];
-  if (hs >= 0) {
+  int e = -1;
+  if (hs >= 0)
     Dh[row * Hp + hs] = vals[j];
-  } else {
-    atomicAdd(&cnt[(int64_t)k * cs + c], 1);
-  }
-  ent[row * maxrow + (j - a)] = hs >= 0 ? -1 : c;
+  else
+    e = (c << kRankBits) | atomicAdd(&cnt[(int64_t)k * cs + c], 1);
+  ent[row * maxrow + (j - a)] = e;
 }
 
 // Exclusive scan of the step's per-column counts into list offsets (three
@@ -311,11 +314,11 @@ __global__ __launch_bounds__(kScanT) void scan_apply_kernel(const int* __restric
   }
 }
 
-// Each light entry takes the next position of its column's list (off[]
-// advances to the end of the list; its start is off - cnt afterwards).
+// Each light entry goes to its rank's position in its column's list (off[c]
+// is the list's start).
 __global__ __launch_bounds__(kT) void split_fill_kernel(
     const int64_t* __restrict__ rowptr, const double* __restrict__ vals,
-    const int32_t* __restrict__ idx, int m, int nsteps, int nchunk, int* __restrict__ off,
+    const int32_t* __restrict__ idx, int m, int nsteps, int nchunk, const int* __restrict__ off,
     int64_t cs, const int* __restrict__ ent, int maxrow, int* __restrict__ lq,
     double* __restrict__ lv, int64_t lcap) {
   const int lane = threadIdx.x & 63;
@@ -327,9 +330,9 @@ __global__ __launch_bounds__(kT) void split_fill_kernel(
   const int64_t a = rowptr[i], b = rowptr[i + 1];
   const int64_t j = a + 64 * ch + lane;
   if (j >= b) return;
-  const int c = ent[row * maxrow + (j - a)];
-  if (c < 0) return;
-  const int pos = atomicAdd(&off[(int64_t)k * cs + c], 1);
+  const int e = ent[row * maxrow + (j - a)];
+  if (e < 0) return;
+  const int pos = off[(int64_t)k * cs + (e >> kRankBits)] + (e & ((1 << kRankBits) - 1));
   lq[(int64_t)k * lcap + pos] = p;
   lv[(int64_t)k * lcap + pos] = vals[j];
 }
@@ -383,18 +386,20 @@ __global__ __launch_bounds__(kT) void split_light_kernel(
   // light columns no other gathered row shares give only p's own product:
   // each lane sums those of its entries (in row order), added at the end
   double self = 0.0;
-  int c = a + lane < b ? erow[lane] : -1;
+  int c = a + lane < b ? erow[lane] : -1;   // the light column (or -1)
+  c = c < 0 ? -1 : c >> kRankBits;
   double vp = c >= 0 ? vals[a + lane] : 0.0;
   for (int64_t e0 = a; e0 < b; e0 += 64) {
     // this batch's list extents; the next batch's columns and values
     const int nc = c >= 0 ? cnt[c] : 0;
     const int oc = c >= 0 ? off[c] : 0;
     const int64_t jn = e0 + 64 + lane;
-    const int cn = jn < b ? erow[jn - a] : -1;
+    int cn = jn < b ? erow[jn - a] : -1;
+    cn = cn < 0 ? -1 : cn >> kRankBits;
     const double vn = cn >= 0 ? vals[jn] : 0.0;
     if (nc == 1) self = fma(vp, vp, self);
     const int n = nc >= 2 ? nc : 0;
-    const int s0 = oc - n;
+    const int s0 = oc;
     // staging positions: exclusive prefix of the list lengths
     int pre = n;
 #pragma unroll
@@ -585,7 +590,9 @@ SplitLayout csr_split_layout(const CsrSplitInfo& info, int64_t cols, int m, int 
 hipError_t launch_csr_gram_split(const CsrView& A, const CsrSplitInfo& info, const int32_t* idx,
                                  int m, int nsteps, double scale, double shift, bool overlap,
                                  double* G, double* dws, int* iws, hipStream_t st) {
-  if (m < 1 || m > kSplitMaxRows || nsteps < 1 || nsteps > 65535) return hipErrorInvalidValue;
+  if (m < 1 || m > kSplitMaxRows || nsteps < 1 || nsteps > 65535 ||
+      A.cols > ((int64_t)1 << (31 - kRankBits)) || kSplitMaxRows > (1 << kRankBits))
+    return hipErrorInvalidValue;
   const SplitLayout L = csr_split_layout(info, A.cols, m, nsteps);
   const int64_t cs = L.cs;
   double* Dh = dws;
