@@ -46,6 +46,7 @@ constexpr int kSplitMaxRows = 512;
 constexpr int kSplitAhead = 16;             // steps per split Gram launch (at most)
 constexpr size_t kSplitBudget = (size_t)512 << 20;   // its scratch (bytes, at most)
 constexpr int64_t kSplitMaxCols = (int64_t)1 << 22;   // its per-step tables index columns
+constexpr int kSplitMaxRowLen = 1 << 22;              // entries of a row, below
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
 
@@ -644,6 +645,9 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   int* split_i = nullptr;
   if (split) {
     HIP_TRY(csr_split_prepare(M.C, B.split_prep, &sinfo, st));
+  }
+  if (split && sinfo.maxrow >= kSplitMaxRowLen) split = false;   // entry keys need < 2^22
+  if (split) {
     ksplit = std::min(gram_slots(M, sb_full), kSplitAhead);
     // a launch takes 1..ksplit steps; its doubles, then its ints, must fit
     size_t dmax = 0, imax = 0;
@@ -725,6 +729,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   while (bp < b) bp *= 2;
   const bool pre_inv = K > 1 && bp <= 16 && (int64_t)s * bp <= 512;
   int ahead = 0, gslot = 0;                       // precomputed Grams left, next slot
+  int split_nst = 0;                              // steps of the last split launch
   int64_t h = 0, k = 0, slot = 0;
   int64_t chunk_begin = -1, chunk_end = -1;
   const int64_t chunk_iters = kIdxChunkSteps * (int64_t)s;
@@ -761,6 +766,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
           }));
         else
           HIP_TRY(mat_gram_steps(M, idx, m, nst, scale, shift, B.G, B.partials, st, &timer));
+        split_nst = nst;
         // their diagonal blocks inverted together, off the solves' chains
         if (pre_inv)
           HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] {
@@ -796,6 +802,11 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     sa.pre_inverted = from_ahead && pre_inv ? 1 : 0;
     HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] { return launch_solve(sa, st); }));
     HIP_TRY(timer.run(CABCD_PHASE_UPDATE, [&] {
+      // steps whose Gram came from a split launch: the deterministic update
+      // from its panel and sorted lists
+      if (from_ahead && split)
+        return launch_csr_update_split(M.C, sinfo, idx, m, split_nst, gslot - 1, B.delta, gamma,
+                                       comp, split_d, split_i, st);
       return mat_scatter(M, idx, m, B.delta, gamma, nullptr, 0.0, true, comp, B.scratch, st);
     }));
     h += sk;

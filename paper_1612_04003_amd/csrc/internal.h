@@ -239,6 +239,7 @@ hipError_t launch_csr_rowdot_rows(const CsrView& A, const int32_t* idx, int64_t 
 // needs back to the host.  m <= 512.
 struct CsrSplitInfo {
   const int* hmap;   // per column: heavy slot (column order) or -1
+  const int* hcol;   // per heavy slot: its column
   int heavy;         // heavy columns
   int maxrow;        // longest row
   int maxlight;      // most light entries in one row
@@ -257,6 +258,14 @@ SplitLayout csr_split_layout(const CsrSplitInfo& info, int64_t cols, int m, int 
 hipError_t launch_csr_gram_split(const CsrView& A, const CsrSplitInfo& info, const int32_t* idx,
                                  int m, int nsteps, double scale, double shift, bool overlap,
                                  double* G, double* dws, int* iws, hipStream_t st);
+// The companion update out += gamma Y^T delta of step `step` of the split
+// launch of nsteps steps that is still in (dws, iws): one writer per column,
+// fixed summation order (heavy columns from the step's dense panel, light ones
+// from its row-sorted column lists).
+hipError_t launch_csr_update_split(const CsrView& A, const CsrSplitInfo& info,
+                                   const int32_t* idx, int m, int nsteps, int step,
+                                   const double* delta, double gamma, double* out, double* dws,
+                                   int* iws, hipStream_t st);
 hipError_t launch_csr_scatter(const CsrView& A, const int32_t* idx, int64_t m, const double* v,
                               double gamma, double* out, hipStream_t st);
 // out[p] = A[p] . v + beta * base[p] for every row.

@@ -1,9 +1,11 @@
 """CSR path vs the CPU oracle through the C-ABI.
 
 Tolerances as for the dense FP64 path: Gram entries within 1e-12 of
-scale * |Y||Y|^T, iterates within 1e-10 relative.  The companion scatter uses
-FP64 atomic adds, so the GPU result is reproducible only up to the order of
-those additions; every comparison here has a tolerance.
+scale * |Y||Y|^T, iterates within 1e-10 relative.  Outer steps whose Grams come
+from the split launch (s b >= 256) update the companion vector with one writer
+per column; the other steps scatter with FP64 atomic adds, which makes their
+result reproducible only up to the order of those additions, so every
+comparison with the oracle has a tolerance.
 """
 
 import numpy as np
@@ -200,6 +202,24 @@ def test_csr_steps_cross_index_chunks(gpu_lib):
     ao, wo = bcd.dual_bcd(S.T.tocsc(), y, 1e-2, 2, 2, H, 13)
     assert _rel(a.cpu(), ao) <= 1e-10
     assert _rel(w.cpu(), wo) <= 1e-10
+
+
+def test_csr_split_steps_are_reproducible(gpu_lib):
+    """Outer steps whose Grams come from the split launch update the companion
+    vector with one writer per column and fixed summation orders: two runs
+    give bitwise the same alpha and w (and the oracle's to 1e-10)."""
+    rows, cols = 3000, 20000
+    rowptr, colidx, vals, y, _ = synth.zipf_csr_ridge(rows, cols, 60, 78)
+    S = scipy.sparse.csr_matrix((vals, colidx, rowptr), shape=(rows, cols))
+    XT = gpu_lib.CSR.from_scipy(S, DEV)
+    s, b = 32, 16
+    H = 5 * s                  # five full outer steps of 512 gathered rows
+    runs = [gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), 1e-3, b, s, H, 23)
+            for _ in range(2)]
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    ao, wo = bcd.dual_bcd(S.T.tocsc(), y, 1e-3, b, s, H, 23)
+    assert _rel(runs[0][0].cpu(), ao) <= 1e-10
+    assert _rel(runs[0][1].cpu(), wo) <= 1e-10
 
 
 @pytest.mark.parametrize("density,s", [(0.01, 32), (0.2, 32), (0.05, 40), (0.05, 64)])
