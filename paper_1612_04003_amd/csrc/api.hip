@@ -340,17 +340,22 @@ class PhaseTimer {
   }
   template <class F>
   hipError_t run(int phase, F&& f) {
+    return run_on(st_, phase, f);
+  }
+  // The same for work enqueued on another stream (the events go there).
+  template <class F>
+  hipError_t run_on(hipStream_t st, int phase, F&& f) {
     if (out_ == nullptr || !((mask_ >> phase) & 1u)) return f();
     Rec r{phase, nullptr, nullptr};
     hipError_t e = hipEventCreate(&r.a);
     if (e == hipSuccess) e = hipEventCreate(&r.b);
     if (e != hipSuccess) return e;
     recs_.push_back(r);
-    e = hipEventRecord(r.a, st_);
+    e = hipEventRecord(r.a, st);
     if (e != hipSuccess) return e;
     e = f();
     if (e != hipSuccess) return e;
-    return hipEventRecord(r.b, st_);
+    return hipEventRecord(r.b, st);
   }
   // Call after the stream has been synchronised.
   hipError_t collect() {
@@ -374,6 +379,34 @@ class PhaseTimer {
   uint32_t mask_;
   hipStream_t st_;
   std::vector<Rec> recs_;
+};
+
+// The second stream of a device (created once, default priority): Grams
+// computed ahead run there beside the steps of the previous batch.
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (streams[dev] == nullptr &&
+      hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
+// The two events of one call's hand-offs between the streams.
+struct StreamEvents {
+  hipEvent_t issued = nullptr, ready = nullptr;
+  hipError_t create() {
+    hipError_t e = hipEventCreateWithFlags(&issued, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    return e;
+  }
+  ~StreamEvents() {
+    if (issued != nullptr) (void)hipEventDestroy(issued);
+    if (ready != nullptr) (void)hipEventDestroy(ready);
+  }
 };
 
 // Layout of the Gram partials a launch of `plan` writes for the dense M.
@@ -460,18 +493,18 @@ hipError_t mat_gram_steps(const Mat& M, const int32_t* idx, int m, int nsteps, d
                           double shift, double* G, double* partials, hipStream_t st,
                           PhaseTimer* timer) {
   if (M.csr)
-    return timer->run(CABCD_PHASE_GRAM, [&] {
+    return timer->run_on(st, CABCD_PHASE_GRAM, [&] {
       return launch_csr_gram_steps(M.C, idx, m, nsteps, scale, shift, true, G, st);
     });
   const GramPlan plan = plan_for(M, m);
-  hipError_t e = timer->run(CABCD_PHASE_GRAM, [&] {
+  hipError_t e = timer->run_on(st, CABCD_PHASE_GRAM, [&] {
     return M.lowp() ? launch_gram_lp(plan, M.dtype, M.Q, M.ld, M.cols, idx, m, nullptr, partials,
                                      st, nsteps)
                     : launch_gram_f64(plan, M.X, M.ld, M.cols, idx, m, nullptr, partials, st,
                                       nsteps);
   });
   if (e != hipSuccess) return e;
-  return timer->run(CABCD_PHASE_REDUCE, [&] {
+  return timer->run_on(st, CABCD_PHASE_REDUCE, [&] {
     return launch_gram_reduce(plan, partials, idx, m, scale, shift, true, G, nullptr, st,
                               partial_layout(M, plan), M.lowp() ? M.rs : nullptr, nsteps);
   });
@@ -488,10 +521,12 @@ struct StepBuffers {
   int* split_prep;   // the split Gram's per-matrix numbering of heavy columns
   int* status;
   int32_t* idx;      // kIdxChunkSteps * s * b
-  double* G;         // gram_slots x sb x sb
+  double* G;         // gram_slots x sb x sb (twice when computed ahead)
+  double* G2;        // the second buffer of Grams computed ahead (or G)
   double* Yu;        // sb
   double* delta;     // sb
   double* partials;  // dense Gram partials
+  double* partials2; // the second buffer of the ahead path's partials (or partials)
   double* scratch;   // gemv row-group partials
   double* obj;       // objective scratch
   double* rtmp;      // residual temporary (monitoring)
@@ -506,13 +541,16 @@ size_t layout(Carve& c, StepBuffers& B, const Mat& M, int b, int s, int64_t rtmp
   B.split_prep = c.take<int>(use_split(M, sb) ? csr_split_prepare_ints(M.C) : 1);
   B.status = c.take<int>(1);
   B.idx = c.take<int32_t>((size_t)kIdxChunkSteps * sb);
-  B.G = c.take<double>((size_t)gram_slots(M, sb) * sb * sb);
+  const int slots = gram_slots(M, sb);
+  const int nbuf = slots > 1 ? 2 : 1;   // Grams computed ahead: the next batch's buffer too
+  B.G = c.take<double>((size_t)nbuf * slots * sb * sb);
+  B.G2 = B.G + (size_t)(nbuf - 1) * slots * sb * sb;
   B.Yu = c.take<double>(sb);
   B.delta = c.take<double>(sb);
-  const int slots = gram_slots(M, sb);
-  B.partials = c.take<double>(std::max(
-      max_partials(M, sb),
-      M.csr || slots == 1 ? (size_t)0 : (size_t)slots * gram_partial_doubles(plan_for(M, sb))));
+  const size_t ahead_p =
+      M.csr || slots == 1 ? (size_t)0 : (size_t)slots * gram_partial_doubles(plan_for(M, sb));
+  B.partials = c.take<double>(std::max(max_partials(M, sb), nbuf * ahead_p));
+  B.partials2 = B.partials + (nbuf - 1) * ahead_p;
   B.scratch = c.take<double>(mat_scratch_doubles(M, sb));
   B.obj = c.take<double>(objective_scratch_doubles(0, 0));
   B.rtmp = c.take<double>(std::max<int64_t>(rtmp_len, 1));
@@ -641,8 +679,8 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   bool split = use_split(M, sb_full);
   CsrSplitInfo sinfo{};
   int ksplit = 0;
-  double* split_d = nullptr;
-  int* split_i = nullptr;
+  double* split_d[2] = {nullptr, nullptr};   // the scratch of two launches (see the loop)
+  int* split_i[2] = {nullptr, nullptr};
   if (split) {
     HIP_TRY(csr_split_prepare(M.C, B.split_prep, &sinfo, st));
   }
@@ -661,7 +699,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       return dmax * sizeof(double) + imax * sizeof(int) + 512;
     };
     while (ksplit > 1 && bytes_of(ksplit) > kSplitBudget) ksplit /= 2;
-    const size_t sbytes = bytes_of(ksplit);
+    const size_t sbytes = (bytes_of(ksplit) + 255) & ~(size_t)255;   // one launch's
     void* sp = nullptr;
     if (sbytes > kSplitBudget) {
       split = false;   // rows too long for the per-step entry tables
@@ -669,15 +707,17 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       // the split scratch starts at the first 256-byte boundary past `need`
       const uintptr_t w0 = reinterpret_cast<uintptr_t>(o.workspace);
       const uintptr_t s0 = (w0 + need + 255) & ~(uintptr_t)255;
-      if (s0 + sbytes <= w0 + o.workspace_bytes) sp = reinterpret_cast<void*>(s0);
+      if (s0 + 2 * sbytes <= w0 + o.workspace_bytes) sp = reinterpret_cast<void*>(s0);
       split = sp != nullptr;
     } else {
-      e = pool_get(sbytes, &sp, 1);
+      e = pool_get(2 * sbytes, &sp, 1);
       if (e != CABCD_OK) return e;
     }
     if (split) {
-      split_d = static_cast<double*>(sp);
-      split_i = reinterpret_cast<int*>(split_d + dmax);
+      for (int q = 0; q < 2; ++q) {
+        split_d[q] = reinterpret_cast<double*>(static_cast<char*>(sp) + q * sbytes);
+        split_i[q] = reinterpret_cast<int*>(split_d[q] + dmax);
+      }
     }
   }
 
@@ -729,10 +769,56 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   while (bp < b) bp *= 2;
   const bool pre_inv = K > 1 && bp <= 16 && (int64_t)s * bp <= 512;
   int ahead = 0, gslot = 0;                       // precomputed Grams left, next slot
-  int split_nst = 0;                              // steps of the last split launch
+  int split_nst = 0;                              // steps of the current batch
   int64_t h = 0, k = 0, slot = 0;
   int64_t chunk_begin = -1, chunk_end = -1;
   const int64_t chunk_iters = kIdxChunkSteps * (int64_t)s;
+
+  // Grams computed ahead come in batches of up to K (ksplit) full outer steps.
+  // While the steps of one batch run on the call's stream, the next batch's
+  // Grams (whose indices are at hand) are computed on a second stream into
+  // the other of two buffers; the first step of that batch waits for them.
+  double* const Gbuf[2] = {B.G, B.G2};
+  double* const Pbuf[2] = {B.partials, B.partials2};
+  int cur = 0;                                    // buffer of the current batch
+  bool pf_ready = false;                          // next batch launched on the side stream
+  int64_t pf_h = -1;
+  int pf_nst = 0;
+  hipStream_t side = nullptr;
+  StreamEvents ev;
+  if (K > 1) {
+    side = side_stream();
+    if (side == nullptr || ev.create() != hipSuccess) {
+      set_error("creating the second stream or its events failed");
+      return CABCD_EHIP;
+    }
+  }
+  // steps of the batch starting at iteration hb whose indices are at hand (0: none)
+  auto batch_steps = [&](int64_t hb) -> int {
+    int64_t avail = (H - hb) / s;
+    if (o.explicit_idx == nullptr) avail = std::min(avail, (chunk_end - hb) / s);
+    return (int)std::min<int64_t>(split ? ksplit : K, std::max<int64_t>(avail, 0));
+  };
+  auto launch_batch = [&](int64_t hb, int nst, int buf, hipStream_t bs) -> hipError_t {
+    const int32_t* ib = o.explicit_idx != nullptr ? o.explicit_idx + hb * b
+                                                  : B.idx + (hb - chunk_begin) * b;
+    const int mb = s * b;
+    hipError_t he;
+    if (split)
+      he = timer.run_on(bs, CABCD_PHASE_GRAM, [&] {
+        return launch_csr_gram_split(M.C, sinfo, ib, mb, nst, scale, shift, true, Gbuf[buf],
+                                     split_d[buf], split_i[buf], bs);
+      });
+    else
+      he = mat_gram_steps(M, ib, mb, nst, scale, shift, Gbuf[buf], Pbuf[buf], bs, &timer);
+    if (he != hipSuccess) return he;
+    // their diagonal blocks inverted together, off the solves' chains
+    if (pre_inv)
+      he = timer.run_on(bs, CABCD_PHASE_SOLVE, [&] {
+        return launch_invert_diag(Gbuf[buf], nst, mb, b, B.status, bs);
+      });
+    return he;
+  };
   while (h < H) {
     const int sk = (int)std::min<int64_t>(s, H - h);
     const int m = sk * b;
@@ -754,28 +840,32 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     const bool from_ahead = K > 1 && sk == s;
     if (from_ahead) {
       if (ahead == 0) {
-        // the Grams of the next full outer steps whose indices are at hand
-        int64_t avail = (H - h) / s;
-        if (o.explicit_idx == nullptr) avail = std::min(avail, (chunk_end - h) / s);
-        const int nst =
-            (int)std::min<int64_t>(split ? ksplit : K, std::max<int64_t>(avail, 1));
-        if (split)
-          HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
-            return launch_csr_gram_split(M.C, sinfo, idx, m, nst, scale, shift, true, B.G,
-                                         split_d, split_i, st);
-          }));
-        else
-          HIP_TRY(mat_gram_steps(M, idx, m, nst, scale, shift, B.G, B.partials, st, &timer));
-        split_nst = nst;
-        // their diagonal blocks inverted together, off the solves' chains
-        if (pre_inv)
-          HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] {
-            return launch_invert_diag(B.G, nst, m, b, B.status, st);
-          }));
-        ahead = nst;
+        if (pf_ready && pf_h == h) {   // computed on the side stream
+          HIP_TRY(hipStreamWaitEvent(st, ev.ready, 0));
+          cur ^= 1;
+          ahead = pf_nst;
+          pf_ready = false;
+        } else {                       // computed here
+          ahead = std::max(batch_steps(h), 1);
+          HIP_TRY(launch_batch(h, ahead, cur, st));
+        }
+        split_nst = ahead;
         gslot = 0;
+        // the next batch on the side stream, after everything enqueued so far
+        // (the previous batch's steps used its buffer)
+        const int64_t h2 = h + (int64_t)ahead * s;
+        const int n2 = batch_steps(h2);
+        if (n2 > 0) {
+          HIP_TRY(hipEventRecord(ev.issued, st));
+          HIP_TRY(hipStreamWaitEvent(side, ev.issued, 0));
+          HIP_TRY(launch_batch(h2, n2, cur ^ 1, side));
+          HIP_TRY(hipEventRecord(ev.ready, side));
+          pf_ready = true;
+          pf_h = h2;
+          pf_nst = n2;
+        }
       }
-      Gk = B.G + (size_t)gslot * m * m;
+      Gk = Gbuf[cur] + (size_t)gslot * m * m;
       ++gslot;
       --ahead;
       HIP_TRY(timer.run(CABCD_PHASE_YU, [&] {
@@ -806,7 +896,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       // from its panel and sorted lists
       if (from_ahead && split)
         return launch_csr_update_split(M.C, sinfo, idx, m, split_nst, gslot - 1, B.delta, gamma,
-                                       comp, split_d, split_i, st);
+                                       comp, split_d[cur], split_i[cur], st);
       return mat_scatter(M, idx, m, B.delta, gamma, nullptr, 0.0, true, comp, B.scratch, st);
     }));
     h += sk;
@@ -832,6 +922,9 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     }
   }
   if (o.iters_done != nullptr) *o.iters_done = h;
+  // a batch computed ahead and not used (the run stopped early) still ends
+  // before the call's stream moves on
+  if (pf_ready) HIP_TRY(hipStreamWaitEvent(st, ev.ready, 0));
   const cabcd_status fs = finish(st, B.status, (o.flags & CABCD_FLAG_ASYNC) != 0);
   HIP_TRY(timer.collect());
   return fs;
