@@ -21,9 +21,14 @@
  * structs whose pointer fields are device pointers.
  *
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All work is
- * enqueued on it in order.  Unless CABCD_FLAG_ASYNC is set, a call
- * synchronises the stream before returning so that device-detected errors
- * (non-SPD block, non-finite values) can be returned.
+ * enqueued on it in order; the one-problem drivers also compute the Grams of
+ * the next batch of outer steps on a second stream of the library (one per
+ * device, default priority), joined back to `stream` through events before
+ * those steps and before the call returns, so the call behaves as if all of
+ * its work ran on `stream` (also under graph capture).  Unless
+ * CABCD_FLAG_ASYNC is set, a call synchronises the stream before returning so
+ * that device-detected errors (non-SPD block, non-finite values) can be
+ * returned.
  *
  * Workspace.  Scratch memory is taken from a per-device pool that the library
  * grows with hipMalloc and keeps until process exit, unless opts->workspace is
@@ -223,6 +228,11 @@ cabcd_status cabcd_gram_noalloc(const cabcd_matrix* A, const int32_t* idx, int32
  * opts->resid_every to recompute r exactly every few outer steps) or CSR F64.
  * 1 <= b <= min(d, 32), s >= 1, s*b <= 512 dense / 1024 CSR (512 when
  * b > 16), H >= 0, lambda > 0; a larger s*b is CABCD_EUNSUPPORTED.
+ * Results are reproducible bit for bit for dense storage.  For CSR, the
+ * outer steps of 256 to 512 gathered rows whose Grams are computed ahead
+ * update r (w for the dual) with one writer per column and are reproducible
+ * too; other CSR steps add their update with FP64 atomics, whose order varies
+ * between runs.
  */
 cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lambda,
                               int32_t b, int32_t s, int64_t H, uint64_t seed,
