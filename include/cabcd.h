@@ -231,8 +231,8 @@ cabcd_status cabcd_gram_noalloc(const cabcd_matrix* A, const int32_t* idx, int32
  * Results are reproducible bit for bit for dense storage.  For CSR, the
  * outer steps of 256 to 512 gathered rows whose Grams are computed ahead
  * update r (w for the dual) with one writer per column and are reproducible
- * too; other CSR steps add their update with FP64 atomics, whose order varies
- * between runs.
+ * too, also when the run is split into several calls (opts->h0); other CSR
+ * steps add their update with FP64 atomics, whose order varies between runs.
  */
 cabcd_status cabcd_primal_bcd(const cabcd_matrix* X, const double* y, double lambda,
                               int32_t b, int32_t s, int64_t H, uint64_t seed,

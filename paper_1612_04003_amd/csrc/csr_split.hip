@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kT = 256;               // threads of the helper kernels
 constexpr int kHeavyMax = 512;        // panel columns at most
+constexpr int kPanelSteps = 16;       // steps per launch the panel slabs are sized for
 constexpr int kHist = 8192;           // column-count histogram bins (counts capped)
 constexpr int kScanChunk = 1024;      // columns per workgroup of the slot numbering
 constexpr int64_t kSampleRows = 2048; // rows whose columns estimate the popularity
@@ -840,13 +841,16 @@ SplitLayout csr_split_layout(const CsrSplitInfo& info, int64_t cols, int m, int 
   L.lcap = (int64_t)m * info.maxlight;
   L.nblk = (int)((cols + kScanCols - 1) / kScanCols);
   L.cs = (int64_t)L.nblk * kScanCols;
-  // the panel Gram: the nsteps Grams of a launch (their 256-row parts) with
-  // enough column slabs to give every CU a workgroup
+  // the panel Gram: the nsteps Grams of a launch (their 256-row parts), in
+  // column slabs sized so that a launch of kPanelSteps steps gives every CU a
+  // workgroup.  The slabs (and so every sum's order) do not depend on how many
+  // steps a launch actually takes: a run gives the same result however its
+  // steps are batched or split between calls.
   const int sets = m > 256 ? 2 + big_cross_steps(m) : 1;
   L.plan = plan_gram_f64(std::min(m, 256), std::max(L.hp, 16));
   const int kt = L.plan.kt;
   const int64_t width = std::max(L.hp, 16);
-  int want = std::max(1, (256 + nsteps * sets - 1) / (nsteps * sets));
+  const int want = std::max(1, (256 + kPanelSteps * sets - 1) / (kPanelSteps * sets));
   int64_t chunk = (width + want - 1) / want;
   chunk = std::max<int64_t>(kt, (chunk + kt - 1) / kt * kt);
   L.plan.chunk = chunk;

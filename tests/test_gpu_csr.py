@@ -207,16 +207,22 @@ def test_csr_steps_cross_index_chunks(gpu_lib):
 def test_csr_split_steps_are_reproducible(gpu_lib):
     """Outer steps whose Grams come from the split launch update the companion
     vector with one writer per column and fixed summation orders: two runs
-    give bitwise the same alpha and w (and the oracle's to 1e-10)."""
+    give bitwise the same alpha and w (and the oracle's to 1e-10), and so does
+    the same run split into two calls (3 + 2 outer steps, resumed with h0 and
+    the state passed on), whose Grams are computed in other batches."""
     rows, cols = 3000, 20000
     rowptr, colidx, vals, y, _ = synth.zipf_csr_ridge(rows, cols, 60, 78)
     S = scipy.sparse.csr_matrix((vals, colidx, rowptr), shape=(rows, cols))
     XT = gpu_lib.CSR.from_scipy(S, DEV)
     s, b = 32, 16
     H = 5 * s                  # five full outer steps of 512 gathered rows
-    runs = [gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), 1e-3, b, s, H, 23)
-            for _ in range(2)]
+    yd = torch.tensor(y, device=DEV)
+    runs = [gpu_lib.dual_bcd(XT, yd, 1e-3, b, s, H, 23) for _ in range(2)]
     assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    a2, w2 = gpu_lib.dual_bcd(XT, yd, 1e-3, b, s, 3 * s, 23)
+    gpu_lib.dual_bcd(XT, yd, 1e-3, b, s, 2 * s, 23, alpha=a2, w=w2, h0=3 * s,
+                     flags=gpu_lib.FLAG_STATE_VALID)
+    assert torch.equal(a2, runs[0][0]) and torch.equal(w2, runs[0][1])
     ao, wo = bcd.dual_bcd(S.T.tocsc(), y, 1e-3, b, s, H, 23)
     assert _rel(runs[0][0].cpu(), ao) <= 1e-10
     assert _rel(runs[0][1].cpu(), wo) <= 1e-10
