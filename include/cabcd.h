@@ -272,6 +272,18 @@ cabcd_status cabcd_quantize(const double* A, int64_t rows, int64_t cols, int64_t
                             void* stream);
 
 /*
+ * The leading dimension (in elements) to allocate stored codes with, for
+ * cabcd_quantize's Q: cols rounded up to 256 bytes, plus 256 bytes when that
+ * is a multiple of 64 KiB (such strides put the same columns of every
+ * gathered row on the same HBM channels, and the Gram's row gathers stream
+ * about 12 % slower).  Any ldq >= cols works; this one keeps rows on the
+ * 16-byte boundaries the vector and LDS-DMA loads need.  Host only, no
+ * device work.  Returns -1 (and sets the error string) for cols < 1 or an
+ * unknown dtype.
+ */
+int64_t cabcd_quantize_ld(int64_t cols, int32_t dtype);
+
+/*
  * Exact primal residual and objective (Section 5.1.5: the full residual is
  * recomputed occasionally; eq. primal): given A = X (d x n),
  *   r = X^T w - y (n, FP64 accumulation)   and   *f = f(w)  (device scalar).

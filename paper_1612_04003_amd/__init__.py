@@ -107,6 +107,7 @@ def load():
         "cabcd_dual_residual": (I32, [MP, P, P, P, P, P, P]),
         "cabcd_workspace_bytes": (ctypes.c_size_t, [MP, I32, I32]),
         "cabcd_quantize": (I32, [P, I64, I64, I64, I32, P, I64, P, P]),
+        "cabcd_quantize_ld": (I64, [I64, I32]),
         "cabcd_batch_create": (I32, [ctypes.POINTER(Problem), I32, ctypes.POINTER(BatchOpts), P,
                                      ctypes.POINTER(P)]),
         "cabcd_batch_run": (I32, [P, I64, P, ctypes.POINTER(I32)]),
@@ -132,7 +133,8 @@ def exported_symbols():
             "cabcd_dual_bcd", "cabcd_primal_objective", "cabcd_primal_objective_t",
             "cabcd_dual_to_primal", "cabcd_primal_residual", "cabcd_dual_residual",
             "cabcd_workspace_bytes", "cabcd_last_error",
-            "cabcd_version", "cabcd_quantize", "cabcd_batch_create", "cabcd_batch_run",
+            "cabcd_version", "cabcd_quantize", "cabcd_quantize_ld", "cabcd_batch_create",
+            "cabcd_batch_run",
             "cabcd_batch_query", "cabcd_batch_destroy", "cabcd_primal_bcd_batched"]
 
 
@@ -229,26 +231,34 @@ class Quantized:
         return x
 
 
+def quantize_ld(cols, dtype):
+    """cabcd_quantize_ld: the leading dimension (elements) for stored codes."""
+    ld = load().cabcd_quantize_ld(int(cols), int(dtype))
+    if ld < 0:
+        msg = load().cabcd_last_error()
+        raise CabcdError(EINVAL, msg.decode() if msg else "")
+    return ld
+
+
 def quantize(A, dtype):
     """Store the FP64 matrix A (rows x cols) as BF16 or FP8-E4M3 codes.  The
-    codes' rows start on 16-byte boundaries (leading dimension padded with
-    zero codes), which is what the 16-byte loads and the LDS-DMA paths of the
-    kernels need; `codes` is the rows x cols view."""
+    codes' rows start on 16-byte boundaries (leading dimension from
+    quantize_ld, padded with zero codes), which is what the 16-byte loads and
+    the LDS-DMA paths of the kernels need; `codes` is the rows x cols view."""
     if not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.float64:
         raise TypeError("A must be a float64 CUDA (HIP) tensor")
     if A.dim() != 2 or A.stride(1) != 1:
         raise ValueError("A must be 2-D with unit column stride")
     rows, cols = A.shape
+    if dtype not in (BF16, FP8_E4M3):
+        raise ValueError("dtype must be BF16 or FP8_E4M3")
+    ldq = quantize_ld(cols, dtype)
     if dtype == BF16:
-        ldq = -(-cols // 8) * 8
         buf = torch.zeros((rows, ldq), dtype=torch.int16, device=A.device)
         scales = None
-    elif dtype == FP8_E4M3:
-        ldq = -(-cols // 16) * 16
+    else:
         buf = torch.zeros((rows, ldq), dtype=torch.uint8, device=A.device)
         scales = torch.empty(rows, dtype=torch.float32, device=A.device)
-    else:
-        raise ValueError("dtype must be BF16 or FP8_E4M3")
     _check(load().cabcd_quantize(_ptr(A), rows, cols, A.stride(0), dtype, _ptr(buf), ldq,
                                  _ptr(scales), _stream()))
     return Quantized(buf[:, :cols], scales, dtype)

@@ -204,6 +204,10 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   const bool want_u = u != nullptr;
   const gptr<const double> ug = glb(u);
   const bool u_dma = want_u && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  // The tile's u segment in LDS: 16-byte slot 16 q + c holds piece
+  // (EPC / 2) c + q of the segment (the q-th pair of u values of chunk c), so
+  // the Y u threads of the sixteen chunks read a piece from consecutive slots.
+  auto upiece = [](int slot) { return (C::EPC / 2) * (slot & 15) + (slot >> 4); };
   // A tile inside the slab is all DMA; the last tile of a slab that ends
   // inside a tile is filled by a compact loop of ordinary loads (zeros past
   // the end), kept out of line of the DMA path to keep the loop body small.
@@ -216,11 +220,11 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
         __builtin_amdgcn_global_load_lds((glb_vptr)(src[i] + k0 * C::ES + cof[i]),
                                          (lds_vptr)(T + (C::DMA_PER_WAVE * W + i) * 1024), 16,
                                          0, 0);
-      if (want_u && W == 7) {   // the tile's u segment, unswizzled after the rows
+      if (want_u && W == 7) {   // the tile's u segment after the rows, pieces transposed
 #pragma unroll
         for (int j = 0; j < C::UDMA; ++j) {
           uint8_t* dst = T + C::TILE + j * 1024;
-          const int64_t ku = k0 + 2 * (64 * j + lane);
+          const int64_t ku = k0 + 2 * upiece(64 * j + lane);
           if (u_dma) {
             __builtin_amdgcn_global_load_lds((glb_vptr)(ug + ku), (lds_vptr)dst, 16, 0, 0);
           } else {
@@ -251,7 +255,7 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
     if (want_u && W == 7) {
 #pragma clang loop unroll(disable)
       for (int j = 0; j < C::UDMA; ++j) {
-        const int64_t ku = k0 + 2 * (64 * j + lane);
+        const int64_t ku = k0 + 2 * upiece(64 * j + lane);
         double2 v;
         v.x = ku < k_end ? ug[ku] : 0.0;
         v.y = ku + 1 < k_end ? ug[ku + 1] : 0.0;
@@ -306,10 +310,16 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
       }
     }
     if (want_u) {
-      const double* us = reinterpret_cast<const double*>(tile + C::TILE) + yc * C::EPC;
+      // the 16-byte pieces of chunk yc sit 256 bytes apart, so the sixteen
+      // chunks' reads of one piece fall in distinct banks
       double ub[C::EPC];
 #pragma unroll
-      for (int e = 0; e < C::EPC; ++e) ub[e] = us[e];
+      for (int q = 0; q < C::EPC / 2; ++q) {
+        const double2 v =
+            *reinterpret_cast<const double2*>(tile + C::TILE + 16 * (16 * q + yc));
+        ub[2 * q] = v.x;
+        ub[2 * q + 1] = v.y;
+      }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int r = yr0 + 32 * j;
