@@ -188,12 +188,23 @@ def measured_traffic(path, key):
         return None
 
 
+def padded(cabcd, X):
+    """X (rows x cols, FP64) copied into rows leading_dim(cols) apart: the same
+    matrix in the layout the library recommends (a 2 MiB row stride, as
+    contiguous rows of 2^18 columns have, sends the gathered rows' same
+    columns to the same HBM channels)."""
+    Y = cabcd.empty_dense(X.shape[0], X.shape[1], X.device)
+    Y.copy_(X)
+    return Y
+
+
 def headline(args, cabcd, torch, synth):
     dev = "cuda:0"
     d, n, b, s, lam = args.d, args.n, args.b, args.s, args.lam
     sb = s * b
     log(f"generating X ({d} x {n}, FP64) on the GPU")
     X, y, _ = synth.spectral_ridge(d, n, 1001, device=dev)
+    X = padded(cabcd, X)
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     gram_only = 1 << cabcd.PHASES.index("gram")
@@ -764,6 +775,7 @@ def main():
     if args.only_extra:
         log(f"generating X ({args.d} x {args.n}, FP64) on the GPU")
         X, y, _ = synth.spectral_ridge(args.d, args.n, 1001, device="cuda:0")
+        X = padded(cabcd, X)
         torch.cuda.synchronize()
         print(json.dumps({"extra": extra_records(args, cabcd, torch, synth, X, y)}), flush=True)
         return

@@ -272,16 +272,17 @@ cabcd_status cabcd_quantize(const double* A, int64_t rows, int64_t cols, int64_t
                             void* stream);
 
 /*
- * The leading dimension (in elements) to allocate stored codes with, for
- * cabcd_quantize's Q: cols rounded up to 256 bytes, plus 256 bytes when that
- * is a multiple of 64 KiB (such strides put the same columns of every
- * gathered row on the same HBM channels, and the Gram's row gathers stream
- * about 12 % slower).  Any ldq >= cols works; this one keeps rows on the
- * 16-byte boundaries the vector and LDS-DMA loads need.  Host only, no
- * device work.  Returns -1 (and sets the error string) for cols < 1 or an
- * unknown dtype.
+ * The leading dimension (in elements) to allocate a dense matrix of `cols`
+ * columns with, for any storage (CABCD_F64, or cabcd_quantize's Q for
+ * CABCD_BF16 / CABCD_FP8_E4M3): the row rounded up to 256 bytes, plus 256
+ * bytes when that is a multiple of 64 KiB.  Such strides put the same columns
+ * of every gathered row on the same HBM channels: the Gram's row gathers
+ * stream about 12 % slower at a 2 MiB stride.  Any ld >= cols works; this one
+ * also keeps rows on the 16-byte boundaries the vector and LDS-DMA loads need.
+ * Host only, no device work.  Returns -1 (and sets the error string) for
+ * cols < 1 or an unknown dtype.
  */
-int64_t cabcd_quantize_ld(int64_t cols, int32_t dtype);
+int64_t cabcd_leading_dim(int64_t cols, int32_t dtype);
 
 /*
  * Exact primal residual and objective (Section 5.1.5: the full residual is

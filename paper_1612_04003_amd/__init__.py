@@ -107,7 +107,7 @@ def load():
         "cabcd_dual_residual": (I32, [MP, P, P, P, P, P, P]),
         "cabcd_workspace_bytes": (ctypes.c_size_t, [MP, I32, I32]),
         "cabcd_quantize": (I32, [P, I64, I64, I64, I32, P, I64, P, P]),
-        "cabcd_quantize_ld": (I64, [I64, I32]),
+        "cabcd_leading_dim": (I64, [I64, I32]),
         "cabcd_batch_create": (I32, [ctypes.POINTER(Problem), I32, ctypes.POINTER(BatchOpts), P,
                                      ctypes.POINTER(P)]),
         "cabcd_batch_run": (I32, [P, I64, P, ctypes.POINTER(I32)]),
@@ -133,7 +133,7 @@ def exported_symbols():
             "cabcd_dual_bcd", "cabcd_primal_objective", "cabcd_primal_objective_t",
             "cabcd_dual_to_primal", "cabcd_primal_residual", "cabcd_dual_residual",
             "cabcd_workspace_bytes", "cabcd_last_error",
-            "cabcd_version", "cabcd_quantize", "cabcd_quantize_ld", "cabcd_batch_create",
+            "cabcd_version", "cabcd_quantize", "cabcd_leading_dim", "cabcd_batch_create",
             "cabcd_batch_run",
             "cabcd_batch_query", "cabcd_batch_destroy", "cabcd_primal_bcd_batched"]
 
@@ -221,29 +221,41 @@ class Quantized:
         self.device = codes.device
 
     def dequantize(self):
-        """X^ in FP64 (exact), computed with torch for tests and baselines."""
-        if self.dtype == BF16:
-            x = self.codes.view(torch.bfloat16).to(torch.float64)
-        else:
-            x = self.codes.view(torch.float8_e4m3fn).to(torch.float64)
-        if self.scales is not None:
-            x = x * self.scales.to(torch.float64)[:, None]
-        return x
+        """X^ in FP64 (exact), computed with torch for tests and baselines; its
+        rows are leading_dim(cols, F64) apart."""
+        rows, cols = self.shape
+        out = empty_dense(rows, cols, self.device)
+        view = torch.bfloat16 if self.dtype == BF16 else torch.float8_e4m3fn
+        for r0 in range(0, rows, 1024):   # row blocks keep the FP64 temporaries small
+            r1 = min(rows, r0 + 1024)
+            x = self.codes[r0:r1].view(view).to(torch.float64)
+            if self.scales is not None:
+                x = x * self.scales[r0:r1].to(torch.float64)[:, None]
+            out[r0:r1] = x
+        return out
 
 
-def quantize_ld(cols, dtype):
-    """cabcd_quantize_ld: the leading dimension (elements) for stored codes."""
-    ld = load().cabcd_quantize_ld(int(cols), int(dtype))
+def leading_dim(cols, dtype):
+    """cabcd_leading_dim: the leading dimension (elements) to allocate a dense
+    matrix of `cols` columns with (F64, BF16 or FP8_E4M3)."""
+    ld = load().cabcd_leading_dim(int(cols), int(dtype))
     if ld < 0:
         msg = load().cabcd_last_error()
         raise CabcdError(EINVAL, msg.decode() if msg else "")
     return ld
 
 
+def empty_dense(rows, cols, device="cuda"):
+    """An uninitialised rows x cols float64 matrix whose rows are
+    leading_dim(cols, F64) apart (the view of a padded buffer)."""
+    ld = leading_dim(cols, F64)
+    return torch.empty((rows, ld), dtype=torch.float64, device=device)[:, :cols]
+
+
 def quantize(A, dtype):
     """Store the FP64 matrix A (rows x cols) as BF16 or FP8-E4M3 codes.  The
     codes' rows start on 16-byte boundaries (leading dimension from
-    quantize_ld, padded with zero codes), which is what the 16-byte loads and
+    leading_dim, padded with zero codes), which is what the 16-byte loads and
     the LDS-DMA paths of the kernels need; `codes` is the rows x cols view."""
     if not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.float64:
         raise TypeError("A must be a float64 CUDA (HIP) tensor")
@@ -252,7 +264,7 @@ def quantize(A, dtype):
     rows, cols = A.shape
     if dtype not in (BF16, FP8_E4M3):
         raise ValueError("dtype must be BF16 or FP8_E4M3")
-    ldq = quantize_ld(cols, dtype)
+    ldq = leading_dim(cols, dtype)
     if dtype == BF16:
         buf = torch.zeros((rows, ldq), dtype=torch.int16, device=A.device)
         scales = None

@@ -1193,13 +1193,13 @@ cabcd_status cabcd_quantize(const double* A, int64_t rows, int64_t cols, int64_t
   return CABCD_OK;
 }
 
-int64_t cabcd_quantize_ld(int64_t cols, int32_t dtype) {
+int64_t cabcd_leading_dim(int64_t cols, int32_t dtype) {
   clear_error();
-  if (cols < 1 || (dtype != CABCD_BF16 && dtype != CABCD_FP8_E4M3)) {
-    set_error("cabcd_quantize_ld: need cols >= 1 and dtype CABCD_BF16 or CABCD_FP8_E4M3");
+  if (cols < 1 || (dtype != CABCD_F64 && dtype != CABCD_BF16 && dtype != CABCD_FP8_E4M3)) {
+    set_error("cabcd_leading_dim: need cols >= 1 and dtype CABCD_F64, CABCD_BF16 or CABCD_FP8_E4M3");
     return -1;
   }
-  const int64_t es = dtype == CABCD_BF16 ? 2 : 1;
+  const int64_t es = dtype == CABCD_F64 ? 8 : dtype == CABCD_BF16 ? 2 : 1;
   int64_t bytes = (cols * es + 255) / 256 * 256;
   // A row stride that is a multiple of 64 KiB sends the same columns of the
   // gathered rows to the same HBM channels: measured on 256 gathered rows of

@@ -208,17 +208,18 @@ def test_residual_entry_point_errors():
     assert lib.cabcd_dual_residual(ctypes.byref(M), p, p, p, p, p, None) == cabcd.EINVAL
 
 
-@pytest.mark.parametrize("dtype,es", [(cabcd.BF16, 2), (cabcd.FP8_E4M3, 1)])
-def test_quantize_leading_dimension(dtype, es):
-    """cabcd_quantize_ld (host only): at least cols, rows on 256-byte
+@pytest.mark.parametrize("dtype,es", [(cabcd.F64, 8), (cabcd.BF16, 2), (cabcd.FP8_E4M3, 1)])
+def test_leading_dimension(dtype, es):
+    """cabcd_leading_dim (host only): at least cols, rows on 256-byte
     boundaries, never a multiple of 64 KiB, at most 511 bytes of padding."""
-    for cols in (1, 7, 127, 128, 4096, 32768, 65536, 100000, 1 << 20, (1 << 20) + 3):
-        ld = cabcd.quantize_ld(cols, dtype)
+    for cols in (1, 7, 127, 128, 4096, 8192, 32768, 65536, 100000, 1 << 18, 1 << 20,
+                 (1 << 20) + 3):
+        ld = cabcd.leading_dim(cols, dtype)
         assert ld >= cols
         assert (ld * es) % 256 == 0 and (ld * es) % 65536 != 0
         assert ld * es - cols * es < 512
-    assert cabcd.quantize_ld(1 << 20, dtype) * es == (1 << 20) * es + 256
+    assert cabcd.leading_dim(1 << 20, dtype) * es == (1 << 20) * es + 256
     for bad in ((0, dtype), (-5, dtype), (10, 7)):
         with pytest.raises(cabcd.CabcdError) as e:
-            cabcd.quantize_ld(*bad)
+            cabcd.leading_dim(*bad)
         assert e.value.status == cabcd.EINVAL
