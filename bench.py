@@ -10,8 +10,9 @@ deferred w / residual updates.  Inputs are resident in HBM before timing.
 
 value = algorithmic Gram flops of the timed steps (n*sb*(sb+1) per step: the
 lower triangle with its diagonal) / wall time of the whole steps, in TFLOP/s.
-roofline: the Gram kernel alone, timed with HIP events on the stream it runs
-on.  cpu_baseline: the FP64 oracle on a bounded number of outer steps of the
+roofline: the Gram kernel (which at s*b = 256 also applies the previous
+step's deferred residual update to the columns it reads), timed with HIP
+events on the stream it runs on.  cpu_baseline: the FP64 oracle on a bounded number of outer steps of the
 same problem on the host.
 
 time_to_tol: wall time from the first s-step until a monitor point (every 4
@@ -228,9 +229,16 @@ def headline(args, cabcd, torch, synth):
         achieved = ybytes / (gram_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
-    roof["kernel"] = ("gram_f64_dma16_kernel" if sb > 128 and n % 2 == 0 else
+    # at s b = 256 on LDS-DMA rows the Gram kernel also applies the previous
+    # step's companion update (all steps but the first of the timed call):
+    # its algorithmic bytes are both steps' gathered rows and r read and written
+    folded = sb == 256 and n % 2 == 0
+    roof["kernel"] = ("gram_f64_dma16_upd_kernel<1>" if folded else
+                      "gram_f64_dma16_kernel" if sb > 128 and n % 2 == 0 else
                       "gram_f64_kernel<16,2>" if sb > 128 else "gram_f64_kernel")
-    roof["per_launch"] = {"flops": gram_flops, "bytes": ybytes, "ms": round(gram_ms, 4)}
+    roof["per_launch"] = {"flops": gram_flops,
+                          "bytes": 2 * ybytes + 16 * n if folded else ybytes,
+                          "ms": round(gram_ms, 4)}
     out = {
         "metric": "CA-BCD Gram TFLOP/s (% peak) + time-to-1e-6 rel obj error, FP64 vs mixed",
         "value": round(value, 3),

@@ -768,6 +768,19 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   int bp = 1;
   while (bp < b) bp *= 2;
   const bool pre_inv = K > 1 && bp <= 16 && (int64_t)s * bp <= 512;
+  // The dense 256-row Gram can apply the previous step's companion update on
+  // its way (one pass over both steps' rows, the update's traffic beside the
+  // matrix cores' work instead of a pass of its own): a full step leaves its
+  // update pending when the next step is a full one with nothing in between
+  // that reads the companion (check, monitor point, exact recomputation) and
+  // keeps its indices in place.  Every such step's update runs through that
+  // device code, folded or alone, so a column's rounding does not depend on
+  // how a run is split into calls.
+  const GramPlan fplan = plan_for(M, kGramRows);
+  const bool fuse_kind = K == 1 && !M.csr && !M.lowp() && (int64_t)s * b == kGramRows &&
+                         gram_f64_takes_update(fplan, M.X, M.ld, kGramRows);
+  bool pending = false;
+  const int32_t* pend_idx = nullptr;
   int ahead = 0, gslot = 0;                       // precomputed Grams left, next slot
   int split_nst = 0;                              // steps of the current batch
   int64_t h = 0, k = 0, slot = 0;
@@ -871,6 +884,16 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       HIP_TRY(timer.run(CABCD_PHASE_YU, [&] {
         return mat_rows_dot(M, idx, m, comp, B.Yu, B.scratch, st);
       }));
+    } else if (pending) {
+      HIP_TRY(timer.run(CABCD_PHASE_GRAM, [&] {
+        return launch_gram_f64_upd(fplan, M.X, M.ld, M.cols, idx, m, B.partials,
+                                   D16Upd{pend_idx, B.delta, gamma, comp}, st);
+      }));
+      HIP_TRY(timer.run(CABCD_PHASE_REDUCE, [&] {
+        return launch_gram_reduce(fplan, B.partials, idx, m, scale, shift, true, B.G, B.Yu, st,
+                                  partial_layout(M, fplan), nullptr);
+      }));
+      pending = false;
     } else {
       HIP_TRY(
           mat_gram(M, idx, m, comp, scale, shift, true, B.G, B.Yu, B.partials, st, &timer));
@@ -897,6 +920,19 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
       if (from_ahead && split)
         return launch_csr_update_split(M.C, sinfo, idx, m, split_nst, gslot - 1, B.delta, gamma,
                                        comp, split_d[cur], split_i[cur], st);
+      if (fuse_kind && m == kGramRows) {
+        const int64_t h1 = h + sk, k1 = k + 1;
+        const bool reads_comp =
+            (o.resid_every > 0 && k1 % o.resid_every == 0) ||
+            (o.monitor_every > 0 && k1 % o.monitor_every == 0 && slot < o.trace_len) ||
+            (checks && k1 % o.check_every == 0);
+        if (H - h1 >= s && !reads_comp && (o.explicit_idx != nullptr || h1 < chunk_end)) {
+          pending = true;
+          pend_idx = idx;
+          return hipSuccess;
+        }
+        return launch_update_f64(fplan, M.X, M.ld, M.cols, D16Upd{idx, B.delta, gamma, comp}, st);
+      }
       return mat_scatter(M, idx, m, B.delta, gamma, nullptr, 0.0, true, comp, B.scratch, st);
     }));
     h += sk;

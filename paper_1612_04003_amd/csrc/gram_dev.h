@@ -552,7 +552,39 @@ struct D16 {
   static constexpr int TILE = SBP * KT + KT;         // doubles per buffer: rows, then u
   static constexpr int DMA_PER_WAVE = SBP * CH / THREADS;   // 4 instructions
   static constexpr int LDS = 2 * TILE;
+  // With the previous step's companion update folded in: two more buffers
+  // for the previous step's rows (and the tile's old companion entries), then
+  // gamma * delta of the previous step.
+  static constexpr int YT = SBP * KT + KT;           // doubles per update buffer
+  static constexpr int YOFF = 2 * TILE;
+  static constexpr int DOFF = 2 * TILE + 2 * YT;
+  static constexpr int LDS_UPD = DOFF + SBP;
 };
+
+
+// x of the lane N places along in the lane's row of sixteen (DPP row_ror),
+// as two 32-bit moves
+template <int N>
+__device__ __forceinline__ double d16_ror(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x120 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// The sum over a row of sixteen lanes, in every lane of the row.
+__device__ __forceinline__ double d16_row_sum(double x) {
+  x += d16_ror<8>(x);
+  x += d16_ror<4>(x);
+  x += d16_ror<2>(x);
+  x += d16_ror<1>(x);
+  return x;
+}
+// x of lane l (the same l in every lane) in every lane.
+__device__ __forceinline__ double d16_read_lane(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  return __hiloint2double(__builtin_amdgcn_readlane((int)(b >> 32), l),
+                          __builtin_amdgcn_readlane((int)b, l));
+}
 
 // Chunk swizzle of row r: the sixteen rows of a fragment read land on
 // distinct banks (8 chunks a row: (r >> 1) & 7; 16 chunks a row: r & 15).
@@ -561,11 +593,26 @@ __device__ __forceinline__ int d16_swz(int r) { return D16::CH == 8 ? (r >> 1) &
 // The whole slab for wave W (block rows W and 15 - W); gram_slab_dma16 picks
 // the instantiation once, so each wave's tile loop is one straight-line path
 // for the register allocator.
-template <int W>
+// MODE 0: the Gram slab (and Y u with u given).  MODE 1: the same, with the
+// previous step's companion update applied to the slab's columns first; Y u
+// then uses the updated companion (u is ignored).  MODE 2: the update alone
+// (the last step of a call, or one followed by a check), by the same code, so
+// a column's update has the same rounding whichever way it runs.
+//
+// The update of tile t's 16 columns: wave W sums column pair W over the 256
+// rows (lane l: rows l + 64 j, then a butterfly over the wave, lane 0's total
+// kept), adds the old entries, writes the companion and, in MODE 1, the
+// tile's u slot.  In MODE 1 it runs one tile ahead of the Gram (tile t + 1
+// during tile t), so the end-of-tile barrier publishes the u slot; the
+// previous step's rows are DMA'd two tiles ahead, their chunks swizzled as
+// the Gram's tiles are ((r >> 1) & 7), so the column-pair reads of sixteen
+// consecutive rows fall in distinct banks.
+template <int W, int MODE>
 __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t ld,
                                          int64_t k_begin, int64_t k_end, const int32_t* idx,
                                          int m, const double* __restrict__ u,
-                                         double* __restrict__ part, double* lds) {
+                                         double* __restrict__ part, double* lds,
+                                         const D16Upd up) {
   using C = D16;
   typedef __attribute__((address_space(3))) void* lds_vptr;
   typedef __attribute__((address_space(1))) const void* glb_vptr;
@@ -583,11 +630,107 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
     const int q = (C::DMA_PER_WAVE * W + i) * 64 + lane;
     const int r = q / C::CH;
     cofs[i] = 2 * ((q % C::CH) ^ d16_swz(r));
-    src[i] = Ag + (int64_t)idx[r < m ? r : 0] * ld;   // rows past m: any valid row
+    // rows past m: any valid row (MODE 2 reads no Gram rows)
+    src[i] = MODE == 2 ? Ag : Ag + (int64_t)idx[r < m ? r : 0] * ld;
   }
-  const bool want_u = u != nullptr;
+  const bool want_u = MODE == 1 || u != nullptr;
   const gptr<const double> ug = glb(u);
-  const bool u_dma = want_u && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  const bool u_dma = MODE == 0 && want_u && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+
+  // The previous step's rows (MODE 1 and 2): DMA instruction i of this wave
+  // fills slots (4 W + i) * 64 + lane of an update buffer, row q / 8, chunk
+  // (q % 8) ^ (row & 7).
+  // (slot q = (4 W + i) 64 + lane holds row 8 (4 W + i) + lane / 8, whose
+  // swizzle (row >> 1) & 7 is (4 i + lane / 16) & 7; the rows are kept as
+  // indices, the addresses formed at each issue, to spare registers)
+  int yrow[C::DMA_PER_WAVE];
+  const gptr<double> rg = glb(up.r);
+  const bool r_dma = (reinterpret_cast<uintptr_t>(up.r) & 15) == 0;
+  if constexpr (MODE != 0) {
+#pragma unroll
+    for (int i = 0; i < C::DMA_PER_WAVE; ++i)
+      yrow[i] = up.idx[8 * (C::DMA_PER_WAVE * W + i) + (lane >> 3)];
+    if (tid < C::SBP) lds[C::DOFF + tid] = up.gamma * up.delta[tid];
+  }
+  auto issue_y = [&](int t, int slot) {
+    const int64_t k0 = k_begin + (int64_t)t * C::KT;
+    double* Y = lds + C::YOFF + slot * C::YT;
+#pragma unroll
+    for (int i = 0; i < C::DMA_PER_WAVE; ++i) {
+      double* dst = Y + (C::DMA_PER_WAVE * W + i) * 128;
+      const int64_t k = k0 + 2 * ((lane & 7) ^ ((4 * i + (lane >> 4)) & 7));
+      const gptr<const double> row = Ag + (int64_t)yrow[i] * ld;
+      if (k + 1 < k_end) {
+        __builtin_amdgcn_global_load_lds((glb_vptr)(row + k), (lds_vptr)dst, 16, 0, 0);
+      } else {
+        double2 v;
+        v.x = k < k_end ? row[k] : 0.0;
+        v.y = 0.0;
+        *reinterpret_cast<double2*>(dst + 2 * lane) = v;
+      }
+    }
+    // the old companion entries of the tile's columns: lanes 0..CH-1 of wave 7
+    if (W == 7 && lane < C::CH) {
+      double* dst = Y + C::SBP * C::KT;
+      const int64_t k = k0 + 2 * lane;
+      if (r_dma && k + 1 < k_end) {
+        __builtin_amdgcn_global_load_lds((glb_vptr)(rg + k), (lds_vptr)dst, 16, 0, 0);
+      } else {
+        double2 v;
+        v.x = k < k_end ? rg[k] : 0.0;
+        v.y = k + 1 < k_end ? rg[k + 1] : 0.0;
+        *reinterpret_cast<double2*>(dst + 2 * lane) = v;
+      }
+    }
+  };
+  // tile t's update from update buffer yslot; MODE 1 also fills the u slot
+  // of Gram buffer uslot
+  auto update = [&](int t, int yslot, int uslot) {
+    const double* Y = lds + C::YOFF + yslot * C::YT;
+    const double* dl = lds + C::DOFF;
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll 2
+    for (int j = 0; j < C::SBP / 64; ++j) {
+      const int r = lane + 64 * j;
+      const double2 y = *reinterpret_cast<const double2*>(Y + r * C::KT + 2 * (W ^ d16_swz(r)));
+      const double dj = dl[r];
+      p0 = fma(y.x, dj, p0);
+      p1 = fma(y.y, dj, p1);
+    }
+    // the wave's total: each row of 16 lanes by DPP rotations, then the four
+    // row sums (lanes 0, 16, 32, 48) in a fixed order
+    p0 = d16_row_sum(p0);
+    p1 = d16_row_sum(p1);
+    p0 = (d16_read_lane(p0, 0) + d16_read_lane(p0, 16)) +
+         (d16_read_lane(p0, 32) + d16_read_lane(p0, 48));
+    p1 = (d16_read_lane(p1, 0) + d16_read_lane(p1, 16)) +
+         (d16_read_lane(p1, 32) + d16_read_lane(p1, 48));
+    if (lane == 0) {
+      const int64_t k = k_begin + (int64_t)t * C::KT + 2 * W;
+      const double* ro = Y + C::SBP * C::KT;
+      const double n0 = ro[2 * W] + p0, n1 = ro[2 * W + 1] + p1;
+      if (k < k_end) rg[k] = n0;
+      if (k + 1 < k_end) rg[k + 1] = n1;
+      if constexpr (MODE == 1) {
+        double* us = lds + uslot * C::TILE + C::SBP * C::KT;
+        us[2 * W] = k < k_end ? n0 : 0.0;
+        us[2 * W + 1] = k + 1 < k_end ? n1 : 0.0;
+      }
+    }
+  };
+  if constexpr (MODE == 2) {
+    issue_y(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+      if (t + 1 < ntiles) issue_y(t + 1, (t + 1) & 1);
+      update(t, t & 1, -1);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    return;
+  }
+
   auto issue = [&](int t, int slot) {
     const int64_t k0 = k_begin + (int64_t)t * C::KT;
     double* T = lds + slot * C::TILE;
@@ -605,7 +748,8 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
       }
     }
     // the tile's KT entries of u (zeros without u): lanes 0..CH-1 of wave 7
-    if (W == 7 && lane < C::CH) {
+    // (MODE 1: the update writes them)
+    if (MODE == 0 && W == 7 && lane < C::CH) {
       double* dst = T + C::SBP * C::KT;
       const int64_t k = k0 + 2 * lane;
       if (u_dma && k + 1 < k_end) {
@@ -633,10 +777,26 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
   double yua[2] = {0.0, 0.0};
 
   issue(0, 0);
+  if constexpr (MODE == 1) {
+    issue_y(0, 0);
+    if (ntiles > 1) issue_y(1, 1);
+  }
   __builtin_amdgcn_s_waitcnt(0);   // the LDS-DMA writes count on the vector memory counter
   __syncthreads();
+  if constexpr (MODE == 1) {
+    update(0, 0, 0);
+    __syncthreads();
+  }
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) issue(t + 1, (t + 1) & 1);
+    if constexpr (MODE == 1) {
+      // update buffer t & 1 held tile t (updated during tile t - 1); tile t + 1
+      // arrived during tile t - 1.  Waves 0-3 update before their matrix
+      // instructions, waves 4-7 (the other wave of each SIMD) after them, so
+      // the update's latency runs beside the other wave's MFMA chain.
+      if (t + 2 < ntiles) issue_y(t + 2, t & 1);
+      if (W < 4 && t + 1 < ntiles) update(t + 1, (t + 1) & 1, (t + 1) & 1);
+    }
     const double* tile = lds + (t & 1) * C::TILE;
 #pragma unroll
     for (int pp = 0; pp < C::PP; ++pp) {
@@ -662,6 +822,9 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
         acc[R0 + 1 + c] = mfma(f1.x, fc.x, acc[R0 + 1 + c]);
         acc[R0 + 1 + c] = mfma(f1.y, fc.y, acc[R0 + 1 + c]);
       }
+    }
+    if constexpr (MODE == 1) {
+      if (W >= 4 && t + 1 < ntiles) update(t + 1, (t + 1) & 1, (t + 1) & 1);
     }
     __builtin_amdgcn_s_waitcnt(0);   // tile t + 1 is in LDS
     __syncthreads();
@@ -690,20 +853,22 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
 
 // The NB = 16 slab of gram_slab<16, 2> on the DMA path; same arguments and
 // partial layout (A must be 16-byte aligned with an even ld).
+template <int MODE = 0>
 __device__ __forceinline__ void gram_slab_dma16(const double* __restrict__ A, int64_t ld,
                                                 int64_t k_begin, int64_t k_end,
                                                 const int32_t* idx, int m,
                                                 const double* __restrict__ u,
-                                                double* __restrict__ part, double* lds) {
+                                                double* __restrict__ part, double* lds,
+                                                const D16Upd up = D16Upd{}) {
   switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-    case 0: d16_slab<0>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
-    case 1: d16_slab<1>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
-    case 2: d16_slab<2>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
-    case 3: d16_slab<3>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
-    case 4: d16_slab<4>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
-    case 5: d16_slab<5>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
-    case 6: d16_slab<6>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
-    default: d16_slab<7>(A, ld, k_begin, k_end, idx, m, u, part, lds); break;
+    case 0: d16_slab<0, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
+    case 1: d16_slab<1, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
+    case 2: d16_slab<2, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
+    case 3: d16_slab<3, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
+    case 4: d16_slab<4, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
+    case 5: d16_slab<5, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
+    case 6: d16_slab<6, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
+    default: d16_slab<7, MODE>(A, ld, k_begin, k_end, idx, m, u, part, lds, up); break;
   }
 }
 

@@ -57,6 +57,20 @@ __global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_kernel(
                   partials + (int64_t)blockIdx.x * (D16::NBLK * 256 + D16::SBP), lds);
 }
 
+// MODE 1: the Gram with the previous step's update folded in; MODE 2: the
+// update alone (one slab per workgroup, the Gram's slabs).
+template <int MODE>
+__global__ __launch_bounds__(D16::THREADS) void gram_f64_dma16_upd_kernel(
+    const double* __restrict__ A, int64_t ld, int64_t cols, const int32_t* __restrict__ idx,
+    int m, int64_t chunk, double* __restrict__ partials, D16Upd up) {
+  __shared__ __attribute__((aligned(16))) double lds[D16::LDS_UPD];
+  const int64_t k_begin = (int64_t)blockIdx.x * chunk;
+  const int64_t k_end = std::min(cols, k_begin + chunk);
+  double* part =
+      MODE == 1 ? partials + (int64_t)blockIdx.x * (D16::NBLK * 256 + D16::SBP) : nullptr;
+  gram_slab_dma16<MODE>(A, ld, k_begin, k_end, idx, m, nullptr, part, lds, up);
+}
+
 // A reduction workgroup has 1024 threads: GROUPS split groups (a wave or more
 // each) for 1024 / GROUPS entries.  Many splits take 16 groups of 64 entries;
 // a few splits take one group, each thread summing all of its entry's splits.
@@ -140,6 +154,10 @@ __global__ __launch_bounds__(512) void big_index_kernel(const int32_t* __restric
   const int nc = m - 256 > 128 ? 4 : 2;
   gdev::big_lists(idx + (int64_t)blockIdx.x * m, m, ia + (int64_t)blockIdx.x * 512,
                   ib + (int64_t)blockIdx.x * 256 * nc, threadIdx.x, 512);
+}
+
+bool d16_ok(const GramPlan& p, const double* A, int64_t ld) {
+  return p.nb == 16 && p.rpw == 1 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (ld & 1) == 0;
 }
 
 template <int NB, int RPW>
@@ -247,6 +265,30 @@ hipError_t launch_gram_f64(const GramPlan& p, const double* A, int64_t ld, int64
     case 16: return launch_nb<16, 2>(p, A, ld, cols, idx, m, nsteps, u, partials, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+bool gram_f64_takes_update(const GramPlan& p, const double* A, int64_t ld, int m) {
+  return m == D16::SBP && d16_ok(p, A, ld);
+}
+
+hipError_t launch_gram_f64_upd(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
+                               const int32_t* idx, int m, double* partials, const D16Upd& up,
+                               hipStream_t st) {
+  if (!gram_f64_takes_update(p, A, ld, m) || up.idx == nullptr || up.delta == nullptr ||
+      up.r == nullptr)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gram_f64_dma16_upd_kernel<1>), dim3((unsigned)p.nsplit), dim3(D16::THREADS),
+                     0, st, A, ld, cols, idx, m, p.chunk, partials, up);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_f64(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
+                             const D16Upd& up, hipStream_t st) {
+  if (!d16_ok(p, A, ld) || up.idx == nullptr || up.delta == nullptr || up.r == nullptr)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gram_f64_dma16_upd_kernel<2>), dim3((unsigned)p.nsplit), dim3(D16::THREADS),
+                     0, st, A, ld, cols, nullptr, 0, p.chunk, nullptr, up);
+  return hipGetLastError();
 }
 
 template <int MODE>

@@ -118,6 +118,29 @@ struct GramPlan {
   int rpw;         // block rows per wave (2: eight waves, 4: four waves)
 };
 GramPlan plan_gram_f64(int m, int64_t cols);
+// The deferred companion update of the previous outer step (Alg. 2: r += gamma
+// Y^T delta with the previous step's rows and delta; Alg. 4 the same for w):
+// its 256 rows idx (all valid), delta (256), the scale gamma, and the
+// companion r, read and then rewritten in place, each column by the one
+// workgroup whose slab holds it.
+struct D16Upd {
+  const int32_t* idx;
+  const double* delta;
+  double gamma;
+  double* r;
+};
+// The dense 256-row Gram can take the previous step's update along
+// (launch_gram_f64_upd) when its plan runs the LDS-DMA kernel: 16-byte
+// aligned rows with an even ld, m = 256.
+bool gram_f64_takes_update(const GramPlan& p, const double* A, int64_t ld, int m);
+// The 256-row Gram (nsteps = 1) of gram_f64 with the previous step's update
+// applied to r first; the Y r partials use the updated r.
+hipError_t launch_gram_f64_upd(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
+                               const int32_t* idx, int m, double* partials, const D16Upd& up,
+                               hipStream_t st);
+// The same update alone, by the same device code (so its rounding matches).
+hipError_t launch_update_f64(const GramPlan& p, const double* A, int64_t ld, int64_t cols,
+                             const D16Upd& up, hipStream_t st);
 size_t gram_partial_doubles(const GramPlan& p);   // partial G + partial Yu
 // partials: nsplit * (nblk*256 + 16*nb) doubles.
 // nsteps > 1: the Grams of nsteps row lists in one launch (step k reads

@@ -89,6 +89,63 @@ def test_dual_fp64_per_step_path_full_steps(gpu_lib):
     assert e_a <= 1e-10 and e_w <= 1e-10
 
 
+def test_folded_update_resume_is_bitwise(gpu_lib):
+    """At s b = 256 with one Gram per step, a full step's companion update is
+    applied inside the next step's Gram kernel, or on its own before a
+    ragged step, a check or the end of a call, by the same device code.  The
+    same run in one call and split in two (h0, state passed on) is bitwise
+    equal, though the split moves one update from folded to alone; both match
+    the oracle.  Primal and dual."""
+    d, n, b, s, lam, seed = 512, 8192, 8, 32, 1e-4, 2003
+    X, y, _ = synth.spectral_ridge(d, n, 1003)
+    Xd, yd = X.to(DEV), y.to(DEV)
+    H = 5 * s
+    w1, r1 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed)
+    w2, r2 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, 2 * s, seed)
+    gpu_lib.primal_bcd(Xd, yd, lam, b, s, 3 * s, seed, w=w2, r=r2, h0=2 * s,
+                       flags=gpu_lib.FLAG_STATE_VALID)
+    assert torch.equal(w1, w2) and torch.equal(r1, r2)
+    wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed)
+    assert _rel(w1.cpu(), wo) <= 1e-10 and _rel(r1.cpu(), zo - y.numpy()) <= 1e-10
+    # dual with the same 512 x 8192 matrix as A = X^T: 512 data points of
+    # 8192 features (16 MiB gathered per step)
+    yt = torch.tensor(np.random.default_rng(9).standard_normal(d))
+    ytd = yt.to(DEV)
+    a1, v1 = gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, 4 * s, seed)
+    a2, v2 = gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, 3 * s, seed)
+    gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, s, seed, alpha=a2, w=v2, h0=3 * s,
+                     flags=gpu_lib.FLAG_STATE_VALID)
+    assert torch.equal(a1, a2) and torch.equal(v1, v2)
+    ao, vo = bcd.dual_bcd(X.numpy().T.copy(), yt.numpy(), 1e-2, b, s, 4 * s, seed)
+    assert _rel(a1.cpu(), ao) <= 1e-10 and _rel(v1.cpu(), vo) <= 1e-10
+
+
+def test_folded_update_with_monitor_and_checks(gpu_lib):
+    """Monitor points, exact recomputations and residual checks read the
+    companion, so the steps before them apply their update on their own; the
+    objective trace and the stopping iteration match the oracle's."""
+    d, n, b, s, lam, seed = 512, 8192, 8, 32, 1e-4, 2004
+    X, y, _ = synth.spectral_ridge(d, n, 1004)
+    Xd, yd = X.to(DEV), y.to(DEV)
+    H = 7 * s
+    trace = torch.zeros(3, dtype=torch.float64, device=DEV)
+    w, r = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed, monitor_every=3, resid_every=5,
+                              trace=trace)
+    fs = []
+    wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed,
+                            monitor=lambda h, w_, z_: fs.append(
+                                bcd.primal_objective(X.numpy(), y.numpy(), lam, w_)))
+    assert np.allclose(trace.cpu().numpy(), np.array(fs[2::3][:2] + [0.0]), rtol=1e-11, atol=0)
+    assert _rel(w.cpu(), wo) <= 1e-10 and _rel(r.cpu(), zo - y.numpy()) <= 1e-10
+    # a residual check every 2 outer steps: the run stops where the oracle's
+    # residual first falls below the tolerance
+    st = {}
+    w3, _ = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed, tol=1e300, check_every=2, stats=st)
+    assert st["h"] == 2 * s
+    w4, _ = gpu_lib.primal_bcd(Xd, yd, lam, b, s, 2 * s, seed)
+    assert torch.equal(w3, w4)
+
+
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 def test_mixed_primal_per_step_path(gpu_lib, dtype):
     """The mixed-precision step at sb = 256 (b = 16, s = 16) on rows of 65536
