@@ -638,11 +638,10 @@ __device__ __forceinline__ void d16_slab(const double* __restrict__ A, int64_t l
   const bool u_dma = MODE == 0 && want_u && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
 
   // The previous step's rows (MODE 1 and 2): DMA instruction i of this wave
-  // fills slots (4 W + i) * 64 + lane of an update buffer, row q / 8, chunk
-  // (q % 8) ^ (row & 7).
-  // (slot q = (4 W + i) 64 + lane holds row 8 (4 W + i) + lane / 8, whose
-  // swizzle (row >> 1) & 7 is (4 i + lane / 16) & 7; the rows are kept as
-  // indices, the addresses formed at each issue, to spare registers)
+  // fills slots q = (4 W + i) * 64 + lane of an update buffer: row q / 8 =
+  // 8 (4 W + i) + lane / 8, chunk (q % 8) ^ ((row >> 1) & 7), the swizzle
+  // being (4 i + lane / 16) & 7.  The rows are kept as indices and the
+  // addresses formed at each issue, to spare registers.
   int yrow[C::DMA_PER_WAVE];
   const gptr<double> rg = glb(up.r);
   const bool r_dma = (reinterpret_cast<uintptr_t>(up.r) & 15) == 0;
