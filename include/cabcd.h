@@ -142,12 +142,15 @@ typedef struct cabcd_opts {
 
 /* Phases reported through cabcd_opts.timing (the breakdown of one outer step). */
 #define CABCD_PHASE_SAMPLE 0    /* block sampler                                   */
-#define CABCD_PHASE_GRAM 1      /* gathered-row Gram (with Y u when fused)         */
+#define CABCD_PHASE_GRAM 1      /* gathered-row Gram (with Y u when fused; dense   */
+                                /* 256-row steps: with the previous step's        */
+                                /* companion update applied on its way)           */
 #define CABCD_PHASE_REDUCE 2    /* sum of the Gram partials, scale and overlap     */
 #define CABCD_PHASE_SOLVE 3     /* s block solves + recurrence + x[idx] += d;      */
                                 /* also the launches that invert the diagonal     */
                                 /* blocks of Grams computed ahead                 */
-#define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta                 */
+#define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta (a launch only  */
+                                /* when it is not left to the next step's Gram)   */
 #define CABCD_PHASE_RECOMPUTE 5 /* exact companion recomputation                   */
 #define CABCD_PHASE_MONITOR 6   /* objective evaluation                            */
 #define CABCD_PHASE_CHECK 7     /* full residual of the stopping test              */
