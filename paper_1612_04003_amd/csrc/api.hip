@@ -915,6 +915,9 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     sa.pre_inverted = from_ahead && pre_inv ? 1 : 0;
     HIP_TRY(timer.run(CABCD_PHASE_SOLVE, [&] { return launch_solve(sa, st); }));
     HIP_TRY(timer.run(CABCD_PHASE_UPDATE, [&] {
+      // an exact recomputation right after this step rebuilds the companion
+      // from the coordinates alone, so the update would be overwritten
+      if (o.resid_every > 0 && (k + 1) % o.resid_every == 0) return hipSuccess;
       // steps whose Gram came from a split launch: the deterministic update
       // from its panel and sorted lists
       if (from_ahead && split)
