@@ -10,9 +10,9 @@ deferred w / residual updates.  Inputs are resident in HBM before timing.
 
 value = algorithmic Gram flops of the timed steps (n*sb*(sb+1) per step: the
 lower triangle with its diagonal) / wall time of the whole steps, in TFLOP/s.
-roofline: the Gram kernel (which at s*b = 256 also applies the previous
-step's deferred residual update to the columns it reads), timed with HIP
-events on the stream it runs on.  cpu_baseline: the FP64 oracle on a bounded number of outer steps of the
+roofline: the Gram kernel alone, timed with HIP events on the stream it runs
+on.  folded_update: the same steps with CABCD_FLAG_FOLD_UPDATE (each step's
+residual update applied inside the next step's Gram kernel).  cpu_baseline: the FP64 oracle on a bounded number of outer steps of the
 same problem on the host.
 
 time_to_tol: wall time from the first s-step until a monitor point (every 4
@@ -139,7 +139,7 @@ def closed_form(cabcd, torch, X, y, lam):
 
 
 def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False, mask=0,
-                 settle_s=0.0):
+                 settle_s=0.0, flags=0):
     """Warm up, then time `steps` outer steps; returns (elapsed s, phase dict).
     `mask` selects the phases bracketed by HIP events (0: all); every event
     pair costs GPU time, so the timed headline run brackets the Gram only.
@@ -158,14 +158,14 @@ def timed_primal(cabcd, torch, X, y, lam, b, s, steps, warmup, seed, dual=False,
     if settle_s > 0.0:
         t_end = time.perf_counter() + settle_s
         while time.perf_counter() < t_end:
-            run(X, y, lam, b, s, 10 * s, seed, **kw0)
+            run(X, y, lam, b, s, 10 * s, seed, flags=flags, **kw0)
             torch.cuda.synchronize()
         coord.zero_()
-    run(X, y, lam, b, s, warmup * s, seed, **kw0)
+    run(X, y, lam, b, s, warmup * s, seed, flags=flags, **kw0)
     torch.cuda.synchronize()
     tm = cabcd.new_timing()
     t0 = time.perf_counter()
-    run(X, y, lam, b, s, steps * s, seed, h0=warmup * s, flags=cabcd.FLAG_STATE_VALID,
+    run(X, y, lam, b, s, steps * s, seed, h0=warmup * s, flags=cabcd.FLAG_STATE_VALID | flags,
         timing=tm, timing_mask=mask, **kw0)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, cabcd.timing_dict(tm)
@@ -229,16 +229,9 @@ def headline(args, cabcd, torch, synth):
         achieved = ybytes / (gram_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
-    # at s b = 256 on LDS-DMA rows the Gram kernel also applies the previous
-    # step's companion update (all steps but the first of the timed call):
-    # its algorithmic bytes are both steps' gathered rows and r read and written
-    folded = sb == 256 and n % 2 == 0
-    roof["kernel"] = ("gram_f64_dma16_upd_kernel<1>" if folded else
-                      "gram_f64_dma16_kernel" if sb > 128 and n % 2 == 0 else
+    roof["kernel"] = ("gram_f64_dma16_kernel" if sb > 128 and n % 2 == 0 else
                       "gram_f64_kernel<16,2>" if sb > 128 else "gram_f64_kernel")
-    roof["per_launch"] = {"flops": gram_flops,
-                          "bytes": 2 * ybytes + 16 * n if folded else ybytes,
-                          "ms": round(gram_ms, 4)}
+    roof["per_launch"] = {"flops": gram_flops, "bytes": ybytes, "ms": round(gram_ms, 4)}
     out = {
         "metric": "CA-BCD Gram TFLOP/s (% peak) + time-to-1e-6 rel obj error, FP64 vs mixed",
         "value": round(value, 3),
@@ -262,6 +255,22 @@ def headline(args, cabcd, torch, synth):
         "phases_ms_per_step": {k: round(v["ms"] / min(args.steps, 10), 4)
                                for k, v in ph_all.items() if v["launches"]},
     }
+    if sb == 256 and n % 2 == 0:
+        # the same steps with each step's residual update applied inside the
+        # next step's Gram kernel: that kernel streams the previous step's
+        # rows too (its bytes 2 sb n 8 + 16 n), the step skips its update pass
+        log("timing the steps with the update folded into the next Gram")
+        el_f, ph_f = timed_primal(cabcd, torch, X, y, lam, b, s, args.steps, args.warmup, 2001,
+                                  mask=gram_only, flags=cabcd.FLAG_FOLD_UPDATE)
+        gf = ph_f["gram"]
+        gf_ms = gf["ms"] / max(gf["launches"], 1)
+        out["folded_update"] = {
+            "ms_per_step": round(el_f / args.steps * 1e3, 4),
+            "value": round(gram_flops * args.steps / el_f / 1e12, 3),
+            "kernel": "gram_f64_dma16_upd_kernel<1> (the call's first step: gram_f64_dma16_kernel)",
+            "gram_ms": round(gf_ms, 4),
+            "gram_frac": round(gram_flops / (gf_ms * 1e-3) / 1e12 / PEAK_FP64_MATRIX_TFLOPS, 4),
+            "gram_bytes": 2 * ybytes + 16 * n}
     return out, X, y
 
 

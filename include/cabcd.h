@@ -102,6 +102,15 @@ typedef struct cabcd_matrix {
 #define CABCD_FLAG_MONITOR_MAINTAINED 4u  /* primal: monitor points evaluate f(w)
                                              from the maintained residual r instead
                                              of recomputing X^T w - y              */
+#define CABCD_FLAG_FOLD_UPDATE 8u  /* dense FP64, s*b = 256, one Gram per outer
+                                      step: apply each step's companion update
+                                      inside the next step's Gram kernel (one
+                                      pass over both steps' rows; the Gram kernel
+                                      then runs longer, the whole step shorter).
+                                      Results differ from the unfolded run in
+                                      rounding only, and are reproducible bit for
+                                      bit however the run is split into calls
+                                      with this flag                           */
 
 typedef struct cabcd_opts {
   int64_t h0;                /* global index of the first inner iteration (resume) */
@@ -142,9 +151,9 @@ typedef struct cabcd_opts {
 
 /* Phases reported through cabcd_opts.timing (the breakdown of one outer step). */
 #define CABCD_PHASE_SAMPLE 0    /* block sampler                                   */
-#define CABCD_PHASE_GRAM 1      /* gathered-row Gram (with Y u when fused; dense   */
-                                /* 256-row steps: with the previous step's        */
-                                /* companion update applied on its way)           */
+#define CABCD_PHASE_GRAM 1      /* gathered-row Gram (with Y u when fused; with    */
+                                /* CABCD_FLAG_FOLD_UPDATE also the previous       */
+                                /* step's companion update)                       */
 #define CABCD_PHASE_REDUCE 2    /* sum of the Gram partials, scale and overlap     */
 #define CABCD_PHASE_SOLVE 3     /* s block solves + recurrence + x[idx] += d;      */
                                 /* also the launches that invert the diagonal     */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcabcd.so")
 OK, EINVAL, ENOTSPD, EHIP, ENOMEM, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 DENSE, CSR_KIND = 0, 1
 F64, BF16, FP8_E4M3 = 0, 1, 2
-FLAG_STATE_VALID, FLAG_ASYNC, FLAG_MONITOR_MAINTAINED = 1, 2, 4
+FLAG_STATE_VALID, FLAG_ASYNC, FLAG_MONITOR_MAINTAINED, FLAG_FOLD_UPDATE = 1, 2, 4, 8
 
 _STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOTSPD: "ENOTSPD", EHIP: "EHIP",
                  ENOMEM: "ENOMEM", EUNSUPPORTED: "EUNSUPPORTED", ENONFINITE: "ENONFINITE"}

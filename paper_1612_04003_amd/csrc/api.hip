@@ -768,16 +768,17 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
   int bp = 1;
   while (bp < b) bp *= 2;
   const bool pre_inv = K > 1 && bp <= 16 && (int64_t)s * bp <= 512;
-  // The dense 256-row Gram can apply the previous step's companion update on
-  // its way (one pass over both steps' rows, the update's traffic beside the
-  // matrix cores' work instead of a pass of its own): a full step leaves its
-  // update pending when the next step is a full one with nothing in between
-  // that reads the companion (check, monitor point, exact recomputation) and
-  // keeps its indices in place.  Every such step's update runs through that
-  // device code, folded or alone, so a column's rounding does not depend on
-  // how a run is split into calls.
+  // CABCD_FLAG_FOLD_UPDATE: the dense 256-row Gram applies the previous
+  // step's companion update on its way (one pass over both steps' rows, the
+  // update's traffic beside the matrix cores' work instead of a pass of its
+  // own): a full step leaves its update pending when the next step is a full
+  // one with nothing in between that reads the companion (check, monitor
+  // point, exact recomputation) and keeps its indices in place.  Every such
+  // step's update runs through that device code, folded or alone, so a
+  // column's rounding does not depend on how a run is split into calls.
   const GramPlan fplan = plan_for(M, kGramRows);
-  const bool fuse_kind = K == 1 && !M.csr && !M.lowp() && (int64_t)s * b == kGramRows &&
+  const bool fuse_kind = (o.flags & CABCD_FLAG_FOLD_UPDATE) != 0 && K == 1 && !M.csr &&
+                         !M.lowp() && (int64_t)s * b == kGramRows &&
                          gram_f64_takes_update(fplan, M.X, M.ld, kGramRows);
   bool pending = false;
   const int32_t* pend_idx = nullptr;

@@ -52,16 +52,19 @@ def _assert_per_step(gpu_lib, t, steps):
 
 # ------------------------------------------------------------------ one Gram per step
 
-def test_primal_fp64_per_step_path_full_steps(gpu_lib):
+@pytest.mark.parametrize("fold", [False, True])
+def test_primal_fp64_per_step_path_full_steps(gpu_lib, fold):
     """Headline path at a shard shape: b = 8, s = 32 (sb = 256), rows of
     32768 FP64 values (64 MiB gathered per step), three full outer steps and a
-    ragged one; the spectrum of the headline matrix (1 .. 1e3)."""
+    ragged one; the spectrum of the headline matrix (1 .. 1e3).  With and
+    without the companion update folded into the next step's Gram."""
     d, n, b, s, lam, seed = 512, 32768, 8, 32, 1e-4, 2001
     H = 3 * s + 5
-    _say("primal per-step", d, n, b, s, H)
+    _say("primal per-step", d, n, b, s, H, "fold" if fold else "")
     X, y, _ = synth.spectral_ridge(d, n, 1001)
     t = gpu_lib.new_timing()
-    w, r = gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), lam, b, s, H, seed, timing=t)
+    w, r = gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), lam, b, s, H, seed, timing=t,
+                              flags=gpu_lib.FLAG_FOLD_UPDATE if fold else 0)
     _assert_per_step(gpu_lib, t, 4)
     trace = []
     wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed,
@@ -90,31 +93,35 @@ def test_dual_fp64_per_step_path_full_steps(gpu_lib):
 
 
 def test_folded_update_resume_is_bitwise(gpu_lib):
-    """At s b = 256 with one Gram per step, a full step's companion update is
-    applied inside the next step's Gram kernel, or on its own before a
-    ragged step, a check or the end of a call, by the same device code.  The
-    same run in one call and split in two (h0, state passed on) is bitwise
-    equal, though the split moves one update from folded to alone; both match
-    the oracle.  Primal and dual."""
+    """CABCD_FLAG_FOLD_UPDATE at s b = 256 with one Gram per step: a full
+    step's companion update is applied inside the next step's Gram kernel, or
+    on its own before a ragged step, a check or the end of a call, by the
+    same device code.  The same run in one call and split in two (h0, state
+    passed on) is bitwise equal, though the split moves one update from folded
+    to alone; both match the oracle, and the unfolded run to rounding.
+    Primal and dual."""
     d, n, b, s, lam, seed = 512, 8192, 8, 32, 1e-4, 2003
     X, y, _ = synth.spectral_ridge(d, n, 1003)
     Xd, yd = X.to(DEV), y.to(DEV)
     H = 5 * s
-    w1, r1 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed)
-    w2, r2 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, 2 * s, seed)
+    fold = gpu_lib.FLAG_FOLD_UPDATE
+    w1, r1 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed, flags=fold)
+    w2, r2 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, 2 * s, seed, flags=fold)
     gpu_lib.primal_bcd(Xd, yd, lam, b, s, 3 * s, seed, w=w2, r=r2, h0=2 * s,
-                       flags=gpu_lib.FLAG_STATE_VALID)
+                       flags=gpu_lib.FLAG_STATE_VALID | fold)
     assert torch.equal(w1, w2) and torch.equal(r1, r2)
     wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed)
     assert _rel(w1.cpu(), wo) <= 1e-10 and _rel(r1.cpu(), zo - y.numpy()) <= 1e-10
+    w0, r0 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed)
+    assert _rel(w1.cpu(), w0.cpu()) <= 1e-12 and _rel(r1.cpu(), r0.cpu()) <= 1e-12
     # dual with the same 512 x 8192 matrix as A = X^T: 512 data points of
     # 8192 features (16 MiB gathered per step)
     yt = torch.tensor(np.random.default_rng(9).standard_normal(d))
     ytd = yt.to(DEV)
-    a1, v1 = gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, 4 * s, seed)
-    a2, v2 = gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, 3 * s, seed)
+    a1, v1 = gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, 4 * s, seed, flags=fold)
+    a2, v2 = gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, 3 * s, seed, flags=fold)
     gpu_lib.dual_bcd(Xd, ytd, 1e-2, b, s, s, seed, alpha=a2, w=v2, h0=3 * s,
-                     flags=gpu_lib.FLAG_STATE_VALID)
+                     flags=gpu_lib.FLAG_STATE_VALID | fold)
     assert torch.equal(a1, a2) and torch.equal(v1, v2)
     ao, vo = bcd.dual_bcd(X.numpy().T.copy(), yt.numpy(), 1e-2, b, s, 4 * s, seed)
     assert _rel(a1.cpu(), ao) <= 1e-10 and _rel(v1.cpu(), vo) <= 1e-10
@@ -122,15 +129,17 @@ def test_folded_update_resume_is_bitwise(gpu_lib):
 
 def test_folded_update_with_monitor_and_checks(gpu_lib):
     """Monitor points, exact recomputations and residual checks read the
-    companion, so the steps before them apply their update on their own; the
-    objective trace and the stopping iteration match the oracle's."""
+    companion, so with CABCD_FLAG_FOLD_UPDATE the steps before them apply
+    their update on their own; the objective trace and the stopping
+    iteration match the oracle's."""
     d, n, b, s, lam, seed = 512, 8192, 8, 32, 1e-4, 2004
     X, y, _ = synth.spectral_ridge(d, n, 1004)
     Xd, yd = X.to(DEV), y.to(DEV)
     H = 7 * s
+    fold = gpu_lib.FLAG_FOLD_UPDATE
     trace = torch.zeros(3, dtype=torch.float64, device=DEV)
     w, r = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed, monitor_every=3, resid_every=5,
-                              trace=trace)
+                              trace=trace, flags=fold)
     fs = []
     wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed,
                             monitor=lambda h, w_, z_: fs.append(
@@ -140,9 +149,10 @@ def test_folded_update_with_monitor_and_checks(gpu_lib):
     # a residual check every 2 outer steps: the run stops where the oracle's
     # residual first falls below the tolerance
     st = {}
-    w3, _ = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed, tol=1e300, check_every=2, stats=st)
+    w3, _ = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, seed, tol=1e300, check_every=2, stats=st,
+                               flags=fold)
     assert st["h"] == 2 * s
-    w4, _ = gpu_lib.primal_bcd(Xd, yd, lam, b, s, 2 * s, seed)
+    w4, _ = gpu_lib.primal_bcd(Xd, yd, lam, b, s, 2 * s, seed, flags=fold)
     assert torch.equal(w3, w4)
 
 
