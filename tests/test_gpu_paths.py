@@ -156,6 +156,29 @@ def test_folded_update_with_monitor_and_checks(gpu_lib):
     assert torch.equal(w3, w4)
 
 
+def test_folded_update_with_explicit_blocks(gpu_lib):
+    """CABCD_FLAG_FOLD_UPDATE with caller-given blocks (explicit_idx): the
+    pending update reads the previous step's rows from the caller's array;
+    blocks that repeat coordinates within and across steps.  Equal to the
+    unfolded run to rounding and to the oracle."""
+    d, n, b, s, lam = 600, 8192, 8, 32, 1e-3
+    X, y, _ = synth.gaussian_ridge(d, n, 1005)
+    Xd, yd = X.to(DEV), y.to(DEV)
+    H = 3 * s
+    rng = np.random.default_rng(17)
+    blocks = np.stack([rng.choice(d, b, replace=False) for _ in range(H)])
+    blocks[5] = blocks[4]                      # a block repeated inside a step
+    blocks[s + 3] = blocks[3]                  # and one repeated across steps
+    idx = torch.tensor(blocks, dtype=torch.int32, device=DEV)
+    wf, rf = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, 0, explicit_idx=idx,
+                                flags=gpu_lib.FLAG_FOLD_UPDATE)
+    w0, r0 = gpu_lib.primal_bcd(Xd, yd, lam, b, s, H, 0, explicit_idx=idx)
+    assert _rel(wf.cpu(), w0.cpu()) <= 1e-12 and _rel(rf.cpu(), r0.cpu()) <= 1e-12
+    wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, 0,
+                            explicit_idx=blocks.tolist())
+    assert _rel(wf.cpu(), wo) <= 1e-10 and _rel(rf.cpu(), zo - y.numpy()) <= 1e-10
+
+
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 def test_mixed_primal_per_step_path(gpu_lib, dtype):
     """The mixed-precision step at sb = 256 (b = 16, s = 16) on rows of 65536
