@@ -637,9 +637,16 @@ void slice(double wp, double target, int64_t n, int kt, int64_t& chunk_out, int&
   nslab_out = (int)((n + chunk - 1) / chunk);
 }
 
+// Slab items per CU a round aims at: FP64 slabs carry matrix-core work and
+// balance best at four; low-precision slabs are pure streams, and fewer,
+// longer items cut their per-item overhead (BF16 batched to 1e-6: 0.153 s at
+// four, 0.141 s at two; FP64 0.334 s at four, 0.339 s at two, 0.374 s at
+// eight).
+double items_per_cu(int dtype) { return dtype == CABCD_F64 ? 4.0 : 2.0; }
+
 // (b, s) of every problem for a target of `rp` rounds per pass over the
-// coordinates, slabs sized so a round has about four items per CU, and the
-// predicted time of one pass (rounds per pass x round time).
+// coordinates, slabs sized so a round has about items_per_cu items per CU, and
+// the predicted time of one pass (rounds per pass x round time).
 double plan_candidate(const std::vector<cabcd_problem>& pb, double rp, int cus,
                       std::vector<Pick>& out) {
   const size_t P = pb.size();
@@ -659,7 +666,7 @@ double plan_candidate(const std::vector<cabcd_problem>& pb, double rp, int cus,
     out[p].s = s;
     W += slab_work(b * s, pb[p].X.cols, pb[p].X.dtype);
   }
-  const double target = std::max(W / (4.0 * cus), 20e-6);
+  const double target = std::max(W / (items_per_cu(pb[0].X.dtype) * cus), 20e-6);
   double crit = 0.0, passes = 0.0;
   for (size_t p = 0; p < P; ++p) {
     const int sb = out[p].b * out[p].s;
@@ -1092,7 +1099,8 @@ cabcd_status replan(cabcd_batch_plan* B, hipStream_t st) {
   }
   std::vector<int64_t> chunk(act.size());
   std::vector<int> nslab(act.size());
-  for (double target = std::max(W / (4.0 * B->cus), 20e-6);; target *= 2.0) {
+  for (double target = std::max(W / (items_per_cu(B->dtype) * B->cus), 20e-6);;
+       target *= 2.0) {
     size_t items = 0, doubles = 0;
     for (size_t i = 0; i < act.size(); ++i) {
       const BProb& o = B->probs[act[i]];
