@@ -107,9 +107,10 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(
 // of LDS) covers the memory latency.  The sixteen 16-byte chunks of a row
 // are stored XOR-swizzled (chunk c of row r at c ^ (r & 15)), so the sixteen
 // rows of a fragment read fall in distinct banks.  Y u is formed from LDS:
-// thread t decodes chunk t % 16 of rows t / 16 + 32 j (j < 8) against the
-// tile's u segment (DMA'd beside the rows) and keeps one FP64 sum per row;
-// the sixteen chunk sums of a row are added in chunk order at the end.
+// thread t of waves 0-3 decodes chunk t % 16 of rows t / 16 + 16 j (j < 16)
+// against the tile's u segment (DMA'd beside the rows) and keeps one FP64
+// sum per row; the sixteen chunk sums of a row are added in chunk order at
+// the end.
 __host__ __device__ constexpr int blk_index16(int r, int c) { return r * (r + 1) / 2 + c; }
 
 template <int FMT>
@@ -278,11 +279,15 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   f4 acc[20];
 #pragma unroll
   for (int a = 0; a < 20; ++a) acc[a] = f4{0.f, 0.f, 0.f, 0.f};
-  // Y u: chunk yc of rows yr0 + 32 j
+  // Y u on waves 0-3 only (one of the two waves of each SIMD, so its vector
+  // work runs beside the other wave's matrix instructions; all eight waves
+  // taking a share: FP8 63.5 against 60.4 us at n = 2^20): thread t < 256
+  // sums chunk yc = t % 16 of rows yr0 + 16 j, yr0 = t / 16, j < 16
+  constexpr int YJ = W < 4 ? 16 : 0;
   const int yc = tid & 15, yr0 = tid >> 4;
-  double yu[8];
+  double yu[16];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) yu[j] = 0.0;
+  for (int j = 0; j < 16; ++j) yu[j] = 0.0;
 
   issue(0, 0);
   __builtin_amdgcn_s_waitcnt(0);   // the LDS-DMA writes count on the vector memory counter
@@ -321,8 +326,8 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
         ub[2 * q + 1] = v.y;
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int r = yr0 + 32 * j;
+      for (int j = 0; j < YJ; ++j) {
+        const int r = yr0 + 16 * j;
         const uint4 v = *reinterpret_cast<const uint4*>(tile + r * C::RB + 16 * (yc ^ (r & 15)));
         double dv[C::EPC];
         lp_decode_all<FMT>(v, dv);
@@ -349,7 +354,7 @@ __device__ __forceinline__ void lp16_slab(const uint8_t* __restrict__ A, int64_t
   if (want_u) {   // the sixteen chunk sums of each row, in chunk order
     double* ys = reinterpret_cast<double*>(lds);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ys[(yr0 + 32 * j) * 16 + yc] = yu[j];
+    for (int j = 0; j < YJ; ++j) ys[(yr0 + 16 * j) * 16 + yc] = yu[j];
     __syncthreads();
     if (tid < C::SBP) {
       double sum = 0.0;
