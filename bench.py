@@ -538,7 +538,12 @@ def batched_tol(cabcd, torch, synth, P=256, tol=1e-6, seed=1004, monitor=4, chea
     ds, ns, lams = synth.ridge_batch(P, seed)
     log(f"batched: generating {P} problems (sum d*n = {sum(d * n for d, n in zip(ds, ns)):.3g})")
     data = [synth.gaussian_ridge(ds[p], ns[p], seed + 1 + p, device="cuda")[:2] for p in range(P)]
+    # every X in the layout the library recommends (rows leading_dim apart:
+    # 16-byte aligned, so the LDS-DMA Gram and 16-byte loads apply to all of
+    # them, as they do to the quantised codes)
+    data = [(padded(cabcd, X), y) for X, y in data]
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
     def fstar(X, y, lam):
         return closed_form(cabcd, torch, X, y, lam)[1]
