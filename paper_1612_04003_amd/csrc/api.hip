@@ -337,7 +337,15 @@ class PhaseTimer {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
+    for (auto& r : dropped_) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
   }
+  // Called from inside a phase that enqueued nothing (an update left to the
+  // next step's Gram or made moot by a recomputation): the phase is not
+  // counted.
+  void drop() { drop_ = true; }
   template <class F>
   hipError_t run(int phase, F&& f) {
     return run_on(st_, phase, f);
@@ -353,8 +361,15 @@ class PhaseTimer {
     recs_.push_back(r);
     e = hipEventRecord(r.a, st);
     if (e != hipSuccess) return e;
+    drop_ = false;
     e = f();
     if (e != hipSuccess) return e;
+    if (drop_) {
+      drop_ = false;
+      dropped_.push_back(r);
+      recs_.pop_back();
+      return hipSuccess;
+    }
     return hipEventRecord(r.b, st);
   }
   // Call after the stream has been synchronised.
@@ -378,6 +393,8 @@ class PhaseTimer {
   double* out_;
   uint32_t mask_;
   hipStream_t st_;
+  bool drop_ = false;
+  std::vector<Rec> dropped_;   // events of dropped phases, destroyed at the end
   std::vector<Rec> recs_;
 };
 
@@ -918,7 +935,10 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
     HIP_TRY(timer.run(CABCD_PHASE_UPDATE, [&] {
       // an exact recomputation right after this step rebuilds the companion
       // from the coordinates alone, so the update would be overwritten
-      if (o.resid_every > 0 && (k + 1) % o.resid_every == 0) return hipSuccess;
+      if (o.resid_every > 0 && (k + 1) % o.resid_every == 0) {
+        timer.drop();
+        return hipSuccess;
+      }
       // steps whose Gram came from a split launch: the deterministic update
       // from its panel and sorted lists
       if (from_ahead && split)
@@ -933,6 +953,7 @@ cabcd_status run_bcd(bool dual, const Mat& M, const double* y, double lambda, in
         if (H - h1 >= s && !reads_comp && (o.explicit_idx != nullptr || h1 < chunk_end)) {
           pending = true;
           pend_idx = idx;
+          timer.drop();
           return hipSuccess;
         }
         return launch_update_f64(fplan, M.X, M.ld, M.cols, D16Upd{idx, B.delta, gamma, comp}, st);

@@ -43,11 +43,13 @@ def _launches(gpu_lib, t):
     return {k: v["launches"] for k, v in gpu_lib.timing_dict(t).items()}
 
 
-def _assert_per_step(gpu_lib, t, steps):
+def _assert_per_step(gpu_lib, t, steps, updates=None):
     n = _launches(gpu_lib, t)
     _say("  launches", n)
     assert n["yu"] == 0, "expected one fused Gram per outer step"
     assert n["gram"] == steps and n["reduce"] == steps and n["solve"] == steps
+    if updates is not None:   # updates not left to the next step's Gram
+        assert n["update"] == updates
 
 
 # ------------------------------------------------------------------ one Gram per step
@@ -65,7 +67,10 @@ def test_primal_fp64_per_step_path_full_steps(gpu_lib, fold):
     t = gpu_lib.new_timing()
     w, r = gpu_lib.primal_bcd(X.to(DEV), y.to(DEV), lam, b, s, H, seed, timing=t,
                               flags=gpu_lib.FLAG_FOLD_UPDATE if fold else 0)
-    _assert_per_step(gpu_lib, t, 4)
+    # folded: the updates of steps 1 and 2 run inside the Grams of steps 2
+    # and 3; step 3's runs alone (no full step follows), as does the ragged
+    # step's
+    _assert_per_step(gpu_lib, t, 4, updates=2 if fold else 4)
     trace = []
     wo, zo = bcd.primal_bcd(X.numpy(), y.numpy(), lam, b, s, H, seed,
                             monitor=lambda h, w_, z_: trace.append(h))
@@ -73,6 +78,35 @@ def test_primal_fp64_per_step_path_full_steps(gpu_lib, fold):
     e_w, e_r = _rel(w.cpu(), wo), _rel(r.cpu(), zo - y.numpy())
     _say(f"  rel err w {e_w:.2e}, r {e_r:.2e}")
     assert e_w <= 1e-10 and e_r <= 1e-10
+
+
+def test_primal_headline_size_full_steps(gpu_lib):
+    """The benchmark's own workload and launch configuration: d = 2048,
+    n = 2^18, b = 8, s = 32 (sb = 256), lambda = 1e-4, X generated as the
+    benchmark generates it (spectrum 1 .. 1e3) and stored with its rows
+    leading_dim apart; three full outer steps through the one-Gram-per-step
+    path, without and with the update folded into the next step's Gram; every
+    entry of w and r against the oracle's run of the same steps."""
+    d, n, b, s, lam, seed = 2048, 1 << 18, 8, 32, 1e-4, 7
+    H = 3 * s
+    _say("primal headline size", d, n, b, s, H)
+    X, y, _ = synth.spectral_ridge(d, n, 1001, device=DEV)
+    Xc, yc = X.cpu().numpy(), y.cpu().numpy()
+    Xp = gpu_lib.empty_dense(d, n, DEV)
+    Xp.copy_(X)
+    del X
+    assert Xp.stride(0) == gpu_lib.leading_dim(n, gpu_lib.F64) != n
+    wo, zo = bcd.primal_bcd(Xc, yc, lam, b, s, H, seed)
+    for fold in (False, True):
+        t = gpu_lib.new_timing()
+        w, r = gpu_lib.primal_bcd(Xp, y, lam, b, s, H, seed, timing=t,
+                                  flags=gpu_lib.FLAG_FOLD_UPDATE if fold else 0)
+        _assert_per_step(gpu_lib, t, 3, updates=1 if fold else 3)
+        e_w, e_r = _rel(w.cpu(), wo), _rel(r.cpu(), zo - yc)
+        _say(f"  {'fold' if fold else 'plain'}: rel err w {e_w:.2e}, r {e_r:.2e}")
+        assert e_w <= 1e-10 and e_r <= 1e-10
+    del Xp
+    torch.cuda.empty_cache()
 
 
 def test_dual_fp64_per_step_path_full_steps(gpu_lib):
