@@ -220,6 +220,51 @@ def test_batch_autotuned_reaches_1e6(gpu_lib):
     _say("  (b, s) chosen:", sorted({(i["b"], i["s"]) for i in infos}))
 
 
+def test_batch_bench_size_sampled_problems(gpu_lib):
+    """The batched workload at its full size: the benchmark's 256 problems (d
+    log-uniform in [32, 1024], n in [4096, 131072], lambda in [1e-6, 1e-1];
+    its generator, seeds and storage with rows leading_dim apart), planned with
+    the autotuned (b, s) and the benchmark's monitoring, 8 rounds.  Eight
+    problems (the smallest and largest d n, the largest s b, five drawn at
+    random) against the oracle's Alg. 2 run of the same outer steps with the
+    same (b, s) and seed: w to 1e-10, r to X^T w - y."""
+    P, rounds = 256, 8
+    ds, ns, lams = synth.ridge_batch(P, 1004)
+    _say("batch bench size, P =", P, "sum d n =", sum(d * n for d, n in zip(ds, ns)))
+    probs = []
+    for p in range(P):
+        X, y, _ = synth.gaussian_ridge(ds[p], ns[p], 1004 + 1 + p, device=DEV)
+        Xp = gpu_lib.empty_dense(ds[p], ns[p], DEV)
+        Xp.copy_(X)
+        probs.append(dict(X=Xp, y=y, lam=lams[p], seed=2_000_000 + p))
+        del X
+    torch.cuda.empty_cache()
+    with gpu_lib.Batch(probs, monitor_every=4, cheap_monitors=7) as B:
+        act = B.run(rounds)
+        infos = [B.info(p) for p in range(P)]
+    torch.cuda.synchronize()
+    assert act == P
+    dn = [d * n for d, n in zip(ds, ns)]
+    pick = {int(np.argmin(dn)), int(np.argmax(dn)),
+            int(np.argmax([i["b"] * i["s"] for i in infos]))}
+    pick |= {int(p) for p in np.random.default_rng(5).choice(P, 5, replace=False)}
+    for p in sorted(pick):
+        inf, q = infos[p], probs[p]
+        b, s = inf["b"], inf["s"]
+        assert inf["steps"] == rounds and inf["h"] == rounds * s
+        Xc = np.ascontiguousarray(q["X"].cpu().numpy())
+        yc = q["y"].cpu().numpy()
+        wo, _ = bcd.primal_bcd(Xc, yc, q["lam"], b, s, rounds * s, q["seed"])
+        w = q["w"].cpu().numpy()
+        err = np.linalg.norm(w - wo) / max(np.linalg.norm(wo), 1e-300)
+        _say(f"  problem {p}: d={ds[p]} n={ns[p]} b={b} s={s}: rel err {err:.2e}")
+        assert err <= 1e-10
+        r = q["r"].cpu().numpy()
+        assert np.linalg.norm(r - (Xc.T @ w - yc)) <= 1e-10 * np.linalg.norm(yc)
+    del probs
+    torch.cuda.empty_cache()
+
+
 def test_batch_one_shot_and_nonfinite(gpu_lib):
     _say("batch one-shot; non-finite data is reported")
     probs = _problems(CASES[:3])

@@ -243,3 +243,33 @@ def test_csr_split_gram_without_and_with_heavy_columns(gpu_lib, density, s):
     ao, wo = bcd.dual_bcd(S.T.tocsc(), y, lam, b, s, H, seed)
     assert _rel(a.cpu(), ao) <= 1e-10
     assert _rel(w.cpu(), wo) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def zipf_bench():
+    rowptr, colidx, vals, y, _ = synth.zipf_csr_ridge(20000, 1 << 20, 315, 1002)
+    return scipy.sparse.csr_matrix((vals, colidx, rowptr), shape=(20000, 1 << 20)), y
+
+
+@pytest.mark.parametrize("s,H", [(1, 64), (8, 8 * 20 + 3), (32, 17 * 32 + 5)])
+def test_csr_dual_bench_size(gpu_lib, zipf_bench, s, H):
+    """The sparse dual workload at its full size and in the benchmark's launch
+    configuration: A = X^T in CSR, 20000 rows x 2^20 columns, 315 Zipf(1.1)
+    features per row (the benchmark's generator and seed), lambda = 1e-5,
+    b = 16, s = 1, 8, 32.  At s = 32 the Grams come from the split launches of
+    16 outer steps each: 17 full steps cross a launch boundary, then a ragged
+    step.  alpha and w against the oracle's run of the same steps."""
+    _say("csr dual bench size", s, H)
+    S, y = zipf_bench
+    XT = gpu_lib.CSR.from_scipy(S, DEV)
+    lam, b, seed = 1e-5, 16, 2002
+    t = gpu_lib.new_timing()
+    a, w = gpu_lib.dual_bcd(XT, torch.tensor(y, device=DEV), lam, b, s, H, seed, timing=t)
+    n = {k: v["launches"] for k, v in gpu_lib.timing_dict(t).items()}
+    _say("  launches", n)
+    steps = -(-H // s)
+    assert n["solve"] >= steps and n["gram"] < steps   # Grams computed ahead
+    ao, wo = bcd.dual_bcd(S.T.tocsc(), y, lam, b, s, H, seed)
+    e_a, e_w = _rel(a.cpu(), ao), _rel(w.cpu(), wo)
+    _say(f"  rel err alpha {e_a:.2e}, w {e_w:.2e}")
+    assert e_a <= 1e-10 and e_w <= 1e-10

@@ -98,6 +98,45 @@ def test_lowp_gram_against_fp64_gram_of_dequantised(gpu_lib, dtype, m, cols):
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_lowp_gram_bench_size(gpu_lib, dtype):
+    """The time-to-1e-6 workload at its full size: d = 4096, n = 2^20,
+    column-scaled, generated as the benchmark generates it and stored by the
+    binding's quantiser; one Gram of 256 distinct gathered rows (the kernel and
+    launch of the benchmark's outer step, sb = 256) with a random u.  The
+    expected values come from the oracle alone: its encoder applied to the
+    gathered FP64 rows (row-local, so equal to the rows of the whole stored
+    matrix) and its Gram of the dequantised rows; every entry within the
+    bound of the small-size test."""
+    d, n, m = 4096, 1 << 20, 256
+    _say("lowp gram bench size", dtype, d, n, m)
+    X, _, _, _ = synth.colscaled_ridge(d, n, 1003, device=DEV)
+    code = gpu_lib.BF16 if dtype == "bf16" else gpu_lib.FP8_E4M3
+    Q = gpu_lib.quantize(X, code)
+    rng = np.random.default_rng(4096)
+    idx = rng.permutation(d)[:m].astype(np.int32)
+    rows = X[torch.tensor(idx, device=DEV, dtype=torch.int64)].cpu().numpy()
+    del X
+    torch.cuda.empty_cache()
+    u = rng.standard_normal(n)
+    scale, shift = 1.0 / n, 1e-4
+    G, Yu = gpu_lib.gram(Q, torch.tensor(idx, device=DEV), scale, shift,
+                         torch.tensor(u, device=DEV))
+    G, Yu = G.cpu().numpy(), Yu.cpu().numpy()
+    del Q
+    torch.cuda.empty_cache()
+    _, _, Yh = quant.quantize_rows(rows, dtype)
+    del rows
+    Go, Yo = bcd.gram(Yh, np.arange(m), scale, shift, u)
+    Ya = np.abs(Yh)
+    rel_bound = n * 2.0 ** -24 + (0.0 if dtype == "bf16" else 2.0 ** -12)
+    mag = scale * (Ya @ Ya.T)
+    err = np.abs(G - Go)
+    _say(f"  max |dG| / (scale |Y||Y|^T) = {(err / np.maximum(mag, 1e-300)).max():.2e}")
+    assert np.all(err <= rel_bound * mag + 1e-300)
+    assert np.all(np.abs(Yu - Yo) <= 1e-12 * (Ya @ np.abs(u)) + 1e-300)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 @pytest.mark.parametrize("d,n", [(37, 70001), (3, 4097), (130, 2 * 4096 + 19)])
 def test_lowp_companion_pass_entrywise(gpu_lib, dtype, d, n):
     # r = X^T w - y over all rows of the stored codes (the exact recomputation
