@@ -80,21 +80,34 @@ def test_primal_fp64_per_step_path_full_steps(gpu_lib, fold):
     assert e_w <= 1e-10 and e_r <= 1e-10
 
 
-def test_primal_headline_size_full_steps(gpu_lib):
-    """The benchmark's own workload and launch configuration: d = 2048,
-    n = 2^18, b = 8, s = 32 (sb = 256), lambda = 1e-4, X generated as the
-    benchmark generates it (spectrum 1 .. 1e3) and stored with its rows
-    leading_dim apart; three full outer steps through the one-Gram-per-step
-    path, without and with the update folded into the next step's Gram; every
-    entry of w and r against the oracle's run of the same steps."""
-    d, n, b, s, lam, seed = 2048, 1 << 18, 8, 32, 1e-4, 7
-    H = 3 * s
-    _say("primal headline size", d, n, b, s, H)
+@pytest.fixture(scope="module")
+def headline_matrix(gpu_lib):
+    """The benchmark's headline matrix: d = 2048, n = 2^18, spectrum 1 .. 1e3,
+    generated as the benchmark generates it, stored with its rows leading_dim
+    apart on the GPU; with its host copy for the oracle."""
+    d, n = 2048, 1 << 18
     X, y, _ = synth.spectral_ridge(d, n, 1001, device=DEV)
     Xc, yc = X.cpu().numpy(), y.cpu().numpy()
     Xp = gpu_lib.empty_dense(d, n, DEV)
     Xp.copy_(X)
     del X
+    torch.cuda.empty_cache()
+    yield Xp, y, Xc, yc
+    del Xp
+    torch.cuda.empty_cache()
+
+
+def test_primal_headline_size_full_steps(gpu_lib, headline_matrix):
+    """The benchmark's own workload and launch configuration: d = 2048,
+    n = 2^18, b = 8, s = 32 (sb = 256), lambda = 1e-4, X stored with its rows
+    leading_dim apart; three full outer steps through the one-Gram-per-step
+    path, without and with the update folded into the next step's Gram; every
+    entry of w and r against the oracle's run of the same steps."""
+    Xp, y, Xc, yc = headline_matrix
+    d, n = Xc.shape
+    b, s, lam, seed = 8, 32, 1e-4, 7
+    H = 3 * s
+    _say("primal headline size", d, n, b, s, H)
     assert Xp.stride(0) == gpu_lib.leading_dim(n, gpu_lib.F64) != n
     wo, zo = bcd.primal_bcd(Xc, yc, lam, b, s, H, seed)
     for fold in (False, True):
@@ -105,7 +118,39 @@ def test_primal_headline_size_full_steps(gpu_lib):
         e_w, e_r = _rel(w.cpu(), wo), _rel(r.cpu(), zo - yc)
         _say(f"  {'fold' if fold else 'plain'}: rel err w {e_w:.2e}, r {e_r:.2e}")
         assert e_w <= 1e-10 and e_r <= 1e-10
-    del Xp
+
+
+@pytest.mark.parametrize("s", [1, 4, 16])
+def test_primal_headline_matrix_s_sweep(gpu_lib, headline_matrix, s):
+    """The s sweep of the benchmark on the headline matrix (b = 8, s = 1, 4,
+    16: one Gram per outer step of 8 to 128 gathered rows of 2 MiB), four
+    outer steps against the oracle."""
+    Xp, y, Xc, yc = headline_matrix
+    b, lam, seed = 8, 1e-4, 2001
+    H = 4 * s
+    _say("primal headline matrix, s =", s)
+    w, r = gpu_lib.primal_bcd(Xp, y, lam, b, s, H, seed)
+    wo, zo = bcd.primal_bcd(Xc, yc, lam, b, s, H, seed)
+    e_w, e_r = _rel(w.cpu(), wo), _rel(r.cpu(), zo - yc)
+    _say(f"  rel err w {e_w:.2e}, r {e_r:.2e}")
+    assert e_w <= 1e-10 and e_r <= 1e-10
+
+
+def test_dual_headline_matrix(gpu_lib, headline_matrix):
+    """The benchmark's dense dual: A = X^T of the headline matrix (2^18 data
+    points of 2048 features), b = 8, s = 1, 4, 16, 32 (the Grams of future
+    steps computed ahead), four outer steps each against the oracle."""
+    Xp, y, Xc, yc = headline_matrix
+    XT = Xp.t().contiguous()
+    b, lam, seed = 8, 1e-4, 2001
+    for s in (1, 4, 16, 32):
+        H = 4 * s
+        a, w = gpu_lib.dual_bcd(XT, y, lam, b, s, H, seed)
+        ao, wo = bcd.dual_bcd(Xc, yc, lam, b, s, H, seed)
+        e_a, e_w = _rel(a.cpu(), ao), _rel(w.cpu(), wo)
+        _say(f"  dual s={s}: rel err alpha {e_a:.2e}, w {e_w:.2e}")
+        assert e_a <= 1e-10 and e_w <= 1e-10
+    del XT
     torch.cuda.empty_cache()
 
 
