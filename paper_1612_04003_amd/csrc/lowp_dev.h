@@ -19,12 +19,13 @@ constexpr int kLpThreads = 512;   // 8 waves, two block rows each
 
 // FMT: CABCD_BF16 (2-byte elements, one MFMA per 16-byte fragment) or
 // CABCD_FP8_E4M3 (1-byte elements, one K = 128 MFMA per two 16-byte fragments).
-template <int NB, int FMT>
+// TB: tile bytes per row times NB (a tile of SBP rows holds 16 TB bytes).
+template <int NB, int FMT, int TB = 2048>
 struct LpCfg {
   static constexpr int ES = FMT == CABCD_BF16 ? 2 : 1;      // element bytes
   static constexpr int SBP = 16 * NB;
   static constexpr int NBLK = NB * (NB + 1) / 2;
-  static constexpr int RB = 2048 / NB;                      // tile row bytes: tile = 32 KiB
+  static constexpr int RB = TB / NB;                        // tile row bytes: tile = 16 TB
   static constexpr int RSB = RB + 16;                       // LDS row stride in bytes
   static constexpr int KT = RB / ES;                        // tile width in elements
   static constexpr int EPC = 16 / ES;                       // elements per 16-byte chunk
@@ -67,10 +68,10 @@ __device__ __forceinline__ f4 lp_mma_k128(const lp_i8v& a, const lp_i8v& b, f4 c
   return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
 }
 
-template <int NB, int FMT, int W>
+template <int NB, int FMT, int W, int TB>
 __device__ __forceinline__ void lp_tile(const uint8_t* __restrict__ tile, int lane, int kg,
-                                        f4 (&acc)[LpCfg<NB, FMT>::NACC]) {
-  using C = LpCfg<NB, FMT>;
+                                        f4 (&acc)[LpCfg<NB, FMT, TB>::NACC]) {
+  using C = LpCfg<NB, FMT, TB>;
   constexpr int R1 = NB >= 2 ? W : 0;
   constexpr int R2 = NB >= 2 ? NB - 1 - W : 0;
   const uint8_t* base = tile + (lane & 15) * C::RSB + 16 * (lane >> 4);
@@ -116,14 +117,14 @@ __device__ __forceinline__ void lp_tile(const uint8_t* __restrict__ tile, int la
   }
 }
 
-template <int NB, int FMT, int W = 0>
+template <int NB, int FMT, int TB, int W = 0>
 __device__ __forceinline__ void lp_dispatch(int bw, const uint8_t* tile, int lane, int kg,
-                                            f4 (&acc)[LpCfg<NB, FMT>::NACC]) {
-  if constexpr (W < LpCfg<NB, FMT>::BW) {
+                                            f4 (&acc)[LpCfg<NB, FMT, TB>::NACC]) {
+  if constexpr (W < LpCfg<NB, FMT, TB>::BW) {
     if (bw == W)
-      lp_tile<NB, FMT, W>(tile, lane, kg, acc);
+      lp_tile<NB, FMT, W, TB>(tile, lane, kg, acc);
     else
-      lp_dispatch<NB, FMT, W + 1>(bw, tile, lane, kg, acc);
+      lp_dispatch<NB, FMT, TB, W + 1>(bw, tile, lane, kg, acc);
   }
 }
 
@@ -172,13 +173,13 @@ __device__ __forceinline__ uint4 lp_load(PTR row, int64_t k, int64_t k_end, bool
 // the rows idx[0..m) of the stored codes A (ld in elements), FP32 MFMA
 // accumulation, partial blocks (FP32 MFMA output order) and partial Y u (FP64,
 // decoded codes, row scales not applied) to part.  lds holds LpCfg::LDS bytes.
-template <int NB, int FMT>
+template <int NB, int FMT, int TB = 2048>
 __device__ __forceinline__ void gram_lp_slab(const uint8_t* __restrict__ A, int64_t ld,
                                              int64_t k_begin, int64_t k_end, const int32_t* idx,
                                              int m, const double* __restrict__ u,
                                              double* __restrict__ part, int aligned,
                                              uint8_t* lds) {
-  using C = LpCfg<NB, FMT>;
+  using C = LpCfg<NB, FMT, TB>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -235,7 +236,7 @@ __device__ __forceinline__ void gram_lp_slab(const uint8_t* __restrict__ A, int6
   for (int t = 0; t < ntiles; ++t) {
     const bool more = t + 1 < ntiles;
     if (more) load_tile(t + 1);
-    lp_dispatch<NB, FMT>(bw, lds + (t & 1) * C::TILE, lane, kg, acc);
+    lp_dispatch<NB, FMT, TB>(bw, lds + (t & 1) * C::TILE, lane, kg, acc);
     if (more) store_tile((t + 1) & 1);
     __syncthreads();
   }
