@@ -158,8 +158,10 @@ typedef struct cabcd_opts {
 #define CABCD_PHASE_SOLVE 3     /* s block solves + recurrence + x[idx] += d;      */
                                 /* also the launches that invert the diagonal     */
                                 /* blocks of Grams computed ahead                 */
-#define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta (a launch only  */
-                                /* when it is not left to the next step's Gram)   */
+#define CABCD_PHASE_UPDATE 4    /* companion update with Y^T delta (counted only   */
+                                /* when launched: not when it is left to the next */
+                                /* step's Gram or made moot by the exact          */
+                                /* recomputation right after the step)            */
 #define CABCD_PHASE_RECOMPUTE 5 /* exact companion recomputation                   */
 #define CABCD_PHASE_MONITOR 6   /* objective evaluation                            */
 #define CABCD_PHASE_CHECK 7     /* full residual of the stopping test              */
