@@ -476,10 +476,12 @@ def time_to_tol(cabcd, torch, synth, tol=1e-6, d=4096, n=1 << 20, b=16, s=16, la
                 break
         return time.perf_counter() - t0, steps, err, w
 
-    def gram_rate(A, elem, steps=8):
+    def gram_rate(A, elem, steps=32):
         """The Gram kernel alone over `steps` outer steps (HIP events around the
         Gram launches only): ms per launch, algorithmic bytes (the gathered
-        rows) per second against the HBM peak, and flops per second."""
+        rows) per second against the HBM peak, and flops per second.  Each
+        event pair also holds the launch's dispatch (a few microseconds, a
+        visible share of a 60 us launch)."""
         w = torch.zeros(d, dtype=torch.float64, device="cuda")
         r = torch.empty(n, dtype=torch.float64, device="cuda")
         tm = cabcd.new_timing()
