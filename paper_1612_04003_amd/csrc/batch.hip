@@ -43,7 +43,7 @@ constexpr int kBMaxSlabs = 64;
 // Low-precision slabs stream tiles of 16 kBLpTile bytes (64 KiB; the
 // one-problem kernels use 32 KiB): a round's many problems fill the GPU
 // without narrow slabs, and the doubled bytes in flight per workgroup cut the
-// BF16 record to 1e-6 from 0.141 to 0.133 s.
+// BF16 record to 1e-6 from 0.141 to 0.131 s.
 constexpr int kBLpTile = 4096;
 
 struct BProb {                     // constant per problem (device copy)
